@@ -1,0 +1,169 @@
+"""Throughput of the bit-parallel Gillespie path on one MI355X.
+
+One step = initial state + advance of every replica to t_end (budget draws
+and the event kernel) + per-replica counts + enantiomeric-excess histogram,
+on the well-mixed Frank workload N_tot = 1024, 2^20 replicas, t_end = 100,
+all-A start, seed 0.  The metric counts every uniformised event (null
+events included, the paper's "iterations") over all replicas.
+
+Prints one JSON line.  Extra fields: the plain one-replica-per-thread engine
+on the same workload, the dominant kernel's roofline, and the CPU oracle on
+a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue slots per word-event (32 replica-events) the bit-sliced method
+# needs for a network with b count planes, B threshold planes and product
+# shift f; see DESIGN.md ("Algorithmic work").
+PHILOX_SLOTS = 100          # 20 32x32->64 multiplies at 4 slots + 20 xor3
+
+
+def word_event_slots(b, B, f, cu_bits):
+    rng = ((B + 3) // 4) * PHILOX_SLOTS
+    select = B + 2 * (B - 1) + 2 * 2 * (B - f) + (B - f) + 8
+    species = 3 * 2 * b
+    products = 2 * (5 * (b + 2) + 2 * (2 * b - 2)) + (4 * (b + 2) + 2 * (2 * b - 2))
+    unimolecular = 3 * B if cu_bits else 0
+    return rng + select + species + products + unimolecular + 3
+
+
+VALU_PEAK = 256 * 128 * 2.4e9   # 32-bit lane-slots/s: 256 CUs x 128 lanes/clk x 2.4 GHz
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-replicas", type=int, default=65536)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path shards by replica across GPUs "
+              "(see DESIGN.md) but no multi-GPU run is part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2412_16613_amd as bwg
+    from workloads import config
+
+    c = config("c1")
+    net, M, t_end = c["net"], c["replicas"], c["t_end"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    network = bwg.Network(net)
+    q = network.quantized()
+
+    def make(engine):
+        ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], engine=engine,
+                           device=dev)
+        counts = torch.empty((M, 3), dtype=torch.int32, device=dev)
+        hist = torch.empty(256, dtype=torch.int64, device=dev)
+        return ens, counts, hist
+
+    def run(engine, steps, warmup):
+        ens, counts, hist = make(engine)
+        stream = torch.cuda.current_stream(dev)
+        k0, k1 = [], []
+        for _ in range(warmup):
+            ens.init(c["init"]).advance(t_end)
+            ens.read_counts(counts)
+            ens.histogram(256, hist)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t0.record(stream)
+        for _ in range(steps):
+            ens.init(c["init"])
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ens.advance(t_end)
+            b.record(stream)
+            k0.append(a)
+            k1.append(b)
+            ens.read_counts(counts)
+            ens.histogram(256, hist)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms = t0.elapsed_time(t1)
+        adv_ms = [x.elapsed_time(y) for x, y in zip(k0, k1)]
+        st = ens.stats()
+        assert int(hist.sum().item()) == M
+        return dict(ms=ms, wall=wall, adv_ms=adv_ms, events=st["events_total"],
+                    real=st["real_total"])
+
+    r = run("bitwise", args.steps, args.warmup)
+    ms_step = r["ms"] / args.steps
+    events_per_step = r["events"]          # same seed every step: same budgets
+    value = events_per_step * args.steps / (r["ms"] / 1e3)
+    adv_avg_ms = sum(r["adv_ms"]) / len(r["adv_ms"])
+    word_events = events_per_step / 32.0
+    slots = word_event_slots(q["b"], q["B"], q["f"], bin(q["c"][0]).count("1") - 1)
+    achieved = slots * word_events / (adv_avg_ms / 1e3)
+    out = {
+        "metric": "replica-events/sec (bit-parallel vs plain SSA, 1 GPU)",
+        "value": value,
+        "unit": "replica-events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 bit-planes",
+        "data": "synthetic",
+        "config": {"workload": "well-mixed Frank model, N_tot=1024, 2^20 replicas, "
+                               "t_end=100, all-A start, seed 0",
+                   "n_tot": 1024, "replicas": M, "t_end": t_end, "threshold_planes": q["B"],
+                   "count_planes": q["b"]},
+        "real_events_per_s": r["real"] * args.steps / (r["ms"] / 1e3),
+        "replica_time_per_s": M * t_end * args.steps / (r["ms"] / 1e3),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
+                     "traffic": None, "kernel": "wm_event_kernel",
+                     "kernel_ms": adv_avg_ms, "slots_per_word_event": slots},
+    }
+    if not args.no_plain:
+        p = run("plain", max(1, args.steps // 2), 1)
+        pv = p["events"] * max(1, args.steps // 2) / (p["ms"] / 1e3)
+        out["plain_ssa"] = {"value": pv, "unit": "replica-events/s",
+                            "ms_per_step": p["ms"] / max(1, args.steps // 2),
+                            "bitwise_over_plain": value / pv}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(net, c, args.cpu_replicas)
+    print(json.dumps(out))
+
+
+def cpu_baseline(net, c, n_rep):
+    """The CPU oracle on the first n_rep replicas of the same workload."""
+    from oracle import ssa
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    ssa.lib()
+    E = ssa.OracleEnsemble(net, c["replicas"], seed=c["seed"], net_id=c["net_id"], first=0,
+                           count=n_rep, threads=threads)
+    E.init(c["init"])
+    t = time.perf_counter()
+    E.advance(c["t_end"])
+    dt = time.perf_counter() - t
+    ev = int(E.E.sum())
+    return {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d replicas, full t_end (%d events, %.1f s)"
+                      % (n_rep, c["replicas"], ev, dt)}
+
+
+if __name__ == "__main__":
+    main()

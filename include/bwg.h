@@ -1,0 +1,198 @@
+/*
+ * bwg.h -- C ABI of the bit-parallel Gillespie library for MI355X (gfx950).
+ *
+ * The library simulates many independent replicas of a chemical reaction
+ * network with Gillespie's exact stochastic simulation algorithm, holding the
+ * species counts of 32 replicas bit-sliced in each 32-bit word (one replica
+ * per bit lane, one word per bit of the count) and selecting and applying
+ * reactions with word-wide logic and ripple-carry arithmetic.  This is the
+ * bitwise Gillespie method of Castellana and Lacoste, "Parallelization of
+ * Gillespie algorithm based on binary words" (Sec. 4 and App. B), with one
+ * random threshold per replica instead of one shared by all copies.
+ *
+ * Conventions
+ *   - Every function returns an int status: BWG_OK (0) or a negative code
+ *     below; bwg_last_error() returns a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Device memory is owned by the caller: an ensemble lives entirely in one
+ *     caller-allocated device buffer of bwg_ensemble_state_bytes() bytes
+ *     (256-byte aligned).  Output buffers are caller-owned device pointers.
+ *   - Streams are passed as `void*` holding a hipStream_t (NULL = the null
+ *     stream).  Calls marked "async" only enqueue work on that stream;
+ *     results are valid once the stream has synchronised.
+ *   - Handles are not thread-safe; distinct handles may be used from
+ *     distinct threads.  A network must outlive its ensembles.
+ *   - Species order of the Frank model is (L, D, A): the two enantiomers and
+ *     the achiral activator of Sec. 2 of the paper.
+ */
+#ifndef BWG_H
+#define BWG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    BWG_OK = 0,
+    BWG_EINVAL = -1,       /* invalid argument or network                     */
+    BWG_ERANGE = -2,       /* value outside what the planes/tables can hold  */
+    BWG_ENOMEM = -3,       /* caller buffer too small                         */
+    BWG_EDEVICE = -4,      /* HIP runtime error (message has the HIP text)    */
+    BWG_EUNSUPPORTED = -5  /* valid network the GPU kernels do not implement  */
+};
+
+#define BWG_MAX_SPECIES 8
+#define BWG_MAX_REACTIONS 16
+
+/* flags of bwg_net_desc */
+#define BWG_EXACT_INTEGER 1u   /* rates are the integer weights (paper mode) */
+
+/* engines of bwg_opts */
+#define BWG_ENGINE_BITWISE 0   /* bit-sliced words, 32 replicas per lane      */
+#define BWG_ENGINE_PLAIN 1     /* comparator: one replica per thread, int32   */
+
+/* initial-state modes of bwg_ensemble_init */
+#define BWG_INIT_FIXED 0        /* every replica starts from counts[0..S-1]   */
+#define BWG_INIT_MULTINOMIAL 1  /* each molecule L, D, A w.p. 1/4, 1/4, 1/2   */
+
+typedef struct bwg_net bwg_net;
+typedef struct bwg_ens bwg_ens;
+
+/*
+ * A reaction network.  Reaction j consumes reactants[j*S + x] molecules of
+ * species x and produces products[j*S + x]; total order 1 or 2; every
+ * reaction must conserve the molecule count (the paper's networks conserve
+ * N_tot, Sec. 2).  rates[j] is the mass-action constant: the propensity is
+ * rates[j] * h_j(N) with h_j = N_X, N_X N_Y or N_X (N_X - 1)/2 (the forms of
+ * Eq. (7) of the paper).  All pointers are read during the call only.
+ */
+typedef struct {
+    int32_t n_species;          /* S, <= BWG_MAX_SPECIES                      */
+    int32_t n_reactions;        /* R, <= BWG_MAX_REACTIONS                    */
+    const int32_t *reactants;   /* [R][S]                                     */
+    const int32_t *products;    /* [R][S]                                     */
+    const double *rates;        /* [R], finite, >= 0                          */
+    int64_t n_tot;              /* molecules per replica                      */
+    int32_t lx, ly;             /* 0, 0: well-mixed                           */
+    const double *hop_rates;    /* [S] per molecule per direction, or NULL    */
+    int32_t site_planes;        /* bits per species count on a lattice site   */
+    int32_t precision_bits;     /* rate quantisation, 0 = default (7)         */
+    uint32_t flags;             /* BWG_EXACT_INTEGER                          */
+    uint32_t reserved;
+} bwg_net_desc;
+
+/*
+ * The integer form of a network (what the kernels run and the oracle checks):
+ * reaction j has weight w_j(N) = c[j] * h_j(N); the weights are in units of
+ * 1/s per unit time; W = 2^B bounds sum_j w_j(N) over every state with
+ * N_tot molecules; the uniformised chain runs lambda = 2^B / s events per
+ * replica per unit time, each event picking reaction j with probability
+ * w_j / 2^B and nothing otherwise (the role of the ghost reactions, Eq. (9)).
+ * b planes hold one species count (2^b > N_tot).
+ */
+typedef struct {
+    int32_t n_species, n_reactions;
+    int64_t c[BWG_MAX_REACTIONS];
+    int32_t f;            /* scale exponent: s = 2^f / k_ref                  */
+    int32_t B;            /* threshold planes                                 */
+    int32_t b;            /* planes per species count                         */
+    int32_t gpu_ok;       /* 1 if the GPU kernels implement this network      */
+    double s;
+    double lambda;
+    int64_t max_total;    /* max_N sum_j w_j(N)                               */
+} bwg_qnet;
+
+typedef struct {
+    int32_t engine;              /* BWG_ENGINE_*                              */
+    int32_t block;               /* threads per block, 0 = default            */
+    uint64_t table_capacity;     /* Poisson-table entries, 0 = default 65536  */
+    uint64_t events_per_launch;  /* 0 = whole advance in one launch           */
+    uint64_t reserved[4];
+} bwg_opts;
+
+typedef struct {
+    uint64_t n_replicas;
+    uint64_t advance_index;      /* advances done since init                  */
+    double t_now;
+    uint64_t events_total;       /* sum over replicas of events run           */
+    uint64_t real_total;         /* of which changed the state                */
+} bwg_stats;
+
+/* ---- networks (host only, synchronous) ------------------------------- */
+
+/* Validate and quantise a network (integer weights c_j, scale, bound 2^B).
+ * EINVAL: order not in {1,2}, not count-conserving, negative or non-finite
+ * rate, n_tot < 1, sizes out of range; ERANGE: weights or bound beyond 32
+ * threshold planes or n_tot beyond the count planes.  The returned handle is
+ * owned by the caller (bwg_net_destroy). */
+int bwg_net_create(const bwg_net_desc *desc, bwg_net **out);
+int bwg_net_quantized(const bwg_net *net, bwg_qnet *out);
+void bwg_net_destroy(bwg_net *net);
+
+/* Poisson inverse-CDF table of the event budget for mean mu (host):
+ * table[j] = floor(2^64 P(K <= k_lo + j)), j < len, ending at the first
+ * entry equal to 2^64-1.  ERANGE if cap entries do not suffice (len then
+ * holds the size needed). */
+int bwg_poisson_table(double mu, int64_t *k_lo, uint64_t *table, uint64_t cap,
+                      uint64_t *len);
+
+/* ---- ensembles ---------------------------------------------------------- */
+
+/* Device bytes an ensemble of n_replicas needs (opts may be NULL). */
+int bwg_ensemble_state_bytes(const bwg_net *net, uint64_t n_replicas,
+                             const bwg_opts *opts, uint64_t *bytes);
+
+/* Bind an ensemble to a caller buffer.  seed and net_id key every random
+ * draw (Philox4x32-10 counters); replicas of equal (seed, net_id, index)
+ * see identical draws in any ensemble, batch or word width.  No device work
+ * is enqueued.  ENOMEM if buf_bytes is below bwg_ensemble_state_bytes. */
+int bwg_ensemble_create(const bwg_net *net, uint64_t n_replicas, uint64_t seed,
+                        uint32_t net_id, void *dev_buf, uint64_t buf_bytes,
+                        const bwg_opts *opts, bwg_ens **out);
+
+/* Set every replica's initial state and reset time, event counters and the
+ * advance index.  mode BWG_INIT_FIXED takes counts[S] (host pointer, summing
+ * to n_tot); BWG_INIT_MULTINOMIAL draws the paper's racemic multinomial start
+ * (Frank species only).  Async. */
+int bwg_ensemble_init(bwg_ens *ens, int32_t mode, const int32_t *counts,
+                      void *stream);
+
+/* Advance every replica to time t_end >= t_now: each replica draws its event
+ * count K ~ Poisson(lambda (t_end - t_now)) by inversion of one 64-bit
+ * uniform, then runs K events of the uniformised chain (Sec. 3 update rule,
+ * in the bitwise form of Sec. 4).  EINVAL if t_end < t_now; ERANGE if the
+ * Poisson table exceeds the table capacity.  Async. */
+int bwg_ensemble_advance(bwg_ens *ens, double t_end, void *stream);
+
+/* Run exactly n_events more events in every replica, without time (the
+ * paper's fixed number of iterations, Sec. 5).  Async. */
+int bwg_ensemble_step(bwg_ens *ens, uint64_t n_events, void *stream);
+
+/* Counts of every replica: dev_dst[i*S + x], int32, species order of the
+ * network.  Async. */
+int bwg_ensemble_read_counts(bwg_ens *ens, int32_t *dev_dst, void *stream);
+
+/* Histogram of the enantiomeric excess (N_L - N_D)/N_tot over replicas:
+ * bin = min(n_bins-1, floor((N_L - N_D + N_tot) n_bins / (2 N_tot))),
+ * dev_dst[n_bins] uint64 (overwritten).  Frank species only.  Async. */
+int bwg_ensemble_histogram(bwg_ens *ens, int32_t n_bins, uint64_t *dev_dst,
+                           void *stream);
+
+/* Per-replica events run and real (state-changing) events so far:
+ * dev_events[i], dev_real[i] uint64 (either may be NULL).  Async. */
+int bwg_ensemble_read_events(bwg_ens *ens, uint64_t *dev_events,
+                             uint64_t *dev_real, void *stream);
+
+/* Synchronises the stream and reports totals. */
+int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);
+
+void bwg_ensemble_destroy(bwg_ens *ens);
+
+const char *bwg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BWG_H */

@@ -1,0 +1,191 @@
+"""Bit-parallel Gillespie exact stochastic simulation on MI355X (gfx950).
+
+Python binding of libbwg.so (include/bwg.h): argument marshalling only.
+Every step of the simulation runs in the library's HIP kernels; PyTorch
+provides the device buffers and the stream.  There is no CPU fallback: the
+binding raises if the library has not been built.
+
+    from workloads import frank_network
+    import paper_2412_16613_amd as bwg
+    net = bwg.Network(frank_network(1024))
+    ens = bwg.Ensemble(net, 1 << 20, seed=0)
+    ens.init_fixed((0, 0, 1024))
+    ens.advance(100.0)
+    hist = ens.histogram(256)          # torch.int64 [256] on the GPU
+"""
+
+import ctypes
+
+from . import _abi
+from ._abi import BwgError  # noqa: F401
+
+ENGINES = {"bitwise": _abi.BWG_ENGINE_BITWISE, "plain": _abi.BWG_ENGINE_PLAIN}
+
+
+def _lib():
+    return _abi.load()
+
+
+def _i32arr(vals):
+    return (ctypes.c_int32 * len(vals))(*vals)
+
+
+def poisson_table(mu, cap=1 << 20):
+    """The library's budget table for mean mu: (k_lo, list of uint64)."""
+    L = _lib()
+    k_lo = ctypes.c_int64()
+    n = ctypes.c_uint64()
+    buf = (ctypes.c_uint64 * cap)()
+    _abi.check(L.bwg_poisson_table(float(mu), ctypes.byref(k_lo), buf, cap, ctypes.byref(n)))
+    return k_lo.value, list(buf[: n.value])
+
+
+class Network:
+    """A reaction network (see workloads.frank for the dict layout)."""
+
+    def __init__(self, net, precision_bits=0):
+        L = _lib()
+        S = len(net["species"])
+        R = len(net["rates"])
+        self.net = net
+        self._reac = _i32arr([v for row in net["reactants"] for v in row])
+        self._prod = _i32arr([v for row in net["products"] for v in row])
+        self._rates = (ctypes.c_double * R)(*net["rates"])
+        self._hops = (ctypes.c_double * S)(*net.get("hop_rates", [0.0] * S))
+        d = _abi.NetDesc()
+        d.n_species, d.n_reactions = S, R
+        d.reactants, d.products, d.rates = self._reac, self._prod, self._rates
+        d.n_tot = int(net["n_tot"])
+        d.lx, d.ly = int(net.get("lx", 0)), int(net.get("ly", 0))
+        d.hop_rates = self._hops
+        d.site_planes = int(net.get("site_planes", 0))
+        d.precision_bits = int(precision_bits)
+        d.flags = _abi.BWG_EXACT_INTEGER if net.get("exact_integer") else 0
+        h = ctypes.c_void_p()
+        _abi.check(L.bwg_net_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    def quantized(self):
+        q = _abi.QNet()
+        _abi.check(_lib().bwg_net_quantized(self.handle, ctypes.byref(q)))
+        R = q.n_reactions
+        return dict(c=list(q.c[:R]), f=q.f, B=q.B, W=1 << q.B, b=q.b, s=q.s,
+                    Lambda=q.lambda_, max_total=q.max_total, gpu_ok=bool(q.gpu_ok))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _lib().bwg_net_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def _stream_ptr(stream):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+class Ensemble:
+    """Replicas of one network in a caller-owned device buffer."""
+
+    def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
+                 device="cuda", events_per_launch=0, table_capacity=0, block=0):
+        import torch
+        self.torch = torch
+        L = _lib()
+        self.network = network
+        self.M = int(n_replicas)
+        self.device = torch.device(device)
+        o = _abi.Opts()
+        o.engine = ENGINES[engine]
+        o.block = block
+        o.table_capacity = table_capacity
+        o.events_per_launch = events_per_launch
+        self._opts = o
+        nbytes = ctypes.c_uint64()
+        _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),
+                                              ctypes.byref(nbytes)))
+        self.state_bytes = nbytes.value
+        self._buf = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _abi.check(L.bwg_ensemble_create(network.handle, self.M, int(seed), int(net_id),
+                                         ctypes.c_void_p(base + off), self.state_bytes,
+                                         ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self.groups = (self.M + 31) // 32
+        self.engine = engine
+
+    def _stream(self):
+        return _stream_ptr(self.torch.cuda.current_stream(self.device))
+
+    def init_fixed(self, counts):
+        c = _i32arr(list(counts))
+        _abi.check(_lib().bwg_ensemble_init(self.handle, _abi.BWG_INIT_FIXED, c, self._stream()))
+        return self
+
+    def init_multinomial(self):
+        _abi.check(_lib().bwg_ensemble_init(self.handle, _abi.BWG_INIT_MULTINOMIAL, None,
+                                            self._stream()))
+        return self
+
+    def init(self, mode):
+        if mode[0] == "fixed":
+            return self.init_fixed(mode[1])
+        if mode[0] == "multinomial":
+            return self.init_multinomial()
+        raise ValueError(mode)
+
+    def advance(self, t_end):
+        _abi.check(_lib().bwg_ensemble_advance(self.handle, float(t_end), self._stream()))
+        return self
+
+    def step(self, n_events):
+        _abi.check(_lib().bwg_ensemble_step(self.handle, int(n_events), self._stream()))
+        return self
+
+    def read_counts(self, out=None):
+        t = self.torch
+        if out is None:
+            out = t.empty((self.M, 3), dtype=t.int32, device=self.device)
+        _abi.check(_lib().bwg_ensemble_read_counts(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                                   self._stream()))
+        return out
+
+    def histogram(self, n_bins=256, out=None):
+        t = self.torch
+        if out is None:
+            out = t.empty(n_bins, dtype=t.int64, device=self.device)
+        _abi.check(_lib().bwg_ensemble_histogram(self.handle, n_bins,
+                                                 ctypes.c_void_p(out.data_ptr()),
+                                                 self._stream()))
+        return out
+
+    def read_events(self):
+        """(events per replica, real events per 32-lane group (bitwise) or
+        per replica (plain)) as int64 tensors."""
+        t = self.torch
+        ev = t.empty(self.M, dtype=t.int64, device=self.device)
+        nr = self.groups if self.engine == "bitwise" else self.M
+        real = t.empty(nr, dtype=t.int64, device=self.device)
+        _abi.check(_lib().bwg_ensemble_read_events(self.handle, ctypes.c_void_p(ev.data_ptr()),
+                                                   ctypes.c_void_p(real.data_ptr()),
+                                                   self._stream()))
+        return ev, real
+
+    def stats(self):
+        s = _abi.Stats()
+        _abi.check(_lib().bwg_ensemble_stats(self.handle, self._stream(), ctypes.byref(s)))
+        return dict(n_replicas=s.n_replicas, advance_index=s.advance_index, t_now=s.t_now,
+                    events_total=s.events_total, real_total=s.real_total)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _lib().bwg_ensemble_destroy(h)
+            except Exception:
+                pass
+            self.handle = None

@@ -1,0 +1,103 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bwg {
+
+// Random-stream domains of the draw contract (counter word 1, bits 24..31).
+enum : uint32_t {
+    DOM_EVENT = 1,
+    DOM_BUDGET = 2,
+    DOM_INIT = 3,
+    DOM_PLAIN = 4,
+};
+
+// Frank-family structure recognised for the bit-sliced kernel: the reaction
+// table, after dropping trailing ghost reactions, is a subsequence of
+//   A -> L, A -> D, A + L -> 2L, A + D -> 2D, L + D -> 2A
+// with weights (cu, cu, 2^fa, 2^fa, 2^fi).  Absent reactions weigh 0.
+struct FrankShape {
+    uint32_t cu;     // weight constant of A -> L and of A -> D (0: absent)
+    int32_t fa;      // log2 weight of the two autocatalytic reactions, -1 absent
+    int32_t fi;      // log2 weight of L + D -> 2A, -1 absent
+};
+
+// Plain (one replica per thread) engine: 3 species, order <= 2, any table.
+struct PlainReaction {
+    int32_t kind;    // 0: unimolecular N_x; 1: N_x N_y; 2: N_x (N_x - 1) / 2
+    int32_t x, y;    // reactant species
+    int32_t d[3];    // state change
+    uint32_t c;      // weight constant
+};
+
+struct WmArgs {
+    uint32_t *planes;       // [3][NB][wp] words, species (L, D, A)
+    uint64_t *E;            // [32 wp] events done per replica
+    uint64_t *Etgt;         // [32 wp] events to reach in this advance
+    uint64_t *real;         // [wp] real events per 32-lane group
+    uint64_t wp;            // padded words (row stride)
+    uint64_t n_words;       // ceil(M / 32)
+    uint64_t M;             // replicas
+    uint64_t seed;
+    uint64_t max_events;    // events per launch per word (0: no limit)
+    uint32_t net_id;
+    int32_t B;              // threshold planes (runtime, <= BC)
+    uint32_t cu;
+    int32_t fa, fi;
+};
+
+struct PlainArgs {
+    int32_t *counts;        // [mp][3]
+    uint64_t *E;
+    uint64_t *Etgt;
+    uint64_t *real;         // [mp] real events per replica
+    uint64_t M;
+    uint64_t seed;
+    uint64_t max_events;
+    uint32_t net_id;
+    int32_t B;
+    int32_t R;
+    PlainReaction rx[16];
+};
+
+// Launchers (defined in the .hip files).  Each returns a hipError_t.
+using WmLaunch = hipError_t (*)(const WmArgs &, hipStream_t, int block);
+// Table of bit-sliced kernel instantiations: species planes NB, threshold
+// plane capacity BC and product shift FA (-1: shifts chosen at run time).
+struct WmVariant {
+    int nb, bc, fa;
+    WmLaunch fn;
+};
+extern const WmVariant kWmVariants[];
+extern const int kWmVariantCount;
+
+hipError_t launch_plain(const PlainArgs &a, hipStream_t s, int block);
+
+hipError_t launch_init_fixed(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
+                             const int32_t counts[3], uint64_t *E, uint64_t *Etgt,
+                             uint64_t *real, hipStream_t s);
+hipError_t launch_init_multinomial(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
+                                   int64_t n_tot, uint64_t seed, uint32_t net_id,
+                                   uint64_t *E, uint64_t *Etgt, uint64_t *real,
+                                   hipStream_t s);
+hipError_t launch_plain_init(int32_t *counts, uint64_t M, int mode, const int32_t c3[3],
+                             int64_t n_tot, uint64_t seed, uint32_t net_id,
+                             uint64_t *E, uint64_t *Etgt, uint64_t *real, hipStream_t s);
+hipError_t launch_budget(const uint64_t *table, uint64_t len, int64_t k_lo,
+                         uint64_t fixed_k, int use_table, uint64_t seed,
+                         uint32_t net_id, uint64_t advance, uint64_t M,
+                         const uint64_t *E, uint64_t *Etgt, hipStream_t s);
+hipError_t launch_read_counts_planes(const uint32_t *planes, int nb, uint64_t wp,
+                                     uint64_t M, int32_t *dst, hipStream_t s);
+hipError_t launch_read_counts_plain(const int32_t *counts, uint64_t M, int32_t *dst,
+                                    hipStream_t s);
+hipError_t launch_histogram(const uint32_t *planes, const int32_t *counts, int nb,
+                            uint64_t wp, uint64_t M, int64_t n_tot, int n_bins,
+                            uint64_t *dst, hipStream_t s);
+hipError_t launch_copy_u64(const uint64_t *src, uint64_t *dst, uint64_t n, hipStream_t s);
+hipError_t launch_sum_u64(const uint64_t *src, uint64_t n, uint64_t *dst2, int slot,
+                          hipStream_t s);
+
+}  // namespace bwg

@@ -1,0 +1,694 @@
+// C ABI of the bit-parallel Gillespie library: networks, quantisation,
+// ensembles, launches.  See include/bwg.h for the contract of every call.
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bwg.h"
+#include "bwg_internal.h"
+
+namespace bwg {
+int poisson_table_q(double mu, int64_t *k_lo, std::vector<uint64_t> &T);
+}
+
+using namespace bwg;
+
+// ---- errors ------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(BWG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+extern "C" const char *bwg_last_error(void) { return g_err.c_str(); }
+
+// ---- networks ------------------------------------------------------------------
+
+struct Table {
+    int64_t k_lo;
+    uint64_t len;
+    uint64_t *host;  // pinned; lives as long as the network
+};
+
+struct bwg_net {
+    int S = 0, R = 0;
+    std::vector<int32_t> reac, prod;
+    std::vector<double> rates;
+    int64_t n_tot = 0;
+    int32_t lx = 0, ly = 0;
+    bwg_qnet q{};
+    FrankShape shape{};
+    bool shape_ok = false;
+    PlainReaction prx[16]{};
+    bool plain_ok = false;
+    std::mutex mu;
+    std::map<uint64_t, Table> tables;  // keyed by the bits of mu
+    ~bwg_net()
+    {
+        for (auto &kv : tables)
+            if (kv.second.host) (void)hipHostFree(kv.second.host);
+    }
+};
+
+static int64_t comb_h(const int32_t *r, const int64_t *N, int S)
+{
+    int64_t v = 1;
+    for (int x = 0; x < S; ++x) {
+        if (r[x] == 1)
+            v *= N[x];
+        else if (r[x] == 2)
+            v *= N[x] * (N[x] - 1) / 2;
+    }
+    return v;
+}
+
+// Largest total weight over every state with n_tot molecules (3 species).
+static int64_t max_total_weight(const bwg_net &n)
+{
+    int64_t best = 0;
+    const int64_t N = n.n_tot;
+    int64_t st[3];
+    for (int64_t a = 0; a <= N; ++a)
+        for (int64_t b = 0; b <= N - a; ++b) {
+            st[0] = a;
+            st[1] = b;
+            st[2] = N - a - b;
+            int64_t t = 0;
+            for (int j = 0; j < n.R; ++j)
+                if (n.q.c[j]) t += n.q.c[j] * comb_h(&n.reac[j * n.S], st, n.S);
+            if (t > best) best = t;
+        }
+    return best;
+}
+
+static int ilog2_exact(int64_t c)  // log2 of a power of two, else -2
+{
+    if (c <= 0 || (c & (c - 1))) return -2;
+    int k = 0;
+    while ((1ll << k) < c) ++k;
+    return k;
+}
+
+// Frank-family recognition for the bit-sliced kernel (species L, D, A).
+static void classify(bwg_net &n)
+{
+    n.shape_ok = false;
+    if (n.S != 3) return;
+    static const int32_t RX[5][2][3] = {
+        {{0, 0, 1}, {1, 0, 0}},  // A -> L
+        {{0, 0, 1}, {0, 1, 0}},  // A -> D
+        {{1, 0, 1}, {2, 0, 0}},  // A + L -> 2L
+        {{0, 1, 1}, {0, 2, 0}},  // A + D -> 2D
+        {{1, 1, 0}, {0, 0, 2}},  // L + D -> 2A
+    };
+    int64_t c[5] = {0, 0, 0, 0, 0};
+    int last = -1;
+    bool ghosts_started = false;
+    for (int j = 0; j < n.R; ++j) {
+        const int32_t *r = &n.reac[j * 3], *p = &n.prod[j * 3];
+        const bool ghost = r[0] == p[0] && r[1] == p[1] && r[2] == p[2];
+        if (ghost) {
+            ghosts_started = true;
+            continue;
+        }
+        if (ghosts_started) return;
+        int t = -1;
+        for (int k = 0; k < 5; ++k)
+            if (!memcmp(r, RX[k][0], sizeof(RX[k][0])) && !memcmp(p, RX[k][1], sizeof(RX[k][1])))
+                t = k;
+        if (t < 0 || t <= last) return;
+        last = t;
+        c[t] = n.q.c[j];
+    }
+    if (c[0] != c[1]) return;
+    if (c[2] != c[3]) return;
+    if (c[0] >= (1ll << 32)) return;
+    const int fa = c[2] ? ilog2_exact(c[2]) : -1;
+    const int fi = c[4] ? ilog2_exact(c[4]) : -1;
+    if (fa == -2 || fi == -2) return;
+    n.shape.cu = (uint32_t)c[0];
+    n.shape.fa = fa;
+    n.shape.fi = fi;
+    n.shape_ok = true;
+}
+
+static void classify_plain(bwg_net &n)
+{
+    n.plain_ok = false;
+    if (n.S != 3 || n.R > 16) return;
+    for (int j = 0; j < n.R; ++j) {
+        const int32_t *r = &n.reac[j * 3], *p = &n.prod[j * 3];
+        PlainReaction &rx = n.prx[j];
+        int xs[2], k = 0;
+        for (int x = 0; x < 3; ++x)
+            for (int m = 0; m < r[x]; ++m) xs[k++] = x;
+        if (k == 1) {
+            rx.kind = 0;
+            rx.x = rx.y = xs[0];
+        } else if (xs[0] != xs[1]) {
+            rx.kind = 1;
+            rx.x = xs[0];
+            rx.y = xs[1];
+        } else {
+            rx.kind = 2;
+            rx.x = rx.y = xs[0];
+        }
+        for (int x = 0; x < 3; ++x) rx.d[x] = p[x] - r[x];
+        if (n.q.c[j] >= (1ll << 32)) return;
+        rx.c = (uint32_t)n.q.c[j];
+    }
+    n.plain_ok = true;
+}
+
+extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
+{
+    if (!d || !out) return fail(BWG_EINVAL, "null argument");
+    *out = nullptr;
+    const int S = d->n_species, R = d->n_reactions;
+    if (S < 1 || S > BWG_MAX_SPECIES) return fail(BWG_EINVAL, "n_species %d out of range", S);
+    if (R < 1 || R > BWG_MAX_REACTIONS) return fail(BWG_EINVAL, "n_reactions %d out of range", R);
+    if (!d->reactants || !d->products || !d->rates) return fail(BWG_EINVAL, "null table");
+    if (d->n_tot < 1) return fail(BWG_EINVAL, "n_tot must be >= 1");
+    if (d->lx || d->ly) return fail(BWG_EUNSUPPORTED, "lattice networks are not available");
+    if (S != 3) return fail(BWG_EUNSUPPORTED, "the GPU engines implement 3 species");
+    if (d->n_tot >= (1ll << 14)) return fail(BWG_ERANGE, "n_tot beyond 14 count planes");
+    auto n = new bwg_net();
+    n->S = S;
+    n->R = R;
+    n->reac.assign(d->reactants, d->reactants + S * R);
+    n->prod.assign(d->products, d->products + S * R);
+    n->rates.assign(d->rates, d->rates + R);
+    n->n_tot = d->n_tot;
+    for (int j = 0; j < R; ++j) {
+        int o = 0, op = 0;
+        for (int x = 0; x < S; ++x) {
+            const int32_t r = n->reac[j * S + x], p = n->prod[j * S + x];
+            if (r < 0 || p < 0) {
+                delete n;
+                return fail(BWG_EINVAL, "reaction %d: negative stoichiometry", j);
+            }
+            o += r;
+            op += p;
+        }
+        if (o < 1 || o > 2) {
+            delete n;
+            return fail(BWG_EINVAL, "reaction %d: order %d not in {1, 2}", j, o);
+        }
+        if (o != op) {
+            delete n;
+            return fail(BWG_EINVAL, "reaction %d does not conserve the molecule count", j);
+        }
+        const double k = n->rates[j];
+        if (!(k >= 0) || std::isinf(k)) {
+            delete n;
+            return fail(BWG_EINVAL, "reaction %d: rate must be finite and >= 0", j);
+        }
+    }
+    // ---- quantisation: integer weights c_j = rint(k_j s), s = 2^f / k_ref
+    bwg_qnet &q = n->q;
+    q.n_species = S;
+    q.n_reactions = R;
+    const int prec = d->precision_bits > 0 ? d->precision_bits : 7;
+    if (d->flags & BWG_EXACT_INTEGER) {
+        for (int j = 0; j < R; ++j) {
+            const double k = n->rates[j];
+            if (k != std::floor(k) || k >= 4294967296.0) {
+                delete n;
+                return fail(BWG_EINVAL, "exact-integer table: rate %d is not a 32-bit integer", j);
+            }
+            q.c[j] = (int64_t)k;
+        }
+        q.f = 0;
+        q.s = 1.0;
+    } else {
+        double k_bi = 0, k_any = 0;
+        for (int j = 0; j < R; ++j) {
+            int o = 0;
+            for (int x = 0; x < S; ++x) o += n->reac[j * S + x];
+            if (n->rates[j] > 0) {
+                k_any = std::max(k_any, n->rates[j]);
+                if (o == 2) k_bi = std::max(k_bi, n->rates[j]);
+            }
+        }
+        if (k_any <= 0) {
+            delete n;
+            return fail(BWG_EINVAL, "every rate is zero");
+        }
+        const double k_ref = k_bi > 0 ? k_bi : k_any;
+        int f = 0;
+        for (; f < 63; ++f) {
+            const double s = std::ldexp(1.0, f) / k_ref;
+            bool ok = true;
+            for (int j = 0; j < R && ok; ++j) {
+                if (!(n->rates[j] > 0)) continue;
+                const double x = n->rates[j] * s;
+                const double c = std::nearbyint(x);
+                if (!(x == c || c >= std::ldexp(1.0, prec))) ok = false;
+            }
+            if (ok) break;
+        }
+        if (f >= 63) {
+            delete n;
+            return fail(BWG_ERANGE, "no scale reaches %d bits of rate precision", prec);
+        }
+        q.f = f;
+        q.s = std::ldexp(1.0, f) / k_ref;
+        for (int j = 0; j < R; ++j) {
+            const double c = std::nearbyint(n->rates[j] * q.s);
+            if (c >= 4294967296.0) {
+                delete n;
+                return fail(BWG_ERANGE, "weight of reaction %d beyond 32 bits", j);
+            }
+            q.c[j] = (int64_t)c;
+        }
+    }
+    q.max_total = max_total_weight(*n);
+    int B = 1;
+    while (B < 63 && (1ll << B) < q.max_total) ++B;
+    if (B > 32) {
+        delete n;
+        return fail(BWG_ERANGE, "total weight %lld needs %d threshold planes (max 32)",
+                    (long long)q.max_total, B);
+    }
+    q.B = B;
+    int b = 1;
+    while ((1ll << b) <= n->n_tot) ++b;
+    q.b = b;
+    q.lambda = std::ldexp(1.0, B) / q.s;
+    classify(*n);
+    classify_plain(*n);
+    q.gpu_ok = n->shape_ok ? 1 : 0;
+    *out = n;
+    return BWG_OK;
+}
+
+extern "C" int bwg_net_quantized(const bwg_net *n, bwg_qnet *out)
+{
+    if (!n || !out) return fail(BWG_EINVAL, "null argument");
+    *out = n->q;
+    return BWG_OK;
+}
+
+extern "C" void bwg_net_destroy(bwg_net *n) { delete n; }
+
+extern "C" int bwg_poisson_table(double mu, int64_t *k_lo, uint64_t *table, uint64_t cap,
+                                 uint64_t *len)
+{
+    if (!k_lo || !len) return fail(BWG_EINVAL, "null argument");
+    std::vector<uint64_t> T;
+    if (poisson_table_q(mu, k_lo, T) != 0) return fail(BWG_EINVAL, "invalid mean %g", mu);
+    *len = T.size();
+    if (T.size() > cap || !table)
+        return table ? fail(BWG_ERANGE, "table needs %zu entries", T.size()) : BWG_OK;
+    memcpy(table, T.data(), T.size() * sizeof(uint64_t));
+    return BWG_OK;
+}
+
+// Cached pinned copy of the table for mean mu.
+static int get_table(bwg_net *n, double mu, const Table **out)
+{
+    uint64_t key;
+    memcpy(&key, &mu, sizeof key);
+    std::lock_guard<std::mutex> g(n->mu);
+    auto it = n->tables.find(key);
+    if (it == n->tables.end()) {
+        std::vector<uint64_t> T;
+        int64_t k_lo;
+        if (poisson_table_q(mu, &k_lo, T) != 0) return fail(BWG_EINVAL, "invalid mean %g", mu);
+        Table t{k_lo, T.size(), nullptr};
+        HIP_TRY(hipHostMalloc((void **)&t.host, T.size() * sizeof(uint64_t), hipHostMallocDefault));
+        memcpy(t.host, T.data(), T.size() * sizeof(uint64_t));
+        it = n->tables.emplace(key, t).first;
+    }
+    *out = &it->second;
+    return BWG_OK;
+}
+
+// ---- ensembles ------------------------------------------------------------------
+
+struct bwg_ens {
+    bwg_net *net = nullptr;
+    uint64_t M = 0, seed = 0;
+    uint32_t net_id = 0;
+    int engine = 0, block = 0;
+    uint64_t table_cap = 0, epl = 0;
+    uint8_t *buf = nullptr;
+    uint64_t bytes = 0;
+    uint64_t wp = 0;
+    int nb = 0;
+    const WmVariant *var = nullptr;
+    uint32_t *planes = nullptr;
+    int32_t *counts = nullptr;
+    uint64_t *E = nullptr, *Et = nullptr, *real = nullptr, *table = nullptr, *scratch = nullptr;
+    double t_now = 0;
+    uint64_t adv = 0;
+    uint64_t lag = 0;      // bound on how far a word's lanes can be apart
+    bool inited = false;
+};
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+struct Layout {
+    uint64_t wp, planes, counts, E, Et, real, table, scratch, total;
+};
+
+static const WmVariant *pick_variant(const bwg_net *n)
+{
+    if (!n->shape_ok) return nullptr;
+    const int b = n->q.b;
+    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
+    const int fa = n->shape.fa, fi = n->shape.fi;
+    const int f_common = fa >= 0 ? fa : fi;
+    const bool same = (fa < 0 || fi < 0 || fa == fi);
+    const WmVariant *best = nullptr;
+    for (int i = 0; i < kWmVariantCount; ++i) {
+        const WmVariant &v = kWmVariants[i];
+        if (v.nb < b || v.bc < need_bc) continue;
+        if (v.fa >= 0 && !(same && v.fa == f_common && f_common >= 0)) continue;
+        if (fa >= v.bc || fi >= v.bc) continue;
+        if (!best) {
+            best = &v;
+            continue;
+        }
+        // prefer a compile-time shift, then the fewest planes
+        const bool vs = v.fa >= 0, bs = best->fa >= 0;
+        if (vs != bs) {
+            if (vs) best = &v;
+            continue;
+        }
+        if (v.nb + v.bc < best->nb + best->bc) best = &v;
+    }
+    return best;
+}
+
+static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_cap,
+                     const WmVariant *v)
+{
+    Layout L{};
+    const uint64_t words = (M + 31) / 32;
+    L.wp = (words + 63) / 64 * 64;
+    const uint64_t mp = 32 * L.wp;
+    uint64_t off = 0;
+    if (engine == BWG_ENGINE_BITWISE) {
+        L.planes = off;
+        off = align256(off + 3ull * (uint64_t)v->nb * L.wp * 4);
+        L.counts = ~0ull;
+    } else {
+        L.counts = off;
+        off = align256(off + 3ull * mp * 4);
+        L.planes = ~0ull;
+    }
+    L.E = off;
+    off = align256(off + mp * 8);
+    L.Et = off;
+    off = align256(off + mp * 8);
+    L.real = off;
+    off = align256(off + (engine == BWG_ENGINE_BITWISE ? L.wp : mp) * 8);
+    L.table = off;
+    off = align256(off + table_cap * 8);
+    L.scratch = off;
+    off = align256(off + 64 * 8);
+    L.total = off;
+    (void)n;
+    return L;
+}
+
+static int check_engine(const bwg_net *n, int engine, const WmVariant **v)
+{
+    *v = nullptr;
+    if (engine == BWG_ENGINE_BITWISE) {
+        if (!n->shape_ok)
+            return fail(BWG_EUNSUPPORTED,
+                        "network is not of the Frank family the bit-sliced kernel implements");
+        *v = pick_variant(n);
+        if (!*v)
+            return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for b=%d B=%d fa=%d fi=%d",
+                        n->q.b, n->q.B, n->shape.fa, n->shape.fi);
+        return BWG_OK;
+    }
+    if (engine == BWG_ENGINE_PLAIN) {
+        if (!n->plain_ok) return fail(BWG_EUNSUPPORTED, "network not supported by the plain engine");
+        return BWG_OK;
+    }
+    return fail(BWG_EINVAL, "unknown engine %d", engine);
+}
+
+extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_opts *o,
+                                        uint64_t *bytes)
+{
+    if (!n || !bytes) return fail(BWG_EINVAL, "null argument");
+    if (M == 0 || M >= (1ull << 32)) return fail(BWG_EINVAL, "replica count out of range");
+    const int engine = o ? o->engine : BWG_ENGINE_BITWISE;
+    const WmVariant *v;
+    int rc = check_engine(n, engine, &v);
+    if (rc) return rc;
+    const uint64_t cap = (o && o->table_capacity) ? o->table_capacity : 65536;
+    *bytes = layout(n, M, engine, cap, v).total;
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, uint32_t net_id,
+                                   void *dev_buf, uint64_t buf_bytes, const bwg_opts *o,
+                                   bwg_ens **out)
+{
+    if (!n || !out || !dev_buf) return fail(BWG_EINVAL, "null argument");
+    *out = nullptr;
+    if ((uintptr_t)dev_buf & 255) return fail(BWG_EINVAL, "device buffer not 256-byte aligned");
+    uint64_t need;
+    int rc = bwg_ensemble_state_bytes(n, M, o, &need);
+    if (rc) return rc;
+    if (buf_bytes < need)
+        return fail(BWG_ENOMEM, "buffer of %llu bytes, need %llu", (unsigned long long)buf_bytes,
+                    (unsigned long long)need);
+    auto e = new bwg_ens();
+    e->net = const_cast<bwg_net *>(n);
+    e->M = M;
+    e->seed = seed;
+    e->net_id = net_id;
+    e->engine = o ? o->engine : BWG_ENGINE_BITWISE;
+    e->block = o ? o->block : 0;
+    e->table_cap = (o && o->table_capacity) ? o->table_capacity : 65536;
+    e->epl = o ? o->events_per_launch : 0;
+    check_engine(n, e->engine, &e->var);
+    const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
+    e->buf = (uint8_t *)dev_buf;
+    e->bytes = buf_bytes;
+    e->wp = L.wp;
+    e->nb = e->var ? e->var->nb : 0;
+    if (e->engine == BWG_ENGINE_BITWISE)
+        e->planes = (uint32_t *)(e->buf + L.planes);
+    else
+        e->counts = (int32_t *)(e->buf + L.counts);
+    e->E = (uint64_t *)(e->buf + L.E);
+    e->Et = (uint64_t *)(e->buf + L.Et);
+    e->real = (uint64_t *)(e->buf + L.real);
+    e->table = (uint64_t *)(e->buf + L.table);
+    e->scratch = (uint64_t *)(e->buf + L.scratch);
+    *out = e;
+    return BWG_OK;
+}
+
+extern "C" void bwg_ensemble_destroy(bwg_ens *e) { delete e; }
+
+extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    hipStream_t s = (hipStream_t)stream;
+    const bwg_net *n = e->net;
+    int32_t c[3] = {0, 0, 0};
+    if (mode == BWG_INIT_FIXED) {
+        if (!counts) return fail(BWG_EINVAL, "fixed init needs counts");
+        int64_t sum = 0;
+        for (int x = 0; x < 3; ++x) {
+            if (counts[x] < 0) return fail(BWG_EINVAL, "negative initial count");
+            c[x] = counts[x];
+            sum += counts[x];
+        }
+        if (sum != n->n_tot)
+            return fail(BWG_EINVAL, "initial counts sum to %lld, not n_tot = %lld", (long long)sum,
+                        (long long)n->n_tot);
+    } else if (mode != BWG_INIT_MULTINOMIAL) {
+        return fail(BWG_EINVAL, "unknown init mode %d", mode);
+    }
+    if (e->engine == BWG_ENGINE_BITWISE) {
+        if (mode == BWG_INIT_FIXED)
+            HIP_TRY(launch_init_fixed(e->planes, e->nb, e->wp, e->M, c, e->E, e->Et, e->real, s));
+        else
+            HIP_TRY(launch_init_multinomial(e->planes, e->nb, e->wp, e->M, n->n_tot, e->seed,
+                                            e->net_id, e->E, e->Et, e->real, s));
+    } else {
+        HIP_TRY(launch_plain_init(e->counts, 32 * e->wp, mode == BWG_INIT_FIXED ? 0 : 1, c,
+                                  n->n_tot, e->seed, e->net_id, e->E, e->Et, e->real, s));
+    }
+    e->t_now = 0;
+    e->adv = 0;
+    e->lag = 0;
+    e->inited = true;
+    return BWG_OK;
+}
+
+// Enqueue the event launches of one advance or step.  k_min/k_max bound the
+// budgets just drawn.
+static int run_events(bwg_ens *e, uint64_t k_min, uint64_t k_max, hipStream_t s)
+{
+    const bwg_net *n = e->net;
+    uint64_t launches = 1;
+    if (e->epl) {
+        const uint64_t span = k_max + e->lag;
+        launches = span ? (span + e->epl - 1) / e->epl : 1;
+    }
+    e->lag += k_max - k_min;
+    for (uint64_t l = 0; l < launches; ++l) {
+        if (e->engine == BWG_ENGINE_BITWISE) {
+            WmArgs a{};
+            a.planes = e->planes;
+            a.E = e->E;
+            a.Etgt = e->Et;
+            a.real = e->real;
+            a.wp = e->wp;
+            a.n_words = (e->M + 31) / 32;
+            a.M = e->M;
+            a.seed = e->seed;
+            a.max_events = e->epl;
+            a.net_id = e->net_id;
+            a.B = n->q.B;
+            a.cu = n->shape.cu;
+            a.fa = n->shape.fa;
+            a.fi = n->shape.fi;
+            HIP_TRY(e->var->fn(a, s, e->block));
+        } else {
+            PlainArgs a{};
+            a.counts = e->counts;
+            a.E = e->E;
+            a.Etgt = e->Et;
+            a.real = e->real;
+            a.M = e->M;
+            a.seed = e->seed;
+            a.max_events = e->epl;
+            a.net_id = e->net_id;
+            a.B = n->q.B;
+            a.R = n->R;
+            for (int j = 0; j < n->R; ++j) a.rx[j] = n->prx[j];
+            HIP_TRY(launch_plain(a, s, e->block));
+        }
+    }
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
+    if (!(t_end >= e->t_now)) return fail(BWG_EINVAL, "t_end %g before t_now %g", t_end, e->t_now);
+    if (e->adv >= (1ull << 48)) return fail(BWG_ERANGE, "advance index overflow");
+    hipStream_t s = (hipStream_t)stream;
+    const double mu = e->net->q.lambda * (t_end - e->t_now);
+    uint64_t kmin = 0, kmax = 0;
+    if (mu > 0) {
+        const Table *t;
+        int rc = get_table(e->net, mu, &t);
+        if (rc) return rc;
+        if (t->len > e->table_cap)
+            return fail(BWG_ERANGE, "Poisson table of %llu entries exceeds capacity %llu",
+                        (unsigned long long)t->len, (unsigned long long)e->table_cap);
+        HIP_TRY(hipMemcpyAsync(e->table, t->host, t->len * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_budget(e->table, t->len, t->k_lo, 0, 1, e->seed, e->net_id, e->adv, e->M,
+                              e->E, e->Et, s));
+        kmin = (uint64_t)t->k_lo;
+        kmax = (uint64_t)t->k_lo + t->len;
+    } else {
+        HIP_TRY(launch_budget(nullptr, 0, 0, 0, 0, e->seed, e->net_id, e->adv, e->M, e->E, e->Et,
+                              s));
+    }
+    int rc = run_events(e, kmin, kmax, s);
+    if (rc) return rc;
+    e->t_now = t_end;
+    e->adv += 1;
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_budget(nullptr, 0, 0, n_events, 0, e->seed, e->net_id, 0, e->M, e->E, e->Et, s));
+    return run_events(e, n_events, n_events, s);
+}
+
+extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)
+{
+    if (!e || !dst) return fail(BWG_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (e->engine == BWG_ENGINE_BITWISE)
+        HIP_TRY(launch_read_counts_planes(e->planes, e->nb, e->wp, e->M, dst, s));
+    else
+        HIP_TRY(launch_read_counts_plain(e->counts, e->M, dst, s));
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst, void *stream)
+{
+    if (!e || !dst) return fail(BWG_EINVAL, "null argument");
+    if (n_bins < 1 || n_bins > 16384) return fail(BWG_EINVAL, "n_bins %d out of range", n_bins);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_histogram(e->engine == BWG_ENGINE_BITWISE ? e->planes : nullptr, e->counts,
+                             e->nb, e->wp, e->M, e->net->n_tot, n_bins, dst, s));
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_read_events(bwg_ens *e, uint64_t *dev_events, uint64_t *dev_real,
+                                        void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    hipStream_t s = (hipStream_t)stream;
+    if (dev_events) HIP_TRY(launch_copy_u64(e->E, dev_events, e->M, s));
+    if (dev_real) {
+        if (e->engine == BWG_ENGINE_BITWISE)
+            HIP_TRY(launch_copy_u64(e->real, dev_real, (e->M + 31) / 32, s));
+        else
+            HIP_TRY(launch_copy_u64(e->real, dev_real, e->M, s));
+    }
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_stats(bwg_ens *e, void *stream, bwg_stats *out)
+{
+    if (!e || !out) return fail(BWG_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_sum_u64(e->E, e->M, e->scratch, 0, s));
+    HIP_TRY(launch_sum_u64(e->real, e->engine == BWG_ENGINE_BITWISE ? (e->M + 31) / 32 : e->M,
+                           e->scratch, 1, s));
+    uint64_t h[2];
+    HIP_TRY(hipMemcpyAsync(h, e->scratch, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out->n_replicas = e->M;
+    out->advance_index = e->adv;
+    out->t_now = e->t_now;
+    out->events_total = h[0];
+    out->real_total = h[1];
+    return BWG_OK;
+}

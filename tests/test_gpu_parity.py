@@ -1,0 +1,226 @@
+"""GPU path against the CPU oracle, through the C ABI.
+
+Every comparison is bit-exact: counts of every replica, events run per
+replica and real (state-changing) events per 32-lane group.  Both sides use
+the same seeded inputs and the same draw contract; they share no code.
+"""
+
+import numpy as np
+import pytest
+
+import paper_2412_16613_amd as bwg
+from oracle import ssa
+from oracle.poisson import poisson_table
+from oracle.quantize import quantize
+from workloads import config, frank_network, paper_network
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def gpu_run(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0):
+    n = bwg.Network(net)
+    ens = bwg.Ensemble(n, M, seed=seed, net_id=net_id, engine=engine, events_per_launch=epl)
+    ens.init(init)
+    for op, v in schedule:
+        if op == "advance":
+            ens.advance(v)
+        else:
+            ens.step(v)
+    counts = ens.read_counts()
+    ev, real = ens.read_events()
+    torch.cuda.synchronize()
+    return (counts.cpu().numpy(), ev.cpu().numpy().astype(np.uint64),
+            real.cpu().numpy().astype(np.uint64), ens)
+
+
+def oracle_run(net, M, init, schedule, seed=0, net_id=0, draw=ssa.DRAW_EVENT, first=0,
+               count=None):
+    E = ssa.OracleEnsemble(net, M, seed=seed, net_id=net_id, draw=draw, first=first,
+                           count=count)
+    E.init(init)
+    for op, v in schedule:
+        if op == "advance":
+            E.advance(v)
+        else:
+            E.step(v)
+    return E
+
+
+def group_sums(x, M):
+    g = (M + 31) // 32
+    out = np.zeros(g, dtype=np.uint64)
+    np.add.at(out, np.arange(M) // 32, x.astype(np.uint64))
+    return out
+
+
+def check_parity(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0):
+    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl)
+    counts, ev, real, ens = gpu_run(torch, net, M, init, schedule, seed, net_id, engine, epl)
+    draw = ssa.DRAW_EVENT if engine == "bitwise" else ssa.DRAW_PLAIN
+    o = oracle_run(net, M, init, schedule, seed, net_id, draw)
+    np.testing.assert_array_equal(counts, o.counts)
+    np.testing.assert_array_equal(ev, o.E)
+    if engine == "bitwise":
+        np.testing.assert_array_equal(real, group_sums(o.real, M))
+    else:
+        np.testing.assert_array_equal(real, o.real)
+    assert (counts.sum(1) == net["n_tot"]).all()
+    return counts, ens
+
+
+# ---- bit-sliced engine --------------------------------------------------------
+
+def test_small_well_mixed_workload_exact(torch):
+    c = config("c0")
+    counts, ens = check_parity(torch, c["net"], c["replicas"], c["init"],
+                               [("advance", c["t_end"])])
+    h = ens.histogram(256).cpu().numpy()
+    np.testing.assert_array_equal(h, ssa.ee_histogram(counts, 32, 256).astype(np.int64))
+    s = ens.stats()
+    assert s["advance_index"] == 1 and s["t_now"] == 50.0
+
+
+def test_ragged_replicas_and_several_advances(torch):
+    check_parity(torch, frank_network(32), 1000, ("fixed", (0, 0, 32)),
+                 [("advance", 10.0), ("advance", 25.0), ("advance", 25.0), ("advance", 50.0)],
+                 seed=7, net_id=3)
+
+
+@pytest.mark.parametrize("M", [1, 31, 33, 65])
+def test_partial_words(torch, M):
+    check_parity(torch, frank_network(32), M, ("fixed", (4, 3, 25)),
+                 [("advance", 20.0), ("step", 300)], seed=11, net_id=1)
+
+
+def test_events_per_launch_chunking(torch):
+    net = frank_network(32)
+    sched = [("advance", 15.0), ("advance", 40.0)]
+    check_parity(torch, net, 2048, ("fixed", (0, 0, 32)), sched, seed=5, epl=97)
+    a = gpu_run(torch, net, 2048, ("fixed", (0, 0, 32)), sched, seed=5, epl=0)
+    b = gpu_run(torch, net, 2048, ("fixed", (0, 0, 32)), sched, seed=5, epl=1)
+    np.testing.assert_array_equal(a[0], b[0])
+
+
+def test_per_event_trajectories(torch):
+    # state after every single event equals the oracle's trajectory
+    net = frank_network(32, k0=0.05)
+    M, K = 96, 150
+    n = bwg.Network(net)
+    ens = bwg.Ensemble(n, M, seed=2, net_id=9)
+    ens.init_fixed((10, 12, 10))
+    states = []
+    for _ in range(K):
+        ens.step(1)
+        states.append(ens.read_counts().cpu().numpy())
+    torch.cuda.synchronize()
+    q = quantize(net)
+    counts0 = np.tile(np.array([10, 12, 10], np.int32), (M, 1))
+    _, _, traj = ssa.run_events(net, q, 2, 9, 0, counts0, np.zeros(M, np.uint64),
+                                np.full(M, K, np.uint64), traj_len=K)
+    for t in range(K):
+        np.testing.assert_array_equal(states[t], traj[:, t, :])
+
+
+def test_paper_network_multinomial_start(torch):
+    c = config("c0p")
+    check_parity(torch, c["net"], 4096, ("multinomial",), [("step", 3000)], seed=1)
+
+
+@pytest.mark.parametrize("n_tot,k0", [(12, 0.01), (40, 0.05), (100, 0.01), (300, 0.002),
+                                      (1000, 0.02), (16, 0.1)])
+def test_run_time_shift_kernels(torch, n_tot, k0):
+    net = frank_network(n_tot, k0=k0)
+    check_parity(torch, net, 700, ("fixed", (0, 0, n_tot)), [("advance", 3.0)], seed=4,
+                 net_id=n_tot)
+
+
+def test_pure_conversion_without_bimolecular_reactions(torch):
+    net = frank_network(20, k0=0.05, k1=0.0, k2=0.0)
+    check_parity(torch, net, 512, ("fixed", (0, 0, 20)), [("advance", 5.0)], seed=12)
+
+
+def test_paper_network_without_ghosts(torch):
+    net = paper_network(24, ghosts=False)
+    check_parity(torch, net, 256, ("multinomial",), [("step", 1000)], seed=13)
+
+
+def test_zero_length_advance_is_a_no_op(torch):
+    net = frank_network(32)
+    a = gpu_run(torch, net, 128, ("fixed", (0, 0, 32)), [("advance", 5.0)], seed=3)
+    b = gpu_run(torch, net, 128, ("fixed", (0, 0, 32)), [("advance", 5.0), ("advance", 5.0)],
+                seed=3)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_deterministic_reruns(torch):
+    net = frank_network(64)
+    a = gpu_run(torch, net, 4096, ("fixed", (0, 0, 64)), [("advance", 30.0)], seed=21)
+    b = gpu_run(torch, net, 4096, ("fixed", (0, 0, 64)), [("advance", 30.0)], seed=21)
+    np.testing.assert_array_equal(a[0], b[0])
+
+
+def test_error_paths(torch):
+    n = bwg.Network(frank_network(32))
+    ens = bwg.Ensemble(n, 64)
+    with pytest.raises(bwg.BwgError):
+        ens.advance(1.0)          # not initialised
+    ens.init_fixed((0, 0, 32))
+    ens.advance(2.0)
+    with pytest.raises(bwg.BwgError):
+        ens.advance(1.0)          # backwards in time
+    with pytest.raises(bwg.BwgError):
+        ens.init_fixed((0, 0, 31))  # does not sum to N_tot
+    with pytest.raises(bwg.BwgError):
+        ens.histogram(0)
+
+
+# ---- comparator engine -----------------------------------------------------------
+
+def test_plain_engine_exact(torch):
+    c = config("c0")
+    check_parity(torch, c["net"], c["replicas"], c["init"], [("advance", c["t_end"])],
+                 engine="plain")
+
+
+def test_plain_engine_ragged_and_multinomial(torch):
+    check_parity(torch, paper_network(32), 777, ("multinomial",), [("step", 2000)], seed=8,
+                 engine="plain")
+    check_parity(torch, frank_network(100), 333, ("fixed", (0, 0, 100)),
+                 [("advance", 2.0), ("advance", 7.0)], seed=9, engine="plain", epl=50)
+
+
+# ---- full-size workload -----------------------------------------------------------
+
+def test_full_size_well_mixed_workload_sampled(torch):
+    # N_tot = 1024, 2^20 replicas, t_end = 100 in one launch: exact parity on
+    # sampled replicas, exact event counts for every replica, conservation
+    # and histogram mass for all.
+    c = config("c1")
+    net, M = c["net"], c["replicas"]
+    _say("case full-size", M)
+    counts, ev, real, ens = gpu_run(torch, net, M, c["init"], [("advance", c["t_end"])])
+    hist = ens.histogram(256).cpu().numpy()
+    assert (counts.sum(1) == 1024).all() and (counts >= 0).all()
+    assert hist.sum() == M
+    np.testing.assert_array_equal(hist, ssa.ee_histogram(counts, 1024, 256).astype(np.int64))
+    q = quantize(net)
+    table = poisson_table(q["Lambda"] * c["t_end"])
+    K = ssa.budgets(0, 0, 0, 0, M, table)
+    np.testing.assert_array_equal(ev, K)
+    for first in (0, 1 << 19, M - 32, 777 * 32 + 5):
+        E = ssa.OracleEnsemble(net, M, first=first, count=16)
+        E.init(c["init"])
+        E.advance(c["t_end"])
+        np.testing.assert_array_equal(counts[first:first + 16], E.counts)
