@@ -46,14 +46,23 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=65536)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path shards by replica across GPUs "
               "(see DESIGN.md) but no multi-GPU run is part of this build", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+    if args.copy_ref:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": 1 << 30}))
+        return
     import paper_2412_16613_amd as bwg
     from workloads import config
 

@@ -39,8 +39,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
         }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // one 3-input xor each (the round key is wave-uniform)
+        const uint32_t n0 = BWG_OP3((uint32_t)(p1 >> 32), c1, k0, L_XOR3);
+        const uint32_t n2 = BWG_OP3((uint32_t)(p0 >> 32), c3, k1, L_XOR3);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

@@ -65,9 +65,10 @@ struct PlainArgs {
 // Launchers (defined in the .hip files).  Each returns a hipError_t.
 using WmLaunch = hipError_t (*)(const WmArgs &, hipStream_t, int block);
 // Table of bit-sliced kernel instantiations: species planes NB, threshold
-// plane capacity BC and product shift FA (-1: shifts chosen at run time).
+// plane capacity BC, product shift FA and unimolecular weight CU (-1: taken
+// at run time).
 struct WmVariant {
-    int nb, bc, fa;
+    int nb, bc, fa, cu;
     WmLaunch fn;
 };
 extern const WmVariant kWmVariants[];

@@ -388,6 +388,7 @@ static const WmVariant *pick_variant(const bwg_net *n)
         const WmVariant &v = kWmVariants[i];
         if (v.nb < b || v.bc < need_bc) continue;
         if (v.fa >= 0 && !(same && v.fa == f_common && f_common >= 0)) continue;
+        if (v.cu >= 0 && (uint32_t)v.cu != n->shape.cu) continue;
         if (fa >= v.bc || fi >= v.bc) continue;
         if (!best) {
             best = &v;

@@ -83,9 +83,12 @@ __device__ __forceinline__ uint32_t lane_mask(const uint64_t *E, const uint64_t 
     return m;
 }
 
-template <int NB, int BC, int FA>
+// NB count planes, BC = 4 * (quads of threshold planes), FA product shift
+// (-1: run time), CU unimolecular weight (-1: run time).
+template <int NB, int BC, int FA, int CU>
 __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
 {
+    static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
     constexpr int WP = 2 * NB - 2 > 1 ? 2 * NB - 2 : 2;   // product planes
     constexpr int WD = NB + 2;                             // product-delta planes
     const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
         uint32_t U[BC];
 #pragma unroll
         for (int q = 0; q < BC; ++q) U[q] = 0;
-        const uint32_t cu = a.cu;
+        const uint32_t cu = CU >= 0 ? (uint32_t)CU : a.cu;
 #pragma unroll
         for (int k = 0; k < BC; ++k) {
             if ((cu >> k) & 1u) {
@@ -150,24 +153,36 @@ __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
         const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
         const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
         const uint32_t G = (uint32_t)w;
+        // threshold planes in use: nq quads, the last one masked to plane B-1
+        const int nq = (a.B + 3) / 4;
+        uint32_t lastm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
         uint64_t nreal = 0;
 
         for (uint64_t e = lo; e < hi; ++e) {
             const uint32_t act = (e >= blo && e < bhi) ? pend : lane_mask(E, T, pend, e);
 
-            // (a) threshold planes
+            // (a) threshold planes: plane q is output q mod 4 of the Philox
+            // call with plane-quad q / 4; planes at or above B are zero
             uint32_t n[BC];
             const uint32_t e_lo = (uint32_t)e, e_hi = (uint32_t)(e >> 32) & 0xFFFFu;
 #pragma unroll
             for (int q4 = 0; q4 < BC / 4; ++q4) {
                 uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-                if (4 * q4 < a.B)
+                if (q4 < nq)
                     philox4x32_10(e_lo, (DOM_EVENT << 24) | ((uint32_t)q4 << 16) | e_hi, G,
                                   a.net_id, k0, k1, o0, o1, o2, o3);
-                n[4 * q4 + 0] = (4 * q4 + 0 < a.B) ? o0 : 0u;
-                n[4 * q4 + 1] = (4 * q4 + 1 < a.B) ? o1 : 0u;
-                n[4 * q4 + 2] = (4 * q4 + 2 < a.B) ? o2 : 0u;
-                n[4 * q4 + 3] = (4 * q4 + 3 < a.B) ? o3 : 0u;
+                if (q4 == nq - 1) {
+                    o0 &= lastm[0];
+                    o1 &= lastm[1];
+                    o2 &= lastm[2];
+                    o3 &= lastm[3];
+                }
+                n[4 * q4 + 0] = o0;
+                n[4 * q4 + 1] = o1;
+                n[4 * q4 + 2] = o2;
+                n[4 * q4 + 3] = o3;
             }
 
             // (b)-(d) cumulative weights and first crossing
@@ -255,16 +270,25 @@ __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
                     add_sext<WP, WD>(PLD, t, mI);
                 }
             }
-            // U += cu * dA with dA = -1 on mLD, +2 on mI
+            // U += cu * dA with dA = -1 on mLD, +2 on mI: addend planes are the
+            // bits of -cu (two's complement, the +1 as carry-in) on mLD and of
+            // 2 cu on mI
             if (cu) {
                 uint32_t c = mLD;
 #pragma unroll
                 for (int q = 0; q < BC; ++q) {
-                    const uint32_t neg = ((cu >> q) & 1u) ? 0u : mLD;   // bits of ~cu
-                    const uint32_t dbl = (q >= 1 && ((cu >> (q - 1)) & 1u)) ? mI : 0u;
-                    const uint32_t v = neg | dbl;
+                    uint32_t v;
+                    if constexpr (CU >= 0) {
+                        constexpr uint32_t ncu = ~(uint32_t)CU, dcu = 2u * (uint32_t)CU;
+                        const bool bn = (ncu >> q) & 1u, bd = (dcu >> q) & 1u;
+                        v = bn ? (bd ? (mLD | mI) : mLD) : (bd ? mI : 0u);
+                    } else {
+                        const uint32_t neg = ((cu >> q) & 1u) ? 0u : mLD;
+                        const uint32_t dbl = (q >= 1 && ((cu >> (q - 1)) & 1u)) ? mI : 0u;
+                        v = neg | dbl;
+                    }
                     const uint32_t s = BWG_OP3(U[q], v, c, L_XOR3);
-                    c = BWG_OP3(U[q], v, c, L_MAJ);
+                    if (q + 1 < BC) c = BWG_OP3(U[q], v, c, L_MAJ);
                     U[q] = s;
                 }
             }
@@ -294,35 +318,37 @@ __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
     }
 }
 
-template <int NB, int BC, int FA>
+template <int NB, int BC, int FA, int CU>
 hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
 {
     if (block <= 0) block = 128;
     const uint64_t grid = (a.n_words + block - 1) / block;
-    hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA>), dim3((uint32_t)grid), dim3(block), 0, s,
-                       a);
+    hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU>), dim3((uint32_t)grid), dim3(block), 0,
+                       s, a);
     return hipGetLastError();
 }
 
 // Kernel instantiations (both compilation passes) and the host-side table.
+// (NB, BC, FA, CU): FA/CU = -1 are taken at run time.
 #define BWG_WM_VARIANTS(X)                                                    \
-    /* specialised shifts of the named workloads */                          \
-    X(6, 20, 9)    /* N_tot = 32, k0 = 0.01, k1 = k2 = 1/32 */               \
-    X(11, 24, 4)   /* N_tot = 1024 */                                         \
-    X(6, 12, 0)    /* paper network, N_tot <= 63 */                           \
-    /* run-time shifts, any Frank-family network within the plane budget */   \
-    X(4, 20, -1)                                                              \
-    X(6, 20, -1)                                                              \
-    X(8, 24, -1)                                                              \
-    X(10, 24, -1)                                                             \
-    X(12, 28, -1)                                                             \
-    X(14, 32, -1)
+    /* compile-time shift and weight of the named workloads */               \
+    X(6, 20, 9, 164)   /* N_tot = 32, k0 = 0.01, k1 = k2 = 1/32 */           \
+    X(11, 24, 4, 164)  /* N_tot = 1024 */                                     \
+    X(6, 12, 0, 0)     /* paper network, N_tot <= 63 */                       \
+    /* run-time shifts and weights, any Frank-family network in budget */     \
+    X(4, 20, -1, -1)                                                          \
+    X(6, 20, -1, -1)                                                          \
+    X(8, 24, -1, -1)                                                          \
+    X(10, 24, -1, -1)                                                         \
+    X(12, 28, -1, -1)                                                         \
+    X(14, 32, -1, -1)
 
-#define BWG_WM_INST(nb, bc, fa) template __global__ void wm_event_kernel<nb, bc, fa>(WmArgs);
+#define BWG_WM_INST(nb, bc, fa, cu) \
+    template __global__ void wm_event_kernel<nb, bc, fa, cu>(WmArgs);
 BWG_WM_VARIANTS(BWG_WM_INST)
 
 #ifndef __HIP_DEVICE_COMPILE__
-#define BWG_WM_ENTRY(nb, bc, fa) {nb, bc, fa, &launch_wm<nb, bc, fa>},
+#define BWG_WM_ENTRY(nb, bc, fa, cu) {nb, bc, fa, cu, &launch_wm<nb, bc, fa, cu>},
 const WmVariant kWmVariants[] = {BWG_WM_VARIANTS(BWG_WM_ENTRY)};
 const int kWmVariantCount = sizeof(kWmVariants) / sizeof(kWmVariants[0]);
 #endif
