@@ -46,6 +46,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=65536)
+    ap.add_argument("--workload", default="well-mixed", choices=["well-mixed", "batch"],
+                    help="batch: the 256 uneven networks in one persistent launch")
+    ap.add_argument("--batch-nets", type=int, default=256)
+    ap.add_argument("--compare-nets", type=int, default=32,
+                    help="networks for the one-network-per-launch comparison")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -65,6 +70,8 @@ def main():
         return
     import paper_2412_16613_amd as bwg
     from workloads import config
+    if args.workload == "batch":
+        return bench_batch(args)
 
     c = config("c1")
     net, M, t_end = c["net"], c["replicas"], c["t_end"]
@@ -154,6 +161,77 @@ def main():
                             "bitwise_over_plain": value / pv}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, c, args.cpu_replicas)
+    print(json.dumps(out))
+
+
+def bench_batch(args):
+    """Uneven batch: 256 Frank networks (N_tot log-uniform 16..4096, replicas
+    log-uniform 2^10..2^18, k0 uniform 1e-3..1e-1, t_end uniform 10..200) in
+    one persistent launch, against the same networks one launch each (plain
+    engine and bit-sliced engine)."""
+    import torch
+    import paper_2412_16613_amd as bwg
+    from paper_2412_16613_amd import tune
+    from workloads import batch_networks
+
+    cfg = batch_networks()[: args.batch_nets]
+    items = [(c["net"], c["replicas"], c["t_end"]) for c in cfg]
+    nets = [bwg.Network(c["net"]) for c in cfg]
+    waves, order, timings = tune.tune(items)
+
+    def make(engine, sub):
+        ens = []
+        for k, c in enumerate(sub):
+            e = bwg.Ensemble(nets[k], c["replicas"], seed=c["seed"], net_id=c["net_id"],
+                             engine=engine)
+            e.init(c["init"])
+            ens.append(e)
+        return ens
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    res = {}
+
+    def run_batched(sub, tag):
+        ens = make("bitwise", sub)
+        batch = bwg.Batch(ens, waves=waves, order=order)
+        dt = timed(lambda: batch.advance([c["t_end"] for c in sub]))
+        ev = sum(e.stats()["events_total"] for e in ens)
+        res[tag] = {"s": dt, "replica_events_per_s": ev / dt, "networks": len(sub)}
+        return ev
+
+    events = run_batched(cfg, "batched")
+    sub = cfg[: args.compare_nets]
+    ev_sub = run_batched(sub, "batched_subset")
+    for engine in ("bitwise", "plain"):
+        ens = make(engine, sub)
+        dt = timed(lambda: [e.advance(c["t_end"]) for e, c in zip(ens, sub)])
+        ev = sum(e.stats()["events_total"] for e in ens)
+        assert ev == ev_sub
+        res["one_per_launch_" + engine] = {"s": dt, "replica_events_per_s": ev / dt,
+                                           "networks": len(sub)}
+        del ens
+    out = {"metric": "replica-events/sec (batched persistent vs one network per launch, 1 GPU)",
+           "value": res["batched"]["replica_events_per_s"], "unit": "replica-events/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "u32 bit-planes",
+           "data": "synthetic",
+           "config": {"workload": "uneven batch of %d Frank networks" % len(cfg),
+                      "replica_events": events, "waves": waves, "order": order},
+           "tuning_s": timings, "results": res,
+           "speedup_vs_plain_one_per_launch":
+               res["batched_subset"]["replica_events_per_s"] /
+               res["one_per_launch_plain"]["replica_events_per_s"],
+           "speedup_vs_bitwise_one_per_launch":
+               res["batched_subset"]["replica_events_per_s"] /
+               res["one_per_launch_bitwise"]["replica_events_per_s"]}
     print(json.dumps(out))
 
 

@@ -190,6 +190,41 @@ int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);
 
 void bwg_ensemble_destroy(bwg_ens *ens);
 
+/* ---- batches: many ensembles in one persistent launch ------------------- */
+
+typedef struct bwg_batch bwg_batch;
+
+typedef struct {
+    int32_t waves;        /* persistent grid in wavefronts, 0 = default (2048) */
+    int32_t order;        /* 0: longest work items first, 1: in ensemble order */
+    uint64_t reserved[4];
+} bwg_batch_opts;
+
+/* Device bytes the batch bookkeeping needs (queue, descriptors). */
+int bwg_batch_state_bytes(bwg_ens *const *ens, int32_t n, uint64_t *bytes);
+
+/* Group n bit-sliced ensembles (distinct, possibly of different networks,
+ * sizes and plane widths) so that one launch advances all of them.  The
+ * ensembles stay usable on their own.  Synchronises the stream once.
+ * EUNSUPPORTED if an ensemble's planes fit no bucket of the persistent
+ * kernel. */
+int bwg_batch_create(bwg_ens *const *ens, int32_t n, void *dev_buf, uint64_t buf_bytes,
+                     const bwg_batch_opts *opts, void *stream, bwg_batch **out);
+
+/* Advance ensemble k to t_end[k] (host array of n).  Every replica's result
+ * is identical to a bwg_ensemble_advance of its ensemble alone: the draws are
+ * keyed by (seed, net_id, replica, event), not by launch or order.  Async. */
+int bwg_batch_advance(bwg_batch *b, const double *t_end, void *stream);
+
+/* Capture one advance of every ensemble by dt into a HIP graph and replay it
+ * n_steps times (the advance index lives on the device, so each replay draws
+ * new budgets).  EINVAL unless t + dt - t == dt exactly in binary64 for every
+ * step of every ensemble (each replay then has the same Poisson mean).
+ * Synchronises the stream at the end. */
+int bwg_batch_graph_advance(bwg_batch *b, double dt, int32_t n_steps, void *stream);
+
+void bwg_batch_destroy(bwg_batch *b);
+
 const char *bwg_last_error(void);
 
 #ifdef __cplusplus

@@ -189,3 +189,54 @@ class Ensemble:
             except Exception:
                 pass
             self.handle = None
+
+
+class Batch:
+    """Several bit-sliced ensembles advanced by one persistent launch."""
+
+    def __init__(self, ensembles, waves=0, order=0):
+        import torch
+        self.torch = torch
+        L = _lib()
+        self.ensembles = list(ensembles)
+        n = len(self.ensembles)
+        hs = (ctypes.c_void_p * n)(*[e.handle.value for e in self.ensembles])
+        self._hs = hs
+        nbytes = ctypes.c_uint64()
+        _abi.check(L.bwg_batch_state_bytes(hs, n, ctypes.byref(nbytes)))
+        dev = self.ensembles[0].device
+        self.device = dev
+        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        base = self._buf.data_ptr()
+        off = (-base) % 256
+        o = _abi.BatchOpts()
+        o.waves = int(waves)
+        o.order = int(order)
+        h = ctypes.c_void_p()
+        _abi.check(L.bwg_batch_create(hs, n, ctypes.c_void_p(base + off), nbytes.value,
+                                      ctypes.byref(o), self._stream(), ctypes.byref(h)))
+        self.handle = h
+
+    def _stream(self):
+        return _stream_ptr(self.torch.cuda.current_stream(self.device))
+
+    def advance(self, t_end):
+        if not hasattr(t_end, "__len__"):
+            t_end = [t_end] * len(self.ensembles)
+        arr = (ctypes.c_double * len(self.ensembles))(*[float(t) for t in t_end])
+        _abi.check(_lib().bwg_batch_advance(self.handle, arr, self._stream()))
+        return self
+
+    def graph_advance(self, dt, n_steps):
+        _abi.check(_lib().bwg_batch_graph_advance(self.handle, float(dt), int(n_steps),
+                                                  self._stream()))
+        return self
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _lib().bwg_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None

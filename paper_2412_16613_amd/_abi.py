@@ -29,7 +29,8 @@ SYMBOLS = (
     "bwg_ensemble_state_bytes", "bwg_ensemble_create", "bwg_ensemble_init",
     "bwg_ensemble_advance", "bwg_ensemble_step", "bwg_ensemble_read_counts",
     "bwg_ensemble_histogram", "bwg_ensemble_read_events", "bwg_ensemble_stats",
-    "bwg_ensemble_destroy", "bwg_last_error",
+    "bwg_ensemble_destroy", "bwg_last_error", "bwg_batch_state_bytes", "bwg_batch_create",
+    "bwg_batch_advance", "bwg_batch_graph_advance", "bwg_batch_destroy",
 )
 
 
@@ -62,6 +63,11 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_replicas", ctypes.c_uint64), ("advance_index", ctypes.c_uint64),
                 ("t_now", ctypes.c_double), ("events_total", ctypes.c_uint64),
                 ("real_total", ctypes.c_uint64)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("reserved", ctypes.c_uint64 * 4)]
 
 
 class BwgError(RuntimeError):
@@ -100,6 +106,11 @@ def load():
         "bwg_ensemble_stats": (i32, [vp, vp, P(Stats)]),
         "bwg_ensemble_destroy": (None, [vp]),
         "bwg_last_error": (ctypes.c_char_p, []),
+        "bwg_batch_state_bytes": (i32, [P(vp), i32, P(u64)]),
+        "bwg_batch_create": (i32, [P(vp), i32, vp, u64, P(BatchOpts), vp, P(vp)]),
+        "bwg_batch_advance": (i32, [vp, P(ctypes.c_double), vp]),
+        "bwg_batch_graph_advance": (i32, [vp, ctypes.c_double, i32, vp]),
+        "bwg_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

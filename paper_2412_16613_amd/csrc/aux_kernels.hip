@@ -79,30 +79,42 @@ __global__ void init_multinomial_kernel(uint32_t *planes, int nb, uint64_t wp, u
 
 // Etgt[i] = E[i] + K_i with K_i = k_lo + #{j : T[j] <= u_i} (u_i the BUDGET
 // draw of replica i for this advance) or the fixed count.
+__device__ __forceinline__ uint64_t draw_budget(const uint64_t *T, uint64_t len, int64_t k_lo,
+                                                uint64_t seed, uint32_t net_id, uint64_t adv,
+                                                uint64_t i)
+{
+    uint32_t o0, o1, o2, o3;
+    philox4x32_10((uint32_t)adv, (DOM_BUDGET << 24) | ((uint32_t)(adv >> 32) & 0xFFFFu),
+                  (uint32_t)i, net_id, (uint32_t)seed, (uint32_t)(seed >> 32), o0, o1, o2, o3);
+    const uint64_t u = (uint64_t)o0 | ((uint64_t)o1 << 32);
+    uint64_t lo = 0, hi = len;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (T[mid] <= u)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (uint64_t)(k_lo + (int64_t)lo);
+}
+
+// The advance index is read from device memory so that a captured graph of
+// an advance draws new budgets on every replay.
 __global__ void budget_kernel(const uint64_t *T, uint64_t len, int64_t k_lo, uint64_t fixed_k,
-                              int use_table, uint64_t seed, uint32_t net_id, uint64_t adv,
-                              uint64_t M, const uint64_t *E, uint64_t *Et)
+                              int use_table, uint64_t seed, uint32_t net_id,
+                              const uint64_t *adv_dev, uint64_t M, const uint64_t *E,
+                              uint64_t *Et)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     uint64_t K = fixed_k;
-    if (use_table) {
-        uint32_t o0, o1, o2, o3;
-        philox4x32_10((uint32_t)adv, (DOM_BUDGET << 24) | ((uint32_t)(adv >> 32) & 0xFFFFu),
-                      (uint32_t)i, net_id, (uint32_t)seed, (uint32_t)(seed >> 32), o0, o1, o2,
-                      o3);
-        const uint64_t u = (uint64_t)o0 | ((uint64_t)o1 << 32);
-        uint64_t lo = 0, hi = len;
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (T[mid] <= u)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        K = (uint64_t)(k_lo + (int64_t)lo);
-    }
+    if (use_table) K = draw_budget(T, len, k_lo, seed, net_id, *adv_dev, i);
     Et[i] = E[i] + K;
+}
+
+__global__ void add_u64_kernel(uint64_t *p, uint64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] += v;
 }
 
 // ---- readouts ----------------------------------------------------------------
@@ -218,11 +230,24 @@ hipError_t launch_init_multinomial(uint32_t *planes, int nb, uint64_t wp, uint64
 }
 
 hipError_t launch_budget(const uint64_t *T, uint64_t len, int64_t k_lo, uint64_t fixed_k,
-                         int use_table, uint64_t seed, uint32_t net_id, uint64_t adv,
+                         int use_table, uint64_t seed, uint32_t net_id, const uint64_t *adv_dev,
                          uint64_t M, const uint64_t *E, uint64_t *Et, hipStream_t s)
 {
     hipLaunchKernelGGL(budget_kernel, grid_for(M, 256), dim3(256), 0, s, T, len, k_lo,
-                       fixed_k, use_table, seed, net_id, adv, M, E, Et);
+                       fixed_k, use_table, seed, net_id, adv_dev, M, E, Et);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_u64(uint64_t *p, uint64_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(add_u64_kernel, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, grid_for(n, 256), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

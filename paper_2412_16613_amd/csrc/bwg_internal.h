@@ -33,7 +33,7 @@ struct PlainReaction {
 };
 
 struct WmArgs {
-    uint32_t *planes;       // [3][NB][wp] words, species (L, D, A)
+    uint32_t *planes;       // [3][nb_mem][wp] words, species (L, D, A)
     uint64_t *E;            // [32 wp] events done per replica
     uint64_t *Etgt;         // [32 wp] events to reach in this advance
     uint64_t *real;         // [wp] real events per 32-lane group
@@ -46,6 +46,8 @@ struct WmArgs {
     int32_t B;              // threshold planes (runtime, <= BC)
     uint32_t cu;
     int32_t fa, fi;
+    int32_t nb_mem;         // count planes per species in memory (<= NB)
+    int32_t pad;
 };
 
 struct PlainArgs {
@@ -76,6 +78,40 @@ extern const int kWmVariantCount;
 
 hipError_t launch_plain(const PlainArgs &a, hipStream_t s, int block);
 
+// ---- batches ----
+struct BatchEns {
+    WmArgs a;
+    int32_t variant;        // persistent-kernel plane bucket
+    int32_t pad;
+};
+struct BatchItem {
+    uint32_t ens;           // index into the BatchEns array
+    uint32_t word0;         // first of 64 words
+};
+struct BatchBudget {
+    const uint64_t *T;      // Poisson table on the device (len 0: no events)
+    uint64_t len;
+    int64_t k_lo;
+    uint64_t seed;
+    uint64_t offset;        // first global replica of this ensemble
+    uint64_t *adv;          // advance index (device)
+    const uint64_t *E;
+    uint64_t *Et;
+    uint32_t net_id;
+    uint32_t pad;
+};
+struct PersistVariant {
+    int id, nb, bc;
+};
+extern const PersistVariant kPersistVariants[];
+extern const int kPersistVariantCount;
+
+hipError_t launch_persistent(const BatchEns *ens, const BatchItem *items, uint32_t n_items,
+                             uint32_t *counter, int waves, hipStream_t s);
+hipError_t launch_batch_budget(const BatchBudget *bb, int n_ens, uint64_t total, hipStream_t s);
+hipError_t launch_batch_prologue(uint32_t *counter, hipStream_t s);
+hipError_t launch_batch_epilogue(const BatchBudget *bb, int n_ens, hipStream_t s);
+
 hipError_t launch_init_fixed(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
                              const int32_t counts[3], uint64_t *E, uint64_t *Etgt,
                              uint64_t *real, hipStream_t s);
@@ -88,8 +124,10 @@ hipError_t launch_plain_init(int32_t *counts, uint64_t M, int mode, const int32_
                              uint64_t *E, uint64_t *Etgt, uint64_t *real, hipStream_t s);
 hipError_t launch_budget(const uint64_t *table, uint64_t len, int64_t k_lo,
                          uint64_t fixed_k, int use_table, uint64_t seed,
-                         uint32_t net_id, uint64_t advance, uint64_t M,
+                         uint32_t net_id, const uint64_t *advance_dev, uint64_t M,
                          const uint64_t *E, uint64_t *Etgt, hipStream_t s);
+hipError_t launch_add_u64(uint64_t *p, uint64_t v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_read_counts_planes(const uint32_t *planes, int nb, uint64_t wp,
                                      uint64_t M, int32_t *dst, hipStream_t s);
 hipError_t launch_read_counts_plain(const int32_t *counts, uint64_t M, int32_t *dst,

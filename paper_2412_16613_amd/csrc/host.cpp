@@ -14,6 +14,7 @@
 
 #include "bwg.h"
 #include "bwg_internal.h"
+#include "host_internal.h"
 
 namespace bwg {
 int poisson_table_q(double mu, int64_t *k_lo, std::vector<uint64_t> &T);
@@ -23,9 +24,10 @@ using namespace bwg;
 
 // ---- errors ------------------------------------------------------------------
 
+namespace bwg {
 static thread_local std::string g_err;
 
-static int fail(int code, const char *fmt, ...)
+int fail(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -35,43 +37,11 @@ static int fail(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
-
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(BWG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));         \
-    } while (0)
+}  // namespace bwg
 
 extern "C" const char *bwg_last_error(void) { return g_err.c_str(); }
 
 // ---- networks ------------------------------------------------------------------
-
-struct Table {
-    int64_t k_lo;
-    uint64_t len;
-    uint64_t *host;  // pinned; lives as long as the network
-};
-
-struct bwg_net {
-    int S = 0, R = 0;
-    std::vector<int32_t> reac, prod;
-    std::vector<double> rates;
-    int64_t n_tot = 0;
-    int32_t lx = 0, ly = 0;
-    bwg_qnet q{};
-    FrankShape shape{};
-    bool shape_ok = false;
-    PlainReaction prx[16]{};
-    bool plain_ok = false;
-    std::mutex mu;
-    std::map<uint64_t, Table> tables;  // keyed by the bits of mu
-    ~bwg_net()
-    {
-        for (auto &kv : tables)
-            if (kv.second.host) (void)hipHostFree(kv.second.host);
-    }
-};
 
 static int64_t comb_h(const int32_t *r, const int64_t *N, int S)
 {
@@ -328,7 +298,7 @@ extern "C" int bwg_poisson_table(double mu, int64_t *k_lo, uint64_t *table, uint
 }
 
 // Cached pinned copy of the table for mean mu.
-static int get_table(bwg_net *n, double mu, const Table **out)
+int bwg::get_table(bwg_net *n, double mu, const Table **out)
 {
     uint64_t key;
     memcpy(&key, &mu, sizeof key);
@@ -348,26 +318,6 @@ static int get_table(bwg_net *n, double mu, const Table **out)
 }
 
 // ---- ensembles ------------------------------------------------------------------
-
-struct bwg_ens {
-    bwg_net *net = nullptr;
-    uint64_t M = 0, seed = 0;
-    uint32_t net_id = 0;
-    int engine = 0, block = 0;
-    uint64_t table_cap = 0, epl = 0;
-    uint8_t *buf = nullptr;
-    uint64_t bytes = 0;
-    uint64_t wp = 0;
-    int nb = 0;
-    const WmVariant *var = nullptr;
-    uint32_t *planes = nullptr;
-    int32_t *counts = nullptr;
-    uint64_t *E = nullptr, *Et = nullptr, *real = nullptr, *table = nullptr, *scratch = nullptr;
-    double t_now = 0;
-    uint64_t adv = 0;
-    uint64_t lag = 0;      // bound on how far a word's lanes can be apart
-    bool inited = false;
-};
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
@@ -415,7 +365,7 @@ static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_ca
     uint64_t off = 0;
     if (engine == BWG_ENGINE_BITWISE) {
         L.planes = off;
-        off = align256(off + 3ull * (uint64_t)v->nb * L.wp * 4);
+        off = align256(off + 3ull * (uint64_t)n->q.b * L.wp * 4);
         L.counts = ~0ull;
     } else {
         L.counts = off;
@@ -498,7 +448,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
     e->wp = L.wp;
-    e->nb = e->var ? e->var->nb : 0;
+    e->nb = n->q.b;  // planes per species in memory
     if (e->engine == BWG_ENGINE_BITWISE)
         e->planes = (uint32_t *)(e->buf + L.planes);
     else
@@ -508,6 +458,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->real = (uint64_t *)(e->buf + L.real);
     e->table = (uint64_t *)(e->buf + L.table);
     e->scratch = (uint64_t *)(e->buf + L.scratch);
+    e->adv_dev = e->scratch + 8;
     *out = e;
     return BWG_OK;
 }
@@ -544,6 +495,7 @@ extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts
         HIP_TRY(launch_plain_init(e->counts, 32 * e->wp, mode == BWG_INIT_FIXED ? 0 : 1, c,
                                   n->n_tot, e->seed, e->net_id, e->E, e->Et, e->real, s));
     }
+    HIP_TRY(launch_fill_u64(e->adv_dev, 1, 0, s));
     e->t_now = 0;
     e->adv = 0;
     e->lag = 0;
@@ -579,6 +531,7 @@ static int run_events(bwg_ens *e, uint64_t k_min, uint64_t k_max, hipStream_t s)
             a.cu = n->shape.cu;
             a.fa = n->shape.fa;
             a.fi = n->shape.fi;
+            a.nb_mem = e->nb;
             HIP_TRY(e->var->fn(a, s, e->block));
         } else {
             PlainArgs a{};
@@ -616,14 +569,15 @@ extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
             return fail(BWG_ERANGE, "Poisson table of %llu entries exceeds capacity %llu",
                         (unsigned long long)t->len, (unsigned long long)e->table_cap);
         HIP_TRY(hipMemcpyAsync(e->table, t->host, t->len * 8, hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_budget(e->table, t->len, t->k_lo, 0, 1, e->seed, e->net_id, e->adv, e->M,
-                              e->E, e->Et, s));
+        HIP_TRY(launch_budget(e->table, t->len, t->k_lo, 0, 1, e->seed, e->net_id, e->adv_dev,
+                              e->M, e->E, e->Et, s));
         kmin = (uint64_t)t->k_lo;
         kmax = (uint64_t)t->k_lo + t->len;
     } else {
-        HIP_TRY(launch_budget(nullptr, 0, 0, 0, 0, e->seed, e->net_id, e->adv, e->M, e->E, e->Et,
-                              s));
+        HIP_TRY(launch_budget(nullptr, 0, 0, 0, 0, e->seed, e->net_id, e->adv_dev, e->M, e->E,
+                              e->Et, s));
     }
+    HIP_TRY(launch_add_u64(e->adv_dev, 1, s));
     int rc = run_events(e, kmin, kmax, s);
     if (rc) return rc;
     e->t_now = t_end;
@@ -636,7 +590,8 @@ extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_budget(nullptr, 0, 0, n_events, 0, e->seed, e->net_id, 0, e->M, e->E, e->Et, s));
+    HIP_TRY(launch_budget(nullptr, 0, 0, n_events, 0, e->seed, e->net_id, e->adv_dev, e->M, e->E,
+                          e->Et, s));
     return run_events(e, n_events, n_events, s);
 }
 

@@ -1,0 +1,80 @@
+// Host-side structures shared by the C-ABI sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bwg.h"
+#include "bwg_internal.h"
+
+namespace bwg {
+
+int fail(int code, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::bwg::fail(BWG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+}  // namespace bwg
+
+struct Table {  // Poisson table of one mean
+    int64_t k_lo;
+    uint64_t len;
+    uint64_t *host;  // pinned; lives as long as the network
+};
+
+struct bwg_net {
+    int S = 0, R = 0;
+    std::vector<int32_t> reac, prod;
+    std::vector<double> rates;
+    int64_t n_tot = 0;
+    int32_t lx = 0, ly = 0;
+    bwg_qnet q{};
+    bwg::FrankShape shape{};
+    bool shape_ok = false;
+    bwg::PlainReaction prx[16]{};
+    bool plain_ok = false;
+    std::mutex mu;
+    std::map<uint64_t, Table> tables;  // keyed by the bits of mu
+    ~bwg_net()
+    {
+        for (auto &kv : tables)
+            if (kv.second.host) (void)hipHostFree(kv.second.host);
+    }
+};
+
+struct bwg_ens {
+    bwg_net *net = nullptr;
+    uint64_t M = 0, seed = 0;
+    uint32_t net_id = 0;
+    int engine = 0, block = 0;
+    uint64_t table_cap = 0, epl = 0;
+    uint8_t *buf = nullptr;
+    uint64_t bytes = 0;
+    uint64_t wp = 0;
+    int nb = 0;
+    const bwg::WmVariant *var = nullptr;
+    uint32_t *planes = nullptr;
+    int32_t *counts = nullptr;
+    uint64_t *E = nullptr, *Et = nullptr, *real = nullptr, *table = nullptr, *scratch = nullptr;
+    uint64_t *adv_dev = nullptr;  // advance index on the device (scratch slot 8)
+    double t_now = 0;
+    uint64_t adv = 0;
+    uint64_t lag = 0;      // bound on how far a word's lanes can be apart
+    bool inited = false;
+};
+
+
+namespace bwg {
+// Cached pinned Poisson table for mean mu (lives as long as the network).
+int get_table(bwg_net *n, double mu, const Table **out);
+}
