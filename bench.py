@@ -46,9 +46,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=65536)
-    ap.add_argument("--workload", default="well-mixed", choices=["well-mixed", "batch"],
+    ap.add_argument("--workload", default="well-mixed", choices=["well-mixed", "batch", "serve"],
                     help="batch: the 256 uneven networks in one persistent launch")
     ap.add_argument("--batch-nets", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
+    ap.add_argument("--chunk", type=int, default=4096, help="serve: events per word per pass")
     ap.add_argument("--compare-nets", type=int, default=32,
                     help="networks for the one-network-per-launch comparison")
     ap.add_argument("--copy-ref", action="store_true",
@@ -72,6 +75,8 @@ def main():
     from workloads import config
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     c = config("c1")
     net, M, t_end = c["net"], c["replicas"], c["t_end"]
@@ -232,6 +237,28 @@ def bench_batch(args):
            "speedup_vs_bitwise_one_per_launch":
                res["batched_subset"]["replica_events_per_s"] /
                res["one_per_launch_bitwise"]["replica_events_per_s"]}
+    print(json.dumps(out))
+
+
+def bench_serve(args):
+    """Served stream: Poisson arrivals (200/s for 60 s by default) of Frank
+    networks drawn like the uneven batch, admitted by HBM budget into one
+    continuously batched persistent launch; p50/p99 latency and throughput."""
+    from paper_2412_16613_amd.serve import Server, summarize
+    from workloads import serve_requests
+    reqs = [r for r in serve_requests(rate=args.rate, duration=args.duration)
+            if not r["net"].get("lx")]
+    srv = Server(chunk=args.chunk)
+    res = srv.serve(reqs, real_time=True)
+    s = summarize(res, srv.stats)
+    out = {"metric": "p50/p99 request latency and replica-events/sec (served stream, 1 GPU)",
+           "value": s["replica_events_per_s"], "unit": "replica-events/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "u32 bit-planes", "data": "synthetic",
+           "config": {"workload": "Poisson arrivals %.0f/s for %.0f s, well-mixed requests"
+                                  % (args.rate, args.duration),
+                      "requests": len(reqs), "chunk_events": args.chunk},
+           "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
+           "summary": s}
     print(json.dumps(out))
 
 

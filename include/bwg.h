@@ -166,6 +166,20 @@ int bwg_ensemble_init(bwg_ens *ens, int32_t mode, const int32_t *counts,
  * Poisson table exceeds the table capacity.  Async. */
 int bwg_ensemble_advance(bwg_ens *ens, double t_end, void *stream);
 
+/* The two halves of an advance, for callers that interleave the events of
+ * many ensembles (continuous batching): bwg_ensemble_schedule draws every
+ * replica's event budget for an advance to t_end (and moves t_now to t_end)
+ * without running events; bwg_ensemble_run runs pending events, at most
+ * max_events per word (0: all).  Splitting an advance this way, and running
+ * it in any number of capped passes, gives the same result as
+ * bwg_ensemble_advance.  Async. */
+int bwg_ensemble_schedule(bwg_ens *ens, double t_end, void *stream);
+int bwg_ensemble_run(bwg_ens *ens, uint64_t max_events, void *stream);
+
+/* Host-side upper bound on the events any word still has to run (0 once
+ * every scheduled event has been launched).  No device work, no sync. */
+int bwg_ensemble_pending(const bwg_ens *ens, uint64_t *bound);
+
 /* Run exactly n_events more events in every replica, without time (the
  * paper's fixed number of iterations, Sec. 5).  Async. */
 int bwg_ensemble_step(bwg_ens *ens, uint64_t n_events, void *stream);
@@ -195,13 +209,18 @@ void bwg_ensemble_destroy(bwg_ens *ens);
 typedef struct bwg_batch bwg_batch;
 
 typedef struct {
-    int32_t waves;        /* persistent grid in wavefronts, 0 = default (2048) */
-    int32_t order;        /* 0: longest work items first, 1: in ensemble order */
-    uint64_t reserved[4];
+    int32_t waves;          /* persistent grid in wavefronts, 0 = default (2048)  */
+    int32_t order;          /* 0: longest pending work first, 1: member order     */
+    int32_t max_ensembles;  /* capacity for later member changes (0: initial n)   */
+    int32_t reserved0;
+    uint64_t max_items;     /* capacity in 64-word work items (0: initial)        */
+    uint64_t reserved[3];
 } bwg_batch_opts;
 
-/* Device bytes the batch bookkeeping needs (queue, descriptors). */
+/* Device bytes the batch bookkeeping needs (queue, descriptors) for exactly
+ * these members, or for a capacity of members and 64-word work items. */
 int bwg_batch_state_bytes(bwg_ens *const *ens, int32_t n, uint64_t *bytes);
+int bwg_batch_capacity_bytes(int32_t max_ensembles, uint64_t max_items, uint64_t *bytes);
 
 /* Group n bit-sliced ensembles (distinct, possibly of different networks,
  * sizes and plane widths) so that one launch advances all of them.  The
@@ -210,6 +229,14 @@ int bwg_batch_state_bytes(bwg_ens *const *ens, int32_t n, uint64_t *bytes);
  * kernel. */
 int bwg_batch_create(bwg_ens *const *ens, int32_t n, void *dev_buf, uint64_t buf_bytes,
                      const bwg_batch_opts *opts, void *stream, bwg_batch **out);
+
+/* Replace the members (within the capacity; ERANGE beyond it).  Members'
+ * scheduled but unrun events stay pending in the ensembles.  Async. */
+int bwg_batch_set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, void *stream);
+
+/* One persistent launch over every member's pending events, at most
+ * max_events per word (0: all).  Async. */
+int bwg_batch_run(bwg_batch *b, uint64_t max_events, void *stream);
 
 /* Advance ensemble k to t_end[k] (host array of n).  Every replica's result
  * is identical to a bwg_ensemble_advance of its ensemble alone: the draws are

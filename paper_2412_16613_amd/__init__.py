@@ -146,6 +146,21 @@ class Ensemble:
         _abi.check(_lib().bwg_ensemble_step(self.handle, int(n_events), self._stream()))
         return self
 
+    def schedule(self, t_end):
+        """Draw the budgets of an advance to t_end without running events."""
+        _abi.check(_lib().bwg_ensemble_schedule(self.handle, float(t_end), self._stream()))
+        return self
+
+    def run(self, max_events=0):
+        """Run pending events, at most max_events per word (0: all)."""
+        _abi.check(_lib().bwg_ensemble_run(self.handle, int(max_events), self._stream()))
+        return self
+
+    def pending(self):
+        b = ctypes.c_uint64()
+        _abi.check(_lib().bwg_ensemble_pending(self.handle, ctypes.byref(b)))
+        return b.value
+
     def read_counts(self, out=None):
         t = self.torch
         if out is None:
@@ -192,26 +207,38 @@ class Ensemble:
 
 
 class Batch:
-    """Several bit-sliced ensembles advanced by one persistent launch."""
+    """Several bit-sliced ensembles whose events run in one persistent launch.
 
-    def __init__(self, ensembles, waves=0, order=0):
+    With max_ensembles/max_items the batch keeps room for later member
+    changes (set_members), as a continuous-batching server needs."""
+
+    def __init__(self, ensembles, waves=0, order=0, max_ensembles=0, max_items=0,
+                 device=None):
         import torch
         self.torch = torch
         L = _lib()
         self.ensembles = list(ensembles)
         n = len(self.ensembles)
-        hs = (ctypes.c_void_p * n)(*[e.handle.value for e in self.ensembles])
-        self._hs = hs
+        hs = (ctypes.c_void_p * max(n, 1))(*[e.handle.value for e in self.ensembles])
         nbytes = ctypes.c_uint64()
-        _abi.check(L.bwg_batch_state_bytes(hs, n, ctypes.byref(nbytes)))
-        dev = self.ensembles[0].device
-        self.device = dev
-        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        if max_ensembles or max_items:
+            _abi.check(L.bwg_batch_capacity_bytes(max(max_ensembles, n), int(max_items),
+                                                  ctypes.byref(nbytes)))
+            need = ctypes.c_uint64()
+            _abi.check(L.bwg_batch_state_bytes(hs, n, ctypes.byref(need)))
+            nbytes.value = max(nbytes.value, need.value)
+        else:
+            _abi.check(L.bwg_batch_state_bytes(hs, n, ctypes.byref(nbytes)))
+        dev = device if device is not None else self.ensembles[0].device
+        self.device = torch.device(dev)
+        self._buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
         base = self._buf.data_ptr()
         off = (-base) % 256
         o = _abi.BatchOpts()
         o.waves = int(waves)
         o.order = int(order)
+        o.max_ensembles = int(max_ensembles)
+        o.max_items = int(max_items)
         h = ctypes.c_void_p()
         _abi.check(L.bwg_batch_create(hs, n, ctypes.c_void_p(base + off), nbytes.value,
                                       ctypes.byref(o), self._stream(), ctypes.byref(h)))
@@ -220,10 +247,21 @@ class Batch:
     def _stream(self):
         return _stream_ptr(self.torch.cuda.current_stream(self.device))
 
+    def set_members(self, ensembles):
+        self.ensembles = list(ensembles)
+        n = len(self.ensembles)
+        hs = (ctypes.c_void_p * max(n, 1))(*[e.handle.value for e in self.ensembles])
+        _abi.check(_lib().bwg_batch_set_members(self.handle, hs, n, self._stream()))
+        return self
+
+    def run(self, max_events=0):
+        _abi.check(_lib().bwg_batch_run(self.handle, int(max_events), self._stream()))
+        return self
+
     def advance(self, t_end):
         if not hasattr(t_end, "__len__"):
             t_end = [t_end] * len(self.ensembles)
-        arr = (ctypes.c_double * len(self.ensembles))(*[float(t) for t in t_end])
+        arr = (ctypes.c_double * max(len(self.ensembles), 1))(*[float(t) for t in t_end])
         _abi.check(_lib().bwg_batch_advance(self.handle, arr, self._stream()))
         return self
 

@@ -31,6 +31,8 @@ SYMBOLS = (
     "bwg_ensemble_histogram", "bwg_ensemble_read_events", "bwg_ensemble_stats",
     "bwg_ensemble_destroy", "bwg_last_error", "bwg_batch_state_bytes", "bwg_batch_create",
     "bwg_batch_advance", "bwg_batch_graph_advance", "bwg_batch_destroy",
+    "bwg_ensemble_schedule", "bwg_ensemble_run", "bwg_ensemble_pending",
+    "bwg_batch_capacity_bytes", "bwg_batch_set_members", "bwg_batch_run",
 )
 
 
@@ -67,7 +69,8 @@ class Stats(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("waves", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("reserved", ctypes.c_uint64 * 4)]
+                ("max_ensembles", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_items", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 3)]
 
 
 class BwgError(RuntimeError):
@@ -111,6 +114,12 @@ def load():
         "bwg_batch_advance": (i32, [vp, P(ctypes.c_double), vp]),
         "bwg_batch_graph_advance": (i32, [vp, ctypes.c_double, i32, vp]),
         "bwg_batch_destroy": (None, [vp]),
+        "bwg_ensemble_schedule": (i32, [vp, ctypes.c_double, vp]),
+        "bwg_ensemble_run": (i32, [vp, u64, vp]),
+        "bwg_ensemble_pending": (i32, [vp, P(u64)]),
+        "bwg_batch_capacity_bytes": (i32, [i32, u64, P(u64)]),
+        "bwg_batch_set_members": (i32, [vp, P(vp), i32, vp]),
+        "bwg_batch_run": (i32, [vp, u64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

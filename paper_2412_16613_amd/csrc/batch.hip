@@ -32,21 +32,23 @@ namespace bwg {
 // One out-of-line function per bucket, so that each gets its own register
 // allocation instead of the union of all of them.
 template <int NB, int BC>
-__device__ __noinline__ void wm_word_bucket(const WmArgs *ap, uint64_t w)
+__device__ __noinline__ void wm_word_bucket(const WmArgs *ap, uint64_t w, uint64_t max_events)
 {
-    const WmArgs a = *ap;
+    WmArgs a = *ap;
+    a.max_events = max_events;
     wm_word<NB, BC, -1, -1>(a, w);
 }
 
 #define BWG_PERSIST_CASE(id, nb, bc)        \
     case id:                                \
-        wm_word_bucket<nb, bc>(&ens[bi.ens].a, w); \
+        wm_word_bucket<nb, bc>(&ens[bi.ens].a, w, max_events); \
         break;
 
 __global__ __launch_bounds__(64, 2) void wm_persistent_kernel(const BatchEns *ens,
                                                               const BatchItem *items,
                                                               uint32_t n_items,
-                                                              uint32_t *counter)
+                                                              uint32_t *counter,
+                                                              uint64_t max_events)
 {
     for (;;) {
         uint32_t it = 0;
@@ -115,10 +117,10 @@ __global__ void batch_epilogue_kernel(const BatchBudget *bb, int n_ens)
 }
 
 hipError_t launch_persistent(const BatchEns *ens, const BatchItem *items, uint32_t n_items,
-                             uint32_t *counter, int waves, hipStream_t s)
+                             uint32_t *counter, int waves, uint64_t max_events, hipStream_t s)
 {
     hipLaunchKernelGGL(wm_persistent_kernel, dim3((uint32_t)waves), dim3(64), 0, s, ens, items,
-                       n_items, counter);
+                       n_items, counter, max_events);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
-// C ABI of batches: many ensembles advanced by one persistent launch, and a
-// graph of one batch advance replayed for repeated equal time steps.
+// C ABI of batches: many ensembles whose pending events run in one
+// persistent launch; membership can change between launches (continuous
+// batching), and one batch advance can be captured in a graph and replayed.
 
 #include <string.h>
 
@@ -13,17 +14,20 @@ using namespace bwg;
 
 struct bwg_batch {
     std::vector<bwg_ens *> ens;
-    std::vector<int> bucket;       // persistent-kernel plane bucket per ensemble
-    std::vector<double> cost;      // VALU cost of one event of a word, per ensemble
+    std::vector<int> bucket;       // persistent-kernel plane bucket per member
+    std::vector<double> cost;      // issue cost of one event of one word, per member
     int waves = 0;
     int order = 0;
-    uint64_t max_items = 0;
+    int cap_ens = 0;
+    uint64_t cap_items = 0;
+    uint64_t n_items = 0;          // items of the current members
     // device layout (caller buffer)
     BatchEns *d_ens = nullptr;
     BatchBudget *d_budget = nullptr;
     BatchItem *d_items = nullptr;
     uint32_t *d_counter = nullptr;
     // pinned staging and the event that guards its reuse
+    BatchEns *h_ens = nullptr;
     BatchBudget *h_budget = nullptr;
     BatchItem *h_items = nullptr;
     hipEvent_t staged = nullptr;
@@ -32,6 +36,7 @@ struct bwg_batch {
     {
         if (staged_pending) (void)hipEventSynchronize(staged);
         if (staged) (void)hipEventDestroy(staged);
+        if (h_ens) (void)hipHostFree(h_ens);
         if (h_budget) (void)hipHostFree(h_budget);
         if (h_items) (void)hipHostFree(h_items);
     }
@@ -71,15 +76,9 @@ static uint64_t layout_bytes(int n, uint64_t items, uint64_t *off_ens, uint64_t 
     return o;
 }
 
-static uint64_t total_bytes(int n, uint64_t items)
-{
-    uint64_t a, b, c, d;
-    return layout_bytes(n, items, &a, &b, &c, &d);
-}
-
 static int check_members(bwg_ens *const *ens, int32_t n, uint64_t *items)
 {
-    if (!ens || n < 1) return fail(BWG_EINVAL, "empty batch");
+    if (n < 0 || (n > 0 && !ens)) return fail(BWG_EINVAL, "bad member list");
     uint64_t it = 0;
     for (int k = 0; k < n; ++k) {
         const bwg_ens *e = ens[k];
@@ -104,7 +103,72 @@ extern "C" int bwg_batch_state_bytes(bwg_ens *const *ens, int32_t n, uint64_t *b
     uint64_t items;
     int rc = check_members(ens, n, &items);
     if (rc) return rc;
-    *bytes = total_bytes(n, items);
+    uint64_t a, b, c, d;
+    *bytes = layout_bytes(n, items, &a, &b, &c, &d);
+    return BWG_OK;
+}
+
+extern "C" int bwg_batch_capacity_bytes(int32_t max_ensembles, uint64_t max_items, uint64_t *bytes)
+{
+    if (!bytes || max_ensembles < 1) return fail(BWG_EINVAL, "bad capacity");
+    uint64_t a, b, c, d;
+    *bytes = layout_bytes(max_ensembles, max_items, &a, &b, &c, &d);
+    return BWG_OK;
+}
+
+static hipError_t sync_staging(bwg_batch *b)
+{
+    if (!b->staged_pending) return hipSuccess;
+    b->staged_pending = false;
+    return hipEventSynchronize(b->staged);
+}
+
+// Install members: descriptors of every member, uploaded on the stream.
+static int set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, hipStream_t s)
+{
+    uint64_t items;
+    int rc = check_members(ens, n, &items);
+    if (rc) return rc;
+    if (n > b->cap_ens || items > b->cap_items)
+        return fail(BWG_ERANGE, "%d members / %llu items exceed the batch capacity %d / %llu", n,
+                    (unsigned long long)items, b->cap_ens, (unsigned long long)b->cap_items);
+    HIP_TRY(sync_staging(b));
+    b->ens.assign(ens, ens + n);
+    b->bucket.clear();
+    b->cost.clear();
+    b->n_items = items;
+    for (int k = 0; k < n; ++k) {
+        const bwg_ens *e = ens[k];
+        const bwg_net *nt = e->net;
+        const int bk = pick_bucket(e);
+        b->bucket.push_back(bk);
+        const PersistVariant &v = kPersistVariants[bk];
+        // per-event issue cost estimate (orders the queue only)
+        b->cost.push_back(100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
+        BatchEns &d = b->h_ens[k];
+        memset(&d, 0, sizeof d);
+        WmArgs &a = d.a;
+        a.planes = e->planes;
+        a.E = e->E;
+        a.Etgt = e->Et;
+        a.real = e->real;
+        a.wp = e->wp;
+        a.n_words = (e->M + 31) / 32;
+        a.M = e->M;
+        a.seed = e->seed;
+        a.max_events = 0;
+        a.net_id = e->net_id;
+        a.B = nt->q.B;
+        a.cu = nt->shape.cu;
+        a.fa = nt->shape.fa;
+        a.fi = nt->shape.fi;
+        a.nb_mem = e->nb;
+        d.variant = bk;
+    }
+    if (n)
+        HIP_TRY(hipMemcpyAsync(b->d_ens, b->h_ens, sizeof(BatchEns) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(b->staged, s));
+    b->staged_pending = true;
     return BWG_OK;
 }
 
@@ -117,104 +181,91 @@ extern "C" int bwg_batch_create(bwg_ens *const *ens, int32_t n, void *dev_buf, u
     uint64_t items;
     int rc = check_members(ens, n, &items);
     if (rc) return rc;
-    const uint64_t need = total_bytes(n, items);
+    const int cap_ens = std::max<int>(n, opts ? opts->max_ensembles : 0);
+    const uint64_t cap_items = std::max<uint64_t>(items, opts ? opts->max_items : 0);
+    if (cap_ens < 1) return fail(BWG_EINVAL, "empty batch without capacity");
+    uint64_t o_ens, o_bud, o_it, o_cnt;
+    const uint64_t need = layout_bytes(cap_ens, cap_items, &o_ens, &o_bud, &o_it, &o_cnt);
     if (buf_bytes < need)
         return fail(BWG_ENOMEM, "batch buffer of %llu bytes, need %llu",
                     (unsigned long long)buf_bytes, (unsigned long long)need);
     auto b = new bwg_batch();
-    b->ens.assign(ens, ens + n);
     b->waves = (opts && opts->waves > 0) ? opts->waves : 2048;
     b->order = opts ? opts->order : 0;
-    b->max_items = items;
-    uint64_t o_ens, o_bud, o_it, o_cnt;
-    layout_bytes(n, items, &o_ens, &o_bud, &o_it, &o_cnt);
+    b->cap_ens = cap_ens;
+    b->cap_items = cap_items;
     uint8_t *base = (uint8_t *)dev_buf;
     b->d_ens = (BatchEns *)(base + o_ens);
     b->d_budget = (BatchBudget *)(base + o_bud);
     b->d_items = (BatchItem *)(base + o_it);
     b->d_counter = (uint32_t *)(base + o_cnt);
-    hipStream_t s = (hipStream_t)stream;
-    int err = BWG_OK;
-    do {
-        if (hipHostMalloc((void **)&b->h_budget, sizeof(BatchBudget) * n, hipHostMallocDefault) !=
-                hipSuccess ||
-            hipHostMalloc((void **)&b->h_items, sizeof(BatchItem) * items, hipHostMallocDefault) !=
-                hipSuccess ||
-            hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
-            err = fail(BWG_EDEVICE, "pinned staging allocation failed");
-            break;
-        }
-        std::vector<BatchEns> he(n);
-        for (int k = 0; k < n; ++k) {
-            const bwg_ens *e = ens[k];
-            const bwg_net *nt = e->net;
-            const int bk = pick_bucket(e);
-            b->bucket.push_back(bk);
-            const PersistVariant &v = kPersistVariants[bk];
-            // per-event issue cost of the bucket: RNG quads + planes (an estimate
-            // used only to order the queue)
-            b->cost.push_back(100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
-            WmArgs &a = he[k].a;
-            memset(&a, 0, sizeof a);
-            a.planes = e->planes;
-            a.E = e->E;
-            a.Etgt = e->Et;
-            a.real = e->real;
-            a.wp = e->wp;
-            a.n_words = (e->M + 31) / 32;
-            a.M = e->M;
-            a.seed = e->seed;
-            a.max_events = 0;
-            a.net_id = e->net_id;
-            a.B = nt->q.B;
-            a.cu = nt->shape.cu;
-            a.fa = nt->shape.fa;
-            a.fi = nt->shape.fi;
-            a.nb_mem = e->nb;
-            he[k].variant = bk;
-            he[k].pad = 0;
-        }
-        if (hipMemcpyAsync(b->d_ens, he.data(), sizeof(BatchEns) * n, hipMemcpyHostToDevice, s) !=
-            hipSuccess) {
-            err = fail(BWG_EDEVICE, "upload of batch descriptors failed");
-            break;
-        }
-        if (hipStreamSynchronize(s) != hipSuccess) {
-            err = fail(BWG_EDEVICE, "stream synchronisation failed");
-            break;
-        }
-    } while (0);
-    if (err) {
+    if (hipHostMalloc((void **)&b->h_ens, sizeof(BatchEns) * cap_ens, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&b->h_budget, sizeof(BatchBudget) * cap_ens, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&b->h_items, sizeof(BatchItem) * std::max<uint64_t>(cap_items, 1),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
         delete b;
-        return err;
+        return fail(BWG_EDEVICE, "pinned staging allocation failed");
+    }
+    rc = set_members(b, ens, n, (hipStream_t)stream);
+    if (rc) {
+        delete b;
+        return rc;
     }
     *out = b;
     return BWG_OK;
 }
 
+extern "C" int bwg_batch_set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, void *stream)
+{
+    if (!b) return fail(BWG_EINVAL, "null batch");
+    return set_members(b, ens, n, (hipStream_t)stream);
+}
+
 extern "C" void bwg_batch_destroy(bwg_batch *b) { delete b; }
 
-// Stage tables, budgets and the ordered queue of one advance to t_end[k].
-static int stage(bwg_batch *b, const double *t_end, hipStream_t s, double *mu_out)
+// Queue of the members' items, longest pending work first (or in member
+// order), uploaded on the stream.
+static int stage_items(bwg_batch *b, hipStream_t s)
+{
+    std::vector<std::pair<double, BatchItem>> q;
+    q.reserve(b->n_items);
+    for (size_t k = 0; k < b->ens.size(); ++k) {
+        const bwg_ens *e = b->ens[k];
+        const double c = b->cost[k] * (double)e->pending;
+        const uint64_t words = (e->M + 31) / 32;
+        for (uint64_t w0 = 0; w0 < words; w0 += 64)
+            q.push_back({c, BatchItem{(uint32_t)k, (uint32_t)w0}});
+    }
+    if (b->order == 0)
+        std::stable_sort(q.begin(), q.end(),
+                         [](const std::pair<double, BatchItem> &x,
+                            const std::pair<double, BatchItem> &y) { return x.first > y.first; });
+    for (size_t i = 0; i < q.size(); ++i) b->h_items[i] = q[i].second;
+    if (!q.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items, sizeof(BatchItem) * q.size(),
+                               hipMemcpyHostToDevice, s));
+    return BWG_OK;
+}
+
+// Tables and budget descriptors of one advance of every member to t_end[k].
+static int stage_budgets(bwg_batch *b, const double *t_end, hipStream_t s,
+                         std::vector<uint64_t> &kmin, std::vector<uint64_t> &kmax)
 {
     const int n = (int)b->ens.size();
-    if (b->staged_pending) {
-        HIP_TRY(hipEventSynchronize(b->staged));
-        b->staged_pending = false;
-    }
+    kmin.assign(n, 0);
+    kmax.assign(n, 0);
     uint64_t offset = 0;
-    std::vector<std::pair<double, BatchItem>> q;
-    q.reserve(b->max_items);
     for (int k = 0; k < n; ++k) {
         bwg_ens *e = b->ens[k];
         if (!e->inited) return fail(BWG_EINVAL, "ensemble %d not initialised", k);
         if (!(t_end[k] >= e->t_now))
             return fail(BWG_EINVAL, "ensemble %d: t_end %g before t_now %g", k, t_end[k], e->t_now);
         const double mu = e->net->q.lambda * (t_end[k] - e->t_now);
-        mu_out[k] = mu;
         BatchBudget &bb = b->h_budget[k];
         memset(&bb, 0, sizeof bb);
-        uint64_t kmax = 0, kmin = 0;
         if (mu > 0) {
             const Table *t;
             int rc = get_table(e->net, mu, &t);
@@ -226,8 +277,8 @@ static int stage(bwg_batch *b, const double *t_end, hipStream_t s, double *mu_ou
             bb.T = e->table;
             bb.len = t->len;
             bb.k_lo = t->k_lo;
-            kmin = (uint64_t)t->k_lo;
-            kmax = (uint64_t)t->k_lo + t->len;
+            kmin[k] = (uint64_t)t->k_lo;
+            kmax[k] = (uint64_t)t->k_lo + t->len;
         }
         bb.seed = e->seed;
         bb.offset = offset;
@@ -236,45 +287,46 @@ static int stage(bwg_batch *b, const double *t_end, hipStream_t s, double *mu_ou
         bb.Et = e->Et;
         bb.net_id = e->net_id;
         offset += e->M;
-        const double c = b->cost[k] * (double)(kmax + e->lag);
-        const uint64_t words = (e->M + 31) / 32;
-        for (uint64_t w0 = 0; w0 < words; w0 += 64)
-            q.push_back({c, BatchItem{(uint32_t)k, (uint32_t)w0}});
-        (void)kmin;
     }
-    if (b->order == 0)
-        std::stable_sort(q.begin(), q.end(),
-                         [](const std::pair<double, BatchItem> &x,
-                            const std::pair<double, BatchItem> &y) { return x.first > y.first; });
-    for (size_t i = 0; i < q.size(); ++i) b->h_items[i] = q[i].second;
-    HIP_TRY(hipMemcpyAsync(b->d_budget, b->h_budget, sizeof(BatchBudget) * n,
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items, sizeof(BatchItem) * q.size(),
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(b->staged, s));
-    b->staged_pending = true;
+    if (n)
+        HIP_TRY(hipMemcpyAsync(b->d_budget, b->h_budget, sizeof(BatchBudget) * n,
+                               hipMemcpyHostToDevice, s));
     return BWG_OK;
 }
 
-// The kernels of one batch advance (budgets, advance indices, queue reset,
-// persistent event kernel); all graph-capturable.
-static int enqueue(bwg_batch *b, uint64_t total_replicas, hipStream_t s)
+static uint64_t total_replicas(const bwg_batch *b)
+{
+    uint64_t t = 0;
+    for (auto *e : b->ens) t += e->M;
+    return t;
+}
+
+// Budget draws and advance-index increments of every member (kernels only).
+static int enqueue_budgets(bwg_batch *b, hipStream_t s)
 {
     const int n = (int)b->ens.size();
-    HIP_TRY(launch_batch_budget(b->d_budget, n, total_replicas, s));
+    if (!n) return BWG_OK;
+    HIP_TRY(launch_batch_budget(b->d_budget, n, total_replicas(b), s));
     HIP_TRY(launch_batch_epilogue(b->d_budget, n, s));
-    HIP_TRY(launch_batch_prologue(b->d_counter, s));
-    HIP_TRY(launch_persistent(b->d_ens, b->d_items, (uint32_t)b->max_items, b->d_counter, b->waves,
-                              s));
     return BWG_OK;
 }
 
-static void finish_host(bwg_batch *b, const double *t_end, const double *mu)
+// One persistent pass over the staged queue (kernels only).
+static int enqueue_pass(bwg_batch *b, uint64_t max_events, hipStream_t s)
+{
+    if (!b->n_items) return BWG_OK;
+    HIP_TRY(launch_batch_prologue(b->d_counter, s));
+    HIP_TRY(launch_persistent(b->d_ens, b->d_items, (uint32_t)b->n_items, b->d_counter, b->waves,
+                              max_events, s));
+    return BWG_OK;
+}
+
+static void note_budgets(bwg_batch *b, const double *t_end, const std::vector<uint64_t> &kmin,
+                         const std::vector<uint64_t> &kmax)
 {
     for (size_t k = 0; k < b->ens.size(); ++k) {
         bwg_ens *e = b->ens[k];
-        const Table *t = nullptr;
-        if (mu[k] > 0 && get_table(e->net, mu[k], &t) == BWG_OK) e->lag += t->len;
+        note_scheduled(e, kmin[k], kmax[k]);
         e->t_now = t_end[k];
         e->adv += 1;
     }
@@ -282,16 +334,37 @@ static void finish_host(bwg_batch *b, const double *t_end, const double *mu)
 
 extern "C" int bwg_batch_advance(bwg_batch *b, const double *t_end, void *stream)
 {
-    if (!b || !t_end) return fail(BWG_EINVAL, "null argument");
+    if (!b || (!t_end && !b->ens.empty())) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<double> mu(b->ens.size());
-    int rc = stage(b, t_end, s, mu.data());
+    HIP_TRY(sync_staging(b));
+    std::vector<uint64_t> kmin, kmax;
+    int rc = stage_budgets(b, t_end, s, kmin, kmax);
     if (rc) return rc;
-    uint64_t total = 0;
-    for (auto *e : b->ens) total += e->M;
-    rc = enqueue(b, total, s);
+    rc = enqueue_budgets(b, s);
     if (rc) return rc;
-    finish_host(b, t_end, mu.data());
+    note_budgets(b, t_end, kmin, kmax);
+    rc = stage_items(b, s);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b->staged, s));
+    b->staged_pending = true;
+    rc = enqueue_pass(b, 0, s);
+    if (rc) return rc;
+    for (auto *e : b->ens) note_ran(e, 0);
+    return BWG_OK;
+}
+
+extern "C" int bwg_batch_run(bwg_batch *b, uint64_t max_events, void *stream)
+{
+    if (!b) return fail(BWG_EINVAL, "null batch");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(sync_staging(b));
+    int rc = stage_items(b, s);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b->staged, s));
+    b->staged_pending = true;
+    rc = enqueue_pass(b, max_events, s);
+    if (rc) return rc;
+    for (auto *e : b->ens) note_ran(e, max_events);
     return BWG_OK;
 }
 
@@ -313,16 +386,23 @@ extern "C" int bwg_batch_graph_advance(bwg_batch *b, double dt, int32_t n_steps,
             t = t2;
         }
     }
-    std::vector<double> t_end(n), mu(n);
+    HIP_TRY(sync_staging(b));
+    std::vector<double> t_end(n);
     for (size_t k = 0; k < n; ++k) t_end[k] = b->ens[k]->t_now + dt;
-    int rc = stage(b, t_end.data(), s, mu.data());
+    std::vector<uint64_t> kmin, kmax;
+    int rc = stage_budgets(b, t_end.data(), s, kmin, kmax);
     if (rc) return rc;
-    uint64_t total = 0;
-    for (auto *e : b->ens) total += e->M;
+    // the queue order of the first step serves every replay
+    for (size_t k = 0; k < n; ++k) b->ens[k]->pending = b->ens[k]->lag + kmax[k];
+    rc = stage_items(b, s);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b->staged, s));
+    b->staged_pending = true;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = enqueue(b, total, s);
+    rc = enqueue_budgets(b, s);
+    if (!rc) rc = enqueue_pass(b, 0, s);
     hipError_t ce = hipStreamEndCapture(s, &g);
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -341,7 +421,8 @@ extern "C" int bwg_batch_graph_advance(bwg_batch *b, double dt, int32_t n_steps,
             err = fail(BWG_EDEVICE, "graph launch: %s", hipGetErrorString(le));
             break;
         }
-        finish_host(b, t_end.data(), mu.data());
+        note_budgets(b, t_end.data(), kmin, kmax);
+        for (auto *e : b->ens) note_ran(e, 0);
         for (size_t k = 0; k < n; ++k) t_end[k] = b->ens[k]->t_now + dt;
     }
     // the executable graph may still be running: destroy after the stream drains

@@ -499,66 +499,85 @@ extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts
     e->t_now = 0;
     e->adv = 0;
     e->lag = 0;
+    e->pending = 0;
     e->inited = true;
     return BWG_OK;
 }
 
-// Enqueue the event launches of one advance or step.  k_min/k_max bound the
-// budgets just drawn.
-static int run_events(bwg_ens *e, uint64_t k_min, uint64_t k_max, hipStream_t s)
+void bwg::note_scheduled(bwg_ens *e, uint64_t kmin, uint64_t kmax)
+{
+    e->pending = e->lag + kmax;
+    e->lag += kmax - kmin;
+}
+
+void bwg::note_ran(bwg_ens *e, uint64_t max_events)
+{
+    if (max_events == 0 || max_events >= e->pending)
+        e->pending = 0;
+    else
+        e->pending -= max_events;
+}
+
+// One launch of the pending events of every word, at most max_events each
+// (0: all of them).
+static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
 {
     const bwg_net *n = e->net;
-    uint64_t launches = 1;
-    if (e->epl) {
-        const uint64_t span = k_max + e->lag;
-        launches = span ? (span + e->epl - 1) / e->epl : 1;
+    if (e->engine == BWG_ENGINE_BITWISE) {
+        WmArgs a{};
+        a.planes = e->planes;
+        a.E = e->E;
+        a.Etgt = e->Et;
+        a.real = e->real;
+        a.wp = e->wp;
+        a.n_words = (e->M + 31) / 32;
+        a.M = e->M;
+        a.seed = e->seed;
+        a.max_events = max_events;
+        a.net_id = e->net_id;
+        a.B = n->q.B;
+        a.cu = n->shape.cu;
+        a.fa = n->shape.fa;
+        a.fi = n->shape.fi;
+        a.nb_mem = e->nb;
+        HIP_TRY(e->var->fn(a, s, e->block));
+    } else {
+        PlainArgs a{};
+        a.counts = e->counts;
+        a.E = e->E;
+        a.Etgt = e->Et;
+        a.real = e->real;
+        a.M = e->M;
+        a.seed = e->seed;
+        a.max_events = max_events;
+        a.net_id = e->net_id;
+        a.B = n->q.B;
+        a.R = n->R;
+        for (int j = 0; j < n->R; ++j) a.rx[j] = n->prx[j];
+        HIP_TRY(launch_plain(a, s, e->block));
     }
-    e->lag += k_max - k_min;
-    for (uint64_t l = 0; l < launches; ++l) {
-        if (e->engine == BWG_ENGINE_BITWISE) {
-            WmArgs a{};
-            a.planes = e->planes;
-            a.E = e->E;
-            a.Etgt = e->Et;
-            a.real = e->real;
-            a.wp = e->wp;
-            a.n_words = (e->M + 31) / 32;
-            a.M = e->M;
-            a.seed = e->seed;
-            a.max_events = e->epl;
-            a.net_id = e->net_id;
-            a.B = n->q.B;
-            a.cu = n->shape.cu;
-            a.fa = n->shape.fa;
-            a.fi = n->shape.fi;
-            a.nb_mem = e->nb;
-            HIP_TRY(e->var->fn(a, s, e->block));
-        } else {
-            PlainArgs a{};
-            a.counts = e->counts;
-            a.E = e->E;
-            a.Etgt = e->Et;
-            a.real = e->real;
-            a.M = e->M;
-            a.seed = e->seed;
-            a.max_events = e->epl;
-            a.net_id = e->net_id;
-            a.B = n->q.B;
-            a.R = n->R;
-            for (int j = 0; j < n->R; ++j) a.rx[j] = n->prx[j];
-            HIP_TRY(launch_plain(a, s, e->block));
-        }
+    note_ran(e, max_events);
+    return BWG_OK;
+}
+
+// Enqueue the event launches of a scheduled advance or step: enough launches
+// of events_per_launch (if set) to cover the pending bound.
+static int run_events(bwg_ens *e, hipStream_t s)
+{
+    if (!e->epl) return launch_events(e, 0, s);
+    while (e->pending) {
+        int rc = launch_events(e, e->epl, s);
+        if (rc) return rc;
     }
     return BWG_OK;
 }
 
-extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
+int bwg::schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin_out,
+                           uint64_t *kmax_out)
 {
-    if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     if (!(t_end >= e->t_now)) return fail(BWG_EINVAL, "t_end %g before t_now %g", t_end, e->t_now);
     if (e->adv >= (1ull << 48)) return fail(BWG_ERANGE, "advance index overflow");
-    hipStream_t s = (hipStream_t)stream;
     const double mu = e->net->q.lambda * (t_end - e->t_now);
     uint64_t kmin = 0, kmax = 0;
     if (mu > 0) {
@@ -578,11 +597,46 @@ extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
                               e->Et, s));
     }
     HIP_TRY(launch_add_u64(e->adv_dev, 1, s));
-    int rc = run_events(e, kmin, kmax, s);
-    if (rc) return rc;
     e->t_now = t_end;
     e->adv += 1;
+    *kmin_out = kmin;
+    *kmax_out = kmax;
     return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_schedule(bwg_ens *e, double t_end, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    uint64_t kmin, kmax;
+    int rc = schedule_ensemble(e, t_end, (hipStream_t)stream, &kmin, &kmax);
+    if (rc) return rc;
+    note_scheduled(e, kmin, kmax);
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_run(bwg_ens *e, uint64_t max_events, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
+    return launch_events(e, max_events, (hipStream_t)stream);
+}
+
+extern "C" int bwg_ensemble_pending(const bwg_ens *e, uint64_t *bound)
+{
+    if (!e || !bound) return fail(BWG_EINVAL, "null argument");
+    *bound = e->pending;
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t kmin, kmax;
+    int rc = schedule_ensemble(e, t_end, s, &kmin, &kmax);
+    if (rc) return rc;
+    note_scheduled(e, kmin, kmax);
+    return run_events(e, s);
 }
 
 extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
@@ -592,7 +646,8 @@ extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_budget(nullptr, 0, 0, n_events, 0, e->seed, e->net_id, e->adv_dev, e->M, e->E,
                           e->Et, s));
-    return run_events(e, n_events, n_events, s);
+    note_scheduled(e, n_events, n_events);
+    return run_events(e, s);
 }
 
 extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)

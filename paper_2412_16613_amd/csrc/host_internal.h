@@ -70,6 +70,7 @@ struct bwg_ens {
     double t_now = 0;
     uint64_t adv = 0;
     uint64_t lag = 0;      // bound on how far a word's lanes can be apart
+    uint64_t pending = 0;  // bound on the events any word still has to run
     bool inited = false;
 };
 
@@ -77,4 +78,10 @@ struct bwg_ens {
 namespace bwg {
 // Cached pinned Poisson table for mean mu (lives as long as the network).
 int get_table(bwg_net *n, double mu, const Table **out);
+// Budgets of one advance to t_end (no event launches); *kmin/*kmax bound K.
+int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, uint64_t *kmax);
+// Bookkeeping after budgets with K in [kmin, kmax] were drawn.
+void note_scheduled(bwg_ens *e, uint64_t kmin, uint64_t kmax);
+// Bookkeeping after a pass that ran up to max_events per word (0: all).
+void note_ran(bwg_ens *e, uint64_t max_events);
 }

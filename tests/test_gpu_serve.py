@@ -1,0 +1,80 @@
+"""Continuous batching: results alone and in the mix are bit-identical."""
+
+import numpy as np
+import pytest
+
+import paper_2412_16613_amd as bwg
+from paper_2412_16613_amd.serve import Server, summarize
+from oracle import ssa
+from workloads import frank_network, serve_requests
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _requests():
+    nets = [(frank_network(16, k0=0.05), 33, 10.0), (frank_network(100), 1000, 3.0),
+            (frank_network(300, k0=0.003), 2048, 1.5), (frank_network(1000, k0=0.02), 97, 0.6),
+            (frank_network(40, k0=0.1), 5000, 6.0), (frank_network(2000, k0=0.001), 64, 0.3),
+            (frank_network(24, k0=0.02), 700, 8.0), (frank_network(64), 4096, 2.0)]
+    out = []
+    for k, (net, M, t) in enumerate(nets):
+        out.append(dict(arrival=0.7 * k, net=net, replicas=M, seed=17, net_id=500 + k,
+                        init=("fixed", (0, 0, net["n_tot"])), t_end=t))
+    return out
+
+
+def test_served_results_equal_results_alone(torch):
+    reqs = _requests()
+    srv = Server(chunk=200, max_members=4, keep_counts=True)
+    res = srv.serve(reqs, real_time=False, pass_time=1.0)
+    assert len(res) == len(reqs)
+    assert srv.stats["max_active"] >= 2          # the mix really overlapped
+    by_id = {r["id"]: r for r in res}
+    for r in reqs:
+        e = bwg.Ensemble(bwg.Network(r["net"]), r["replicas"], seed=r["seed"],
+                         net_id=r["net_id"])
+        e.init(r["init"]).advance(r["t_end"])
+        h = e.histogram(256).cpu().numpy()
+        c = e.read_counts().cpu().numpy()
+        got = by_id[r["net_id"]]
+        np.testing.assert_array_equal(got["hist"], h)
+        np.testing.assert_array_equal(got["counts"], c)
+
+
+def test_served_small_requests_match_oracle(torch):
+    reqs = _requests()[:2]
+    res = Server(chunk=150, keep_counts=True).serve(reqs, real_time=False)
+    for r, got in zip(reqs, sorted(res, key=lambda x: x["id"])):
+        o = ssa.OracleEnsemble(r["net"], r["replicas"], seed=r["seed"], net_id=r["net_id"])
+        o.init(r["init"])
+        o.advance(r["t_end"])
+        np.testing.assert_array_equal(got["counts"], o.counts)
+
+
+def test_admission_respects_the_memory_budget(torch):
+    reqs = _requests()
+    one = max(bwg.Ensemble(bwg.Network(r["net"]), r["replicas"]).state_bytes for r in reqs)
+    srv = Server(hbm_budget=one + 1, chunk=300)
+    res = srv.serve(reqs, real_time=False)
+    assert len(res) == len(reqs)
+    assert srv.stats["max_active"] <= 2
+
+
+def test_real_time_stream_reports_latency(torch):
+    reqs = [r for r in serve_requests(rate=50.0, duration=1.0, lattice_frac=0.0)]
+    for r in reqs:           # keep the test short: small horizons and sizes
+        r["t_end"] = r["t_end"] / 100.0
+        r["replicas"] = min(r["replicas"], 4096)
+    srv = Server(chunk=1024)
+    res = srv.serve(reqs, real_time=True)
+    s = summarize(res, srv.stats)
+    assert len(res) == len(reqs)
+    assert all(r["latency"] >= 0 for r in res)
+    assert s["p99_latency_s"] >= s["p50_latency_s"]
