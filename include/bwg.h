@@ -56,6 +56,10 @@ enum {
 /* initial-state modes of bwg_ensemble_init */
 #define BWG_INIT_FIXED 0        /* every replica starts from counts[0..S-1]   */
 #define BWG_INIT_MULTINOMIAL 1  /* each molecule L, D, A w.p. 1/4, 1/4, 1/2   */
+#define BWG_INIT_UNIFORM_SITE 2 /* lattice: A uniform in {counts[0]..counts[1]}
+                                   on every site, L = D = 0                    */
+#define BWG_INIT_SITES 3        /* lattice: every replica starts from the site
+                                   counts counts[s*3 + x], s < lx*ly           */
 
 typedef struct bwg_net bwg_net;
 typedef struct bwg_ens bwg_ens;
@@ -104,6 +108,32 @@ typedef struct {
     int64_t max_total;    /* max_N sum_j w_j(N)                               */
 } bwg_qnet;
 
+/*
+ * Integer form of a lattice network (lx, ly > 0).  The paper's method is for
+ * one well-mixed reactor; it names ensembles of small compartments as the
+ * use it aims at (Sec. 1, Sec. 6) without giving their chain, so the library
+ * defines it: every site is a Frank reactor (reactions in the order A -> L,
+ * A -> D, A + L -> 2L, A + D -> 2D, L + D -> 2A, weights c_j h_j of the site
+ * counts) whose molecules hop to each of the 4 periodic neighbours at weight
+ * c_hop; a site holds at most T = 2^P - 1 molecules and a hop into a full
+ * site does nothing.  Uniformisation by components: a reaction component per
+ * site of weight 2^B_r (2^B_r >= max_site, the largest site weight sum) and
+ * a hop component per (site, direction) of weight (T + 1) c_hop, C in all;
+ * lambda = C / s events per replica per unit time.  Each event draws one
+ * component shared by the 2048 replicas of a group, then per replica a
+ * threshold (reaction) or a molecule index j in [0, T] (hop: A if j < n_A,
+ * L if j < n_A + n_L, D if j < n_site).
+ */
+typedef struct {
+    int32_t lx, ly, sites;      /* periodic lattice, sites = lx * ly          */
+    int32_t P, T;               /* planes per species count, site capacity    */
+    int32_t B_r;                /* threshold planes of a reaction component   */
+    int64_t c_hop;              /* hop weight per molecule and direction      */
+    uint64_t C;                 /* total component weight                     */
+    int64_t max_site;           /* largest site weight sum                    */
+    double s, lambda;           /* scale 2^f / k_ref; C / s                   */
+} bwg_lattice_info;
+
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */
     int32_t block;               /* threads per block, 0 = default            */
@@ -129,6 +159,13 @@ typedef struct {
  * owned by the caller (bwg_net_destroy). */
 int bwg_net_create(const bwg_net_desc *desc, bwg_net **out);
 int bwg_net_quantized(const bwg_net *net, bwg_qnet *out);
+
+/* The lattice form of a network created with lx, ly > 0 (EINVAL otherwise).
+ * For such networks bwg_net_quantized reports c[0..4], f, s, B = B_r,
+ * b = P, lambda and max_total = max_site.  Lattice networks need the five
+ * Frank reactions in the order above, one hop rate for all species,
+ * site_planes 1..8 and at most 4096 sites (EUNSUPPORTED / ERANGE). */
+int bwg_net_lattice(const bwg_net *net, bwg_lattice_info *out);
 void bwg_net_destroy(bwg_net *net);
 
 /* Poisson inverse-CDF table of the event budget for mean mu (host):
@@ -155,7 +192,10 @@ int bwg_ensemble_create(const bwg_net *net, uint64_t n_replicas, uint64_t seed,
 /* Set every replica's initial state and reset time, event counters and the
  * advance index.  mode BWG_INIT_FIXED takes counts[S] (host pointer, summing
  * to n_tot); BWG_INIT_MULTINOMIAL draws the paper's racemic multinomial start
- * (Frank species only).  Async. */
+ * (Frank species only).  Lattices take BWG_INIT_FIXED (counts[3] on every
+ * site), BWG_INIT_SITES (counts[sites*3]) or BWG_INIT_UNIFORM_SITE (counts =
+ * {lo, hi}; the draw of replica i, site s is exact: 32-bit multiply-shift
+ * with rejection on INIT draws); ERANGE if a site would exceed T.  Async. */
 int bwg_ensemble_init(bwg_ens *ens, int32_t mode, const int32_t *counts,
                       void *stream);
 
@@ -175,6 +215,11 @@ int bwg_ensemble_advance(bwg_ens *ens, double t_end, void *stream);
  * bwg_ensemble_advance.  Async. */
 int bwg_ensemble_schedule(bwg_ens *ens, double t_end, void *stream);
 int bwg_ensemble_run(bwg_ens *ens, uint64_t max_events, void *stream);
+/* Lattices run whole chunks of 8192 events of their component sequence, so a
+ * capped pass may run up to 8191 events beyond max_events; a lattice accepts
+ * a new schedule, advance or step only once its pending bound is 0 (EINVAL
+ * otherwise), and its per-replica event counts move to their targets when
+ * the last chunk has run. */
 
 /* Host-side upper bound on the events any word still has to run (0 once
  * every scheduled event has been launched).  No device work, no sync. */
@@ -185,19 +230,33 @@ int bwg_ensemble_pending(const bwg_ens *ens, uint64_t *bound);
 int bwg_ensemble_step(bwg_ens *ens, uint64_t n_events, void *stream);
 
 /* Counts of every replica: dev_dst[i*S + x], int32, species order of the
- * network.  Async. */
+ * network; on a lattice the species totals over all sites.  Async. */
 int bwg_ensemble_read_counts(bwg_ens *ens, int32_t *dev_dst, void *stream);
 
 /* Histogram of the enantiomeric excess (N_L - N_D)/N_tot over replicas:
  * bin = min(n_bins-1, floor((N_L - N_D + N_tot) n_bins / (2 N_tot))),
- * dev_dst[n_bins] uint64 (overwritten).  Frank species only.  Async. */
+ * dev_dst[n_bins] uint64 (overwritten).  Frank species only.  On a lattice
+ * N_L, N_D are totals over sites and N_tot is the replica's molecule count
+ * (a replica without molecules goes to bin n_bins/2).  Async. */
 int bwg_ensemble_histogram(bwg_ens *ens, int32_t n_bins, uint64_t *dev_dst,
                            void *stream);
 
-/* Per-replica events run and real (state-changing) events so far:
- * dev_events[i], dev_real[i] uint64 (either may be NULL).  Async. */
+/* Events run per replica, dev_events[i], and real (state-changing) events
+ * so far, dev_real[]: per replica for the plain engine, per 32-replica word
+ * (ceil(M/32) entries) for the bit-sliced engine and lattices.  uint64;
+ * either pointer may be NULL.  Async. */
 int bwg_ensemble_read_events(bwg_ens *ens, uint64_t *dev_events,
                              uint64_t *dev_real, void *stream);
+
+/* Lattice ensembles: site counts of replicas first .. first+count-1,
+ * dev_dst[(k*sites + s)*3 + x] int32 (species L, D, A).  EINVAL for a
+ * well-mixed ensemble or a range beyond the replicas.  Async. */
+int bwg_ensemble_read_sites(bwg_ens *ens, uint64_t first, uint64_t count, int32_t *dev_dst,
+                            void *stream);
+
+/* Lattice ensembles: hops into full sites so far, per 32-replica word,
+ * dev_dst[ceil(M/32)] uint64.  Async. */
+int bwg_ensemble_read_blocked(bwg_ens *ens, uint64_t *dev_dst, void *stream);
 
 /* Synchronises the stream and reports totals. */
 int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);

@@ -70,14 +70,18 @@ uint64_t orc_lat_component(uint64_t seed, uint32_t net_id, uint32_t group, uint6
 {
     const unsigned __int128 two64 = (unsigned __int128)1 << 64;
     const uint64_t thresh = (uint64_t)(two64 % C);
-    for (uint32_t attempt = 0;; ++attempt) {
+    unsigned __int128 m = 0;
+    /* attempts 0..255; the last is taken as it is (reached with probability
+       below (C / 2^64)^255) */
+    for (uint32_t attempt = 0; attempt < 256; ++attempt) {
         uint32_t o[4];
-        philox((uint32_t)e, (5u << 24) | ((attempt & 0xFFu) << 16) | (uint32_t)((e >> 32) & 0xFFFFu),
+        philox((uint32_t)e, (5u << 24) | (attempt << 16) | (uint32_t)((e >> 32) & 0xFFFFu),
                group, net_id, seed, o);
         uint64_t u = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
-        unsigned __int128 m = (unsigned __int128)u * C;
-        if ((uint64_t)m >= thresh) return (uint64_t)(m >> 64);
+        m = (unsigned __int128)u * C;
+        if ((uint64_t)m >= thresh) break;
     }
+    return (uint64_t)(m >> 64);
 }
 
 /* Uniform integer in [lo, hi] for (replica, site), exact. */
@@ -86,14 +90,15 @@ static int32_t init_count(uint64_t seed, uint32_t net_id, uint64_t i, uint32_t s
 {
     const uint32_t R = (uint32_t)(hi - lo + 1);
     const uint32_t thresh = (uint32_t)(-R) % R;
-    for (uint32_t attempt = 0;; ++attempt) {
+    for (uint32_t attempt = 0; attempt < 65536; ++attempt) {
         uint32_t o[4];
-        philox(site, (3u << 24) | (1u << 23) | (attempt & 0xFFFFu), (uint32_t)i, net_id, seed, o);
+        philox(site, (3u << 24) | (1u << 23) | attempt, (uint32_t)i, net_id, seed, o);
         for (int k = 0; k < 4; ++k) {
             uint64_t m = (uint64_t)o[k] * R;
             if ((uint32_t)m >= thresh) return lo + (int32_t)(m >> 32);
         }
     }
+    return lo; /* 262144 rejections in a row: probability below 2^-1000000 */
 }
 
 /* Replicas first + k*stride, k < n: L = D = 0, A uniform in {lo..hi}. */
@@ -199,6 +204,8 @@ int orc_lat_run(const orc_lat *L, uint64_t seed, uint32_t net_id, uint64_t first
                 if (x >= 0) {
                     if (c2[0] + c2[1] + c2[2] >= T) {
                         ++nblk;
+                    } else if (s2 == s) {
+                        /* one site wide along this axis: the hop returns home */
                     } else {
                         c[x] -= 1;
                         c2[x] += 1;

@@ -198,5 +198,6 @@ class OracleLattice:
         t = self.totals().astype(np.int64)
         n = t.sum(1)
         d = t[:, 0] - t[:, 1]
-        bins = np.minimum(n_bins - 1, ((d + n) * n_bins) // np.maximum(2 * n, 1))
+        bins = np.where(n > 0, np.minimum(n_bins - 1, ((d + n) * n_bins) // np.maximum(2 * n, 1)),
+                        n_bins // 2)
         return np.bincount(bins, minlength=n_bins).astype(np.uint64)

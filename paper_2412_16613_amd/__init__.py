@@ -65,12 +65,21 @@ class Network:
         _abi.check(L.bwg_net_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
 
+        self.is_lattice = bool(d.lx or d.ly)
+
     def quantized(self):
         q = _abi.QNet()
         _abi.check(_lib().bwg_net_quantized(self.handle, ctypes.byref(q)))
         R = q.n_reactions
         return dict(c=list(q.c[:R]), f=q.f, B=q.B, W=1 << q.B, b=q.b, s=q.s,
                     Lambda=q.lambda_, max_total=q.max_total, gpu_ok=bool(q.gpu_ok))
+
+    def lattice(self):
+        """Integer form of a lattice network (bwg_net_lattice)."""
+        i = _abi.LatticeInfo()
+        _abi.check(_lib().bwg_net_lattice(self.handle, ctypes.byref(i)))
+        return dict(lx=i.lx, ly=i.ly, sites=i.sites, P=i.P, T=i.T, B_r=i.B_r, c_hop=i.c_hop,
+                    C=i.C, max_site=i.max_site, s=i.s, Lambda=i.lambda_)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -131,11 +140,29 @@ class Ensemble:
                                             self._stream()))
         return self
 
+    def init_uniform_site(self, lo, hi):
+        """Lattice: A uniform in {lo..hi} on every site, L = D = 0."""
+        c = _i32arr([int(lo), int(hi)])
+        _abi.check(_lib().bwg_ensemble_init(self.handle, _abi.BWG_INIT_UNIFORM_SITE, c,
+                                            self._stream()))
+        return self
+
+    def init_sites(self, sites):
+        """Lattice: every replica starts from sites[s][x] (S x 3 counts)."""
+        flat = [int(v) for row in sites for v in row]
+        c = _i32arr(flat)
+        _abi.check(_lib().bwg_ensemble_init(self.handle, _abi.BWG_INIT_SITES, c, self._stream()))
+        return self
+
     def init(self, mode):
-        if mode[0] == "fixed":
+        if mode[0] in ("fixed", "fixed_site"):
             return self.init_fixed(mode[1])
         if mode[0] == "multinomial":
             return self.init_multinomial()
+        if mode[0] == "uniform_site":
+            return self.init_uniform_site(mode[1], mode[2])
+        if mode[0] == "sites":
+            return self.init_sites(mode[1])
         raise ValueError(mode)
 
     def advance(self, t_end):
@@ -176,6 +203,27 @@ class Ensemble:
         _abi.check(_lib().bwg_ensemble_histogram(self.handle, n_bins,
                                                  ctypes.c_void_p(out.data_ptr()),
                                                  self._stream()))
+        return out
+
+    def read_sites(self, first=0, count=None, out=None):
+        """Lattice: site counts of replicas first..first+count-1 as an int32
+        tensor [count, sites, 3]."""
+        t = self.torch
+        S = self.network.lattice()["sites"]
+        count = self.M - first if count is None else int(count)
+        if out is None:
+            out = t.empty((count, S, 3), dtype=t.int32, device=self.device)
+        _abi.check(_lib().bwg_ensemble_read_sites(self.handle, int(first), count,
+                                                  ctypes.c_void_p(out.data_ptr()),
+                                                  self._stream()))
+        return out
+
+    def read_blocked(self):
+        """Lattice: hops into full sites per 32-replica word (int64)."""
+        t = self.torch
+        out = t.empty(self.groups, dtype=t.int64, device=self.device)
+        _abi.check(_lib().bwg_ensemble_read_blocked(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                                    self._stream()))
         return out
 
     def read_events(self):

@@ -22,6 +22,8 @@ BWG_ENGINE_BITWISE = 0
 BWG_ENGINE_PLAIN = 1
 BWG_INIT_FIXED = 0
 BWG_INIT_MULTINOMIAL = 1
+BWG_INIT_UNIFORM_SITE = 2
+BWG_INIT_SITES = 3
 
 # Every symbol include/bwg.h declares.
 SYMBOLS = (
@@ -33,6 +35,7 @@ SYMBOLS = (
     "bwg_batch_advance", "bwg_batch_graph_advance", "bwg_batch_destroy",
     "bwg_ensemble_schedule", "bwg_ensemble_run", "bwg_ensemble_pending",
     "bwg_batch_capacity_bytes", "bwg_batch_set_members", "bwg_batch_run",
+    "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
 )
 
 
@@ -53,6 +56,13 @@ class QNet(ctypes.Structure):
                 ("B", ctypes.c_int32), ("b", ctypes.c_int32), ("gpu_ok", ctypes.c_int32),
                 ("s", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("max_total", ctypes.c_int64)]
+
+
+class LatticeInfo(ctypes.Structure):
+    _fields_ = [("lx", ctypes.c_int32), ("ly", ctypes.c_int32), ("sites", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("T", ctypes.c_int32), ("B_r", ctypes.c_int32),
+                ("c_hop", ctypes.c_int64), ("C", ctypes.c_uint64), ("max_site", ctypes.c_int64),
+                ("s", ctypes.c_double), ("lambda_", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -120,6 +130,9 @@ def load():
         "bwg_batch_capacity_bytes": (i32, [i32, u64, P(u64)]),
         "bwg_batch_set_members": (i32, [vp, P(vp), i32, vp]),
         "bwg_batch_run": (i32, [vp, u64, vp]),
+        "bwg_net_lattice": (i32, [vp, P(LatticeInfo)]),
+        "bwg_ensemble_read_sites": (i32, [vp, u64, u64, vp, vp]),
+        "bwg_ensemble_read_blocked": (i32, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -85,6 +85,8 @@ static int check_members(bwg_ens *const *ens, int32_t n, uint64_t *items)
         if (!e) return fail(BWG_EINVAL, "null ensemble %d", k);
         if (e->engine != BWG_ENGINE_BITWISE)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: batches run the bit-sliced engine", k);
+        if (e->lat)
+            return fail(BWG_EUNSUPPORTED, "ensemble %d: lattices run their own launches", k);
         if (pick_bucket(e) < 0)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: no persistent bucket for b=%d B=%d", k,
                         e->net->q.b, e->net->q.B);

@@ -12,6 +12,7 @@ enum : uint32_t {
     DOM_BUDGET = 2,
     DOM_INIT = 3,
     DOM_PLAIN = 4,
+    DOM_COMPONENT = 5,
 };
 
 // Frank-family structure recognised for the bit-sliced kernel: the reaction
@@ -111,6 +112,71 @@ hipError_t launch_persistent(const BatchEns *ens, const BatchItem *items, uint32
 hipError_t launch_batch_budget(const BatchBudget *bb, int n_ens, uint64_t total, hipStream_t s);
 hipError_t launch_batch_prologue(uint32_t *counter, hipStream_t s);
 hipError_t launch_batch_epilogue(const BatchBudget *bb, int n_ens, hipStream_t s);
+
+// ---- lattices ----
+// Component schedule geometry: a group of LAT_GROUP_WORDS words (2048
+// replicas) shares one component sequence; it is cut into chunks of LAT_CH
+// events, each sorted into at most LAT_CH layers; a pass schedules and runs
+// up to LAT_NCB chunks.
+constexpr int LAT_GROUP_WORDS = 64;
+constexpr int LAT_CH = 8192;
+constexpr int LAT_NCB = 16;
+constexpr int LAT_SLOT = 3 * LAT_CH + 64;   // uint32 per (group, chunk) slot
+constexpr int LAT_MAX_SITES = 4096;
+
+struct LatShape {
+    int32_t lx, ly, S, P;
+    int32_t B_r;            // threshold planes of a reaction component
+    int32_t wx;             // planes of cu * A (A <= 2^P - 1)
+    uint64_t cu;            // weight of A -> L and of A -> D
+    uint64_t ca;            // weight of A + L -> 2L and of A + D -> 2D
+    uint64_t ci;            // weight of L + D -> 2A
+    uint64_t W_R;           // reaction component weight 2^B_r
+    uint64_t W_H;           // hop component weight (T + 1) c_hop
+    uint64_t Wsite;         // W_R + 4 W_H
+    uint64_t C;             // S Wsite
+    uint64_t thresh;        // 2^64 mod C
+};
+
+struct LatArgs {
+    uint32_t *planes;       // [words][S][3][P]
+    const uint64_t *E;      // [32 words] events done before this advance
+    const uint64_t *Et;     // [32 words] events to reach
+    uint64_t *real;         // [words] real events (moves and reactions)
+    uint64_t *blocked;      // [words] hops into full sites
+    uint32_t *sched;        // [groups][LAT_NCB][LAT_SLOT]
+    uint64_t M;
+    uint64_t seed;
+    uint64_t base;          // first event of chunk 0 of the advance
+    uint32_t chunk0;        // first chunk of this pass
+    uint32_t n_chunks;      // chunks in this pass (<= LAT_NCB)
+    uint32_t net_id;
+    uint32_t pad;
+    LatShape sh;
+};
+
+using LatLaunch = hipError_t (*)(const LatArgs &, uint64_t words, hipStream_t);
+// Event-kernel instantiations: species planes P, threshold-plane capacity
+// bc and the weights cu, ca, ci (-1: taken at run time).
+struct LatVariant {
+    int P, bc;
+    int64_t cu, ca, ci;
+    LatLaunch fn;
+};
+extern const LatVariant kLatVariants[];
+extern const int kLatVariantCount;
+
+hipError_t launch_lat_init(uint32_t *planes, uint64_t words, uint64_t M, int S, int P, int mode,
+                           const int32_t *sites_dev, const int32_t c3[3], int32_t lo, int32_t hi,
+                           uint64_t seed, uint32_t net_id, uint64_t *E, uint64_t *Et,
+                           uint64_t *real, uint64_t *blocked, hipStream_t s);
+hipError_t launch_lat_schedule(const LatArgs &a, uint32_t n_groups, hipStream_t s);
+hipError_t launch_lat_totals(const uint32_t *planes, uint64_t M, int S, int P, int32_t *dst,
+                             hipStream_t s);
+hipError_t launch_lat_sites(const uint32_t *planes, int S, int P, uint64_t first, uint64_t count,
+                            int32_t *dst, hipStream_t s);
+hipError_t launch_lat_histogram(const int32_t *tot, uint64_t M, int n_bins, uint64_t *dst,
+                                hipStream_t s);
 
 hipError_t launch_init_fixed(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
                              const int32_t counts[3], uint64_t *E, uint64_t *Etgt,

@@ -162,9 +162,9 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     if (R < 1 || R > BWG_MAX_REACTIONS) return fail(BWG_EINVAL, "n_reactions %d out of range", R);
     if (!d->reactants || !d->products || !d->rates) return fail(BWG_EINVAL, "null table");
     if (d->n_tot < 1) return fail(BWG_EINVAL, "n_tot must be >= 1");
-    if (d->lx || d->ly) return fail(BWG_EUNSUPPORTED, "lattice networks are not available");
+    const bool lattice = d->lx || d->ly;
     if (S != 3) return fail(BWG_EUNSUPPORTED, "the GPU engines implement 3 species");
-    if (d->n_tot >= (1ll << 14)) return fail(BWG_ERANGE, "n_tot beyond 14 count planes");
+    if (!lattice && d->n_tot >= (1ll << 14)) return fail(BWG_ERANGE, "n_tot beyond 14 count planes");
     auto n = new bwg_net();
     n->S = S;
     n->R = R;
@@ -197,10 +197,21 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
             return fail(BWG_EINVAL, "reaction %d: rate must be finite and >= 0", j);
         }
     }
+    n->q.n_species = S;
+    n->q.n_reactions = R;
+    if (lattice) {
+        n->lx = d->lx;
+        n->ly = d->ly;
+        const int rc = lat_net_setup(n, d);
+        if (rc) {
+            delete n;
+            return rc;
+        }
+        *out = n;
+        return BWG_OK;
+    }
     // ---- quantisation: integer weights c_j = rint(k_j s), s = 2^f / k_ref
     bwg_qnet &q = n->q;
-    q.n_species = S;
-    q.n_reactions = R;
     const int prec = d->precision_bits > 0 ? d->precision_bits : 7;
     if (d->flags & BWG_EXACT_INTEGER) {
         for (int j = 0; j < R; ++j) {
@@ -413,10 +424,15 @@ extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_
     if (!n || !bytes) return fail(BWG_EINVAL, "null argument");
     if (M == 0 || M >= (1ull << 32)) return fail(BWG_EINVAL, "replica count out of range");
     const int engine = o ? o->engine : BWG_ENGINE_BITWISE;
+    const uint64_t cap = (o && o->table_capacity) ? o->table_capacity : 65536;
+    if (n->lat) {
+        if (engine != BWG_ENGINE_BITWISE)
+            return fail(BWG_EUNSUPPORTED, "lattices run on the bit-sliced engine only");
+        return lat_state_bytes(n, M, cap, bytes);
+    }
     const WmVariant *v;
     int rc = check_engine(n, engine, &v);
     if (rc) return rc;
-    const uint64_t cap = (o && o->table_capacity) ? o->table_capacity : 65536;
     *bytes = layout(n, M, engine, cap, v).total;
     return BWG_OK;
 }
@@ -443,6 +459,13 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->block = o ? o->block : 0;
     e->table_cap = (o && o->table_capacity) ? o->table_capacity : 65536;
     e->epl = o ? o->events_per_launch : 0;
+    e->buf = (uint8_t *)dev_buf;
+    e->bytes = buf_bytes;
+    if (n->lat) {
+        lat_bind(e);
+        *out = e;
+        return BWG_OK;
+    }
     check_engine(n, e->engine, &e->var);
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
@@ -470,6 +493,7 @@ extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     hipStream_t s = (hipStream_t)stream;
     const bwg_net *n = e->net;
+    if (e->lat) return lat_init(e, mode, counts, s);
     int32_t c[3] = {0, 0, 0};
     if (mode == BWG_INIT_FIXED) {
         if (!counts) return fail(BWG_EINVAL, "fixed init needs counts");
@@ -607,6 +631,7 @@ int bwg::schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *km
 extern "C" int bwg_ensemble_schedule(bwg_ens *e, double t_end, void *stream)
 {
     if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (e->lat) return lat_schedule(e, t_end, (hipStream_t)stream);
     uint64_t kmin, kmax;
     int rc = schedule_ensemble(e, t_end, (hipStream_t)stream, &kmin, &kmax);
     if (rc) return rc;
@@ -618,6 +643,7 @@ extern "C" int bwg_ensemble_run(bwg_ens *e, uint64_t max_events, void *stream)
 {
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
+    if (e->lat) return lat_run(e, max_events, (hipStream_t)stream);
     return launch_events(e, max_events, (hipStream_t)stream);
 }
 
@@ -632,6 +658,10 @@ extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
 {
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     hipStream_t s = (hipStream_t)stream;
+    if (e->lat) {
+        const int rc = lat_schedule(e, t_end, s);
+        return rc ? rc : lat_run(e, 0, s);
+    }
     uint64_t kmin, kmax;
     int rc = schedule_ensemble(e, t_end, s, &kmin, &kmax);
     if (rc) return rc;
@@ -644,6 +674,10 @@ extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     hipStream_t s = (hipStream_t)stream;
+    if (e->lat) {
+        const int rc = lat_step_schedule(e, n_events, s);
+        return rc ? rc : lat_run(e, 0, s);
+    }
     HIP_TRY(launch_budget(nullptr, 0, 0, n_events, 0, e->seed, e->net_id, e->adv_dev, e->M, e->E,
                           e->Et, s));
     note_scheduled(e, n_events, n_events);
@@ -654,6 +688,7 @@ extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)
 {
     if (!e || !dst) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
+    if (e->lat) return lat_read_counts(e, dst, s);
     if (e->engine == BWG_ENGINE_BITWISE)
         HIP_TRY(launch_read_counts_planes(e->planes, e->nb, e->wp, e->M, dst, s));
     else
@@ -666,6 +701,7 @@ extern "C" int bwg_ensemble_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst,
     if (!e || !dst) return fail(BWG_EINVAL, "null argument");
     if (n_bins < 1 || n_bins > 16384) return fail(BWG_EINVAL, "n_bins %d out of range", n_bins);
     hipStream_t s = (hipStream_t)stream;
+    if (e->lat) return lat_histogram(e, n_bins, dst, s);
     HIP_TRY(launch_histogram(e->engine == BWG_ENGINE_BITWISE ? e->planes : nullptr, e->counts,
                              e->nb, e->wp, e->M, e->net->n_tot, n_bins, dst, s));
     return BWG_OK;

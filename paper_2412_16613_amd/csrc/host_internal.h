@@ -43,6 +43,13 @@ struct bwg_net {
     bool shape_ok = false;
     bwg::PlainReaction prx[16]{};
     bool plain_ok = false;
+    // lattice networks
+    bool lat = false;
+    bwg::LatShape lsh{};
+    int64_t c_lat[5]{};         // weights of the five Frank reactions
+    int64_t c_hop = 0;
+    int32_t T = 0;              // site capacity 2^P - 1
+    bool lat_gpu = false;       // the event kernel implements this table
     std::mutex mu;
     std::map<uint64_t, Table> tables;  // keyed by the bits of mu
     ~bwg_net()
@@ -72,6 +79,16 @@ struct bwg_ens {
     uint64_t lag = 0;      // bound on how far a word's lanes can be apart
     uint64_t pending = 0;  // bound on the events any word still has to run
     bool inited = false;
+    // lattice ensembles
+    bool lat = false;
+    const bwg::LatVariant *lvar = nullptr;
+    uint64_t words = 0, groups = 0;
+    uint32_t *sched = nullptr;
+    uint64_t *blocked = nullptr;
+    int32_t *tot = nullptr;          // [32 words][3] species totals
+    int32_t *sites_dev = nullptr;    // [S][3] staging of an initial lattice
+    uint64_t emin = 0, emax = 0;     // bounds on min_i E_i and max_i E_i
+    uint64_t base = 0, n_chunks = 0, cursor = 0;  // chunk window of the advance
 };
 
 
@@ -84,4 +101,15 @@ int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, u
 void note_scheduled(bwg_ens *e, uint64_t kmin, uint64_t kmax);
 // Bookkeeping after a pass that ran up to max_events per word (0: all).
 void note_ran(bwg_ens *e, uint64_t max_events);
+
+// Lattice networks and ensembles (lattice_host.cpp).
+int lat_net_setup(bwg_net *n, const bwg_net_desc *d);
+int lat_state_bytes(const bwg_net *n, uint64_t M, uint64_t table_cap, uint64_t *bytes);
+int lat_bind(bwg_ens *e);
+int lat_init(bwg_ens *e, int32_t mode, const int32_t *counts, hipStream_t s);
+int lat_schedule(bwg_ens *e, double t_end, hipStream_t s);
+int lat_step_schedule(bwg_ens *e, uint64_t n_events, hipStream_t s);
+int lat_run(bwg_ens *e, uint64_t max_events, hipStream_t s);
+int lat_read_counts(bwg_ens *e, int32_t *dst, hipStream_t s);
+int lat_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst, hipStream_t s);
 }

@@ -106,10 +106,6 @@ def test_invalid_networks_are_rejected():
     with pytest.raises(bwg.BwgError) as e:
         bwg.Network(huge)
     assert e.value.code == _abi.BWG_ERANGE
-    lat = frank_network(12, lx=4, ly=4, hop=0.1, site_planes=4)
-    with pytest.raises(bwg.BwgError) as e:
-        bwg.Network(lat)
-    assert e.value.code == _abi.BWG_EUNSUPPORTED
 
 
 def test_non_frank_order_is_plain_only():
@@ -144,3 +140,73 @@ def test_state_bytes_scale_with_replicas():
     assert sizes[3] >= (3 * 11 * 4 + 16 * 32) * (1 << 15)
     b = ctypes.c_uint64()
     assert _abi.load().bwg_ensemble_state_bytes(n.handle, 0, None, ctypes.byref(b)) == _abi.BWG_EINVAL
+
+
+# ---- lattices ----------------------------------------------------------------
+
+def _lat_cmp(net):
+    from oracle.lattice import quantize_lattice
+    n = bwg.Network(net)
+    li, q = n.lattice(), n.quantized()
+    o = quantize_lattice(net)
+    assert q["c"] == o["c"] and q["f"] == o["f"] and q["s"] == o["s"]
+    assert li["c_hop"] == o["c_hop"] and li["B_r"] == o["B_r"] and li["T"] == o["T"]
+    assert li["C"] == o["C"] and li["max_site"] == o["max_site"]
+    assert li["Lambda"] == o["Lambda"] == q["Lambda"]
+    return n
+
+
+def test_lattice_quantisation_matches_oracle():
+    n = _lat_cmp(frank_network(12, lx=64, ly=64, hop=0.1, site_planes=4))
+    assert n.quantized()["gpu_ok"]
+    assert n.lattice()["C"] == 4096 * ((1 << 18) + 64 * 2458)
+    for side in (1, 2, 5, 16, 33):
+        _lat_cmp(frank_network(12, lx=side, ly=max(1, side // 2), hop=0.1, site_planes=4))
+    _lat_cmp(frank_network(1, k0=0.0, k1=0.0, k2=0.0, lx=5, ly=3, hop=0.1, site_planes=4))
+    _lat_cmp(frank_network(4, k0=0.25, k1=1.0, k2=1.0, lx=2, ly=1, hop=0.5, site_planes=2))
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        k = 10.0 ** rng.uniform(-3, 0, 4)
+        _lat_cmp(frank_network(12, k0=float(k[0]), k1=float(k[1]), k2=float(k[2]), lx=8, ly=8,
+                               hop=float(k[3]), site_planes=4))
+
+
+def test_invalid_lattices_are_rejected():
+    def code(net):
+        with pytest.raises(bwg.BwgError) as ei:
+            bwg.Network(net)
+        return ei.value.code
+    assert code(frank_network(12, lx=65, ly=64, hop=0.1, site_planes=4)) == _abi.BWG_ERANGE
+    assert code(frank_network(12, lx=8, ly=8, hop=0.1, site_planes=0)) == _abi.BWG_ERANGE
+    bad = frank_network(12, lx=8, ly=8, hop=0.1, site_planes=4)
+    bad["hop_rates"] = [0.1, 0.2, 0.1]
+    assert code(bad) == _abi.BWG_EUNSUPPORTED
+    swapped = frank_network(12, lx=8, ly=8, hop=0.1, site_planes=4)
+    swapped["reactants"] = swapped["reactants"][::-1]
+    swapped["products"] = swapped["products"][::-1]
+    assert code(swapped) == _abi.BWG_EUNSUPPORTED
+    neg = frank_network(12, lx=8, ly=8, hop=-0.1, site_planes=4)
+    assert code(neg) == _abi.BWG_EINVAL
+    # no event kernel for 3-plane sites: the network exists, ensembles do not
+    n3 = bwg.Network(frank_network(6, lx=4, ly=4, hop=0.1, site_planes=3))
+    assert not n3.quantized()["gpu_ok"]
+    nb = ctypes_u64()
+    rc = _abi.load().bwg_ensemble_state_bytes(n3.handle, 64, None, nb)
+    assert rc == _abi.BWG_EUNSUPPORTED
+    # a well-mixed network has no lattice form
+    with pytest.raises(bwg.BwgError):
+        bwg.Network(frank_network(12)).lattice()
+
+
+def ctypes_u64():
+    import ctypes
+    return ctypes.byref(ctypes.c_uint64())
+
+
+def test_lattice_state_bytes():
+    import ctypes
+    n = bwg.Network(frank_network(12, lx=64, ly=64, hop=0.1, site_planes=4))
+    b = ctypes.c_uint64()
+    _abi.check(_abi.load().bwg_ensemble_state_bytes(n.handle, 1 << 16, None, ctypes.byref(b)))
+    planes = 2048 * 4096 * 12 * 4
+    assert planes <= b.value < planes + (64 << 20)
