@@ -37,6 +37,29 @@ def word_event_slots(b, B, f, cu_bits):
 
 VALU_PEAK = 256 * 128 * 2.4e9   # 32-bit lane-slots/s: 256 CUs x 128 lanes/clk x 2.4 GHz
 
+# HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
+# (the factors of a 1 GiB copy), valid only for the sources they were taken on:
+# kernel -> (sha1 prefix of its sources, sources, bytes per launch, summary file).
+CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
+MEASURED_TRAFFIC = {
+    "wm_event_kernel": ("a291580fbca6", ("bitops.h", "wm_device.h", "wm_kernel.hip"),
+                        34007 * 1024, "profiles/wm_event_kernel_frank1024_2p20.md"),
+}
+
+
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes per launch, or None once the kernel's
+    sources differ from the ones the counters were taken on."""
+    import hashlib
+    if kernel not in MEASURED_TRAFFIC:
+        return None
+    sha, files, nbytes, _ = MEASURED_TRAFFIC[kernel]
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return nbytes if h.hexdigest()[:12] == sha else None
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -46,8 +69,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=65536)
-    ap.add_argument("--workload", default="well-mixed", choices=["well-mixed", "batch", "serve"],
-                    help="batch: the 256 uneven networks in one persistent launch")
+    ap.add_argument("--cpu-replicas-lattice", type=int, default=64)
+    ap.add_argument("--workload", default="well-mixed",
+                    choices=["well-mixed", "lattice", "batch", "serve"],
+                    help="lattice: 64x64 compartments, 2^16 replicas; batch: the 256 uneven "
+                         "networks in one persistent launch")
     ap.add_argument("--batch-nets", type=int, default=256)
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
@@ -75,6 +101,8 @@ def main():
     from workloads import config
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "lattice":
+        return bench_lattice(args)
     if args.workload == "serve":
         return bench_serve(args)
 
@@ -155,7 +183,8 @@ def main():
         "replica_time_per_s": M * t_end * args.steps / (r["ms"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
-                     "traffic": None, "kernel": "wm_event_kernel",
+                     "traffic": measured_traffic("wm_event_kernel"), "traffic_unit": "B/launch",
+                     "kernel": "wm_event_kernel",
                      "kernel_ms": adv_avg_ms, "slots_per_word_event": slots},
     }
     if not args.no_plain:
@@ -167,6 +196,111 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, c, args.cpu_replicas)
     print(json.dumps(out))
+
+
+def lattice_slots(q, li):
+    """VALU issue slots per word-event of the lattice kernel: (reaction, hop).
+    Reaction: ceil(B_r/4) Philox calls, the weights cu A (shift-adds over its
+    set bits into B_r + 1 planes), three P x P products, three shifted adds
+    and five B_r + 1 plane comparisons, masks and the masked +-1 updates; hop:
+    one Philox call, two P-plane sums per site, three comparisons, the full
+    test and six masked +-1 updates."""
+    P, Br = li["P"], li["B_r"]
+    BC = Br + 1
+    cu = q["c"][0]
+    wx = (cu * ((1 << P) - 1)).bit_length()
+    shifts = [k for k in range(BC) if (cu >> k) & 1]
+    cu_adds = sum(2 * (wx - k) for k in shifts[1:])      # the first is a copy
+    product = 4 * P + (P - 1) * (3 * P + 1)              # ANDs + P-plane ripple per row
+    ca_add = 2 * (BC - (q["c"][2].bit_length() - 1))
+    react = (-(-Br // 4)) * PHILOX_SLOTS + cu_adds + 5 * BC + 3 * (product + ca_add) + 8 + 3 * 2 * P
+    hop = PHILOX_SLOTS + 4 * 2 * P + 3 * P + (P - 1) + 6 + 6 * 2 * P
+    return react, hop
+
+
+def bench_lattice(args):
+    """64 x 64 periodic lattice of Frank reactors (12 molecules per site on
+    average, 4 planes per species per site), hops at d = 0.1, A uniform in
+    {9..15} per site, 2^16 replicas, t_end = 20.  One step = init + advance
+    + species totals + ee histogram."""
+    import torch
+    import paper_2412_16613_amd as bwg
+    from workloads import config
+    c = config("c2")
+    net, M, t_end = c["net"], c["replicas"], c["t_end"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    network = bwg.Network(net)
+    q, li = network.quantized(), network.lattice()
+    ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], device=dev)
+    counts = torch.empty((M, 3), dtype=torch.int32, device=dev)
+    hist = torch.empty(256, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        ens.init(c["init"]).advance(t_end)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    adv = []
+    t0.record(stream)
+    for _ in range(args.steps):
+        ens.init(c["init"])
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ens.advance(t_end)
+        b.record(stream)
+        adv.append((a, b))
+        ens.read_counts(counts)
+        ens.histogram(256, hist)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    adv_ms = sum(a.elapsed_time(b) for a, b in adv) / len(adv)
+    st = ens.stats()
+    assert int(hist.sum().item()) == M
+    events = st["events_total"]
+    value = events * args.steps / (ms / 1e3)
+    react, hop = lattice_slots(q, li)
+    W_R, W_H = 1 << li["B_r"], ((li["T"] + 1) * li["c_hop"])
+    f_r = W_R / (W_R + 4 * W_H)
+    slots = f_r * react + (1 - f_r) * hop
+    achieved = slots * (events / 32.0) / (adv_ms / 1e3)
+    out = {
+        "metric": "replica-events/sec (bit-parallel lattice, 1 GPU)",
+        "value": value, "unit": "replica-events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 bit-planes", "data": "synthetic",
+        "config": {"workload": "64x64 periodic lattice of Frank reactors, 12 per site on "
+                               "average (A uniform 9..15), d=0.1, 2^16 replicas, t_end=20, "
+                               "seed 0",
+                   "sites": li["sites"], "replicas": M, "t_end": t_end, "site_planes": li["P"],
+                   "reaction_planes": li["B_r"]},
+        "real_events_per_s": st["real_total"] * args.steps / (ms / 1e3),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "kernel": "lat_event_kernel (+ lat_schedule_kernel, one pass)",
+                     "kernel_ms": adv_ms, "slots_per_word_event": slots,
+                     "slots_reaction": react, "slots_hop": hop},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_lattice(c, args.cpu_replicas_lattice)
+    print(json.dumps(out))
+
+
+def cpu_baseline_lattice(c, n_rep):
+    from oracle.lattice import OracleLattice
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    o = OracleLattice(c["net"], c["replicas"], seed=c["seed"], net_id=c["net_id"], first=0,
+                      count=n_rep, threads=threads)
+    o.init(c["init"])
+    t = time.perf_counter()
+    o.advance(c["t_end"])
+    dt = time.perf_counter() - t
+    ev = int(o.E.sum())
+    return {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d replicas, full t_end (%d events, %.1f s)"
+                      % (n_rep, c["replicas"], ev, dt)}
 
 
 def bench_batch(args):
@@ -242,21 +376,24 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Served stream: Poisson arrivals (200/s for 60 s by default) of Frank
-    networks drawn like the uneven batch, admitted by HBM budget into one
-    continuously batched persistent launch; p50/p99 latency and throughput."""
+    networks drawn like the uneven batch, 30 % of them lattices of side
+    16..64, admitted by HBM budget; well-mixed requests share one continuously
+    batched persistent launch, lattices run beside it; p50/p99 latency and
+    throughput."""
     from paper_2412_16613_amd.serve import Server, summarize
     from workloads import serve_requests
-    reqs = [r for r in serve_requests(rate=args.rate, duration=args.duration)
-            if not r["net"].get("lx")]
+    reqs = serve_requests(rate=args.rate, duration=args.duration)
+    n_lat = sum(1 for r in reqs if r["net"].get("lx"))
     srv = Server(chunk=args.chunk)
     res = srv.serve(reqs, real_time=True)
     s = summarize(res, srv.stats)
     out = {"metric": "p50/p99 request latency and replica-events/sec (served stream, 1 GPU)",
            "value": s["replica_events_per_s"], "unit": "replica-events/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "u32 bit-planes", "data": "synthetic",
-           "config": {"workload": "Poisson arrivals %.0f/s for %.0f s, well-mixed requests"
+           "config": {"workload": "Poisson arrivals %.0f/s for %.0f s, 30%% lattice variants"
                                   % (args.rate, args.duration),
-                      "requests": len(reqs), "chunk_events": args.chunk},
+                      "requests": len(reqs), "lattice_requests": n_lat,
+                      "chunk_events": args.chunk, "lattice_chunk_events": srv.lattice_chunk},
            "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
            "summary": s}
     print(json.dumps(out))

@@ -139,7 +139,7 @@ struct LatShape {
 };
 
 struct LatArgs {
-    uint32_t *planes;       // [words][S][3][P]
+    uint32_t *planes;       // [groups][S][64 words][3][P]
     const uint64_t *E;      // [32 words] events done before this advance
     const uint64_t *Et;     // [32 words] events to reach
     uint64_t *real;         // [words] real events (moves and reactions)
@@ -157,10 +157,12 @@ struct LatArgs {
 
 using LatLaunch = hipError_t (*)(const LatArgs &, uint64_t words, hipStream_t);
 // Event-kernel instantiations: species planes P, threshold-plane capacity
-// bc and the weights cu, ca, ci (-1: taken at run time).
+// bc, the weights cu, ca, ci (-1: taken at run time) and the words per
+// workgroup slice ws.
 struct LatVariant {
     int P, bc;
     int64_t cu, ca, ci;
+    int ws;
     LatLaunch fn;
 };
 extern const LatVariant kLatVariants[];

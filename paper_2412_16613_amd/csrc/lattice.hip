@@ -78,8 +78,23 @@ __device__ __forceinline__ uint32_t lat_neighbour(const LatShape &sh, uint32_t s
     return y * (uint32_t)sh.lx + x;
 }
 
+// ---- layout ----------------------------------------------------------------
+// Site planes of word w in group g = w / 64: a group stores, site by site, the
+// 3P planes of each of its 64 words (padded), so the planes of one site of
+// consecutive words are contiguous:
+//   planes[((g S + s) 64 + (w mod 64)) 3P + x P + q],  species x in (L, D, A).
+__device__ __forceinline__ uint32_t *site_planes(uint32_t *planes, uint64_t w, uint32_t s,
+                                                 int S, int NP)
+{
+    return planes + (((w >> 6) * (uint64_t)S + s) * 64 + (w & 63)) * (uint64_t)NP;
+}
+__device__ __forceinline__ const uint32_t *site_planes(const uint32_t *planes, uint64_t w,
+                                                       uint32_t s, int S, int NP)
+{
+    return planes + (((w >> 6) * (uint64_t)S + s) * 64 + (w & 63)) * (uint64_t)NP;
+}
+
 // ---- initial states -------------------------------------------------------------
-// Site planes of word w: planes[((w S + s) 3 + x) P + q], species x in (L, D, A).
 
 // mode 0: every site of every replica holds site[s] (sites = null: site0 for
 // all sites); one thread per (word, site).
@@ -98,7 +113,7 @@ __global__ void lat_init_fixed_kernel(uint32_t *planes, uint64_t words, uint64_t
         c[1] = sites[3 * s + 1];
         c[2] = sites[3 * s + 2];
     }
-    uint32_t *p = planes + ((uint64_t)w * S + s) * 3 * P;
+    uint32_t *p = site_planes(planes, w, s, S, 3 * P);
     for (int x = 0; x < 3; ++x)
         for (int q = 0; q < P; ++q) p[x * P + q] = ((c[x] >> q) & 1) ? live : 0u;
     if (s == 0) {
@@ -128,7 +143,7 @@ __global__ void lat_init_uniform_kernel(uint32_t *planes, uint64_t words, uint64
     for (int q = 0; q < P; ++q) {
         const uint64_t bits = __ballot(ok && ((a >> q) & 1));
         if ((lane & 31) == 0 && w < words) {
-            uint32_t *p = planes + ((uint64_t)w * S + s) * 3 * P;
+            uint32_t *p = site_planes(planes, w, s, S, 3 * P);
             p[q] = 0u;
             p[P + q] = 0u;
             p[2 * P + q] = lane ? (uint32_t)(bits >> 32) : (uint32_t)bits;
@@ -457,16 +472,15 @@ __device__ __forceinline__ void event_planes(uint32_t (&n)[BC], uint64_t seed, u
     }
 }
 
-// Reaction component of site p for the lanes in act; returns the lanes whose
-// state changed.
+// Reaction component of site p (planes l, d, x already loaded) for the
+// lanes in act; returns the lanes whose state changed.
 template <int P, int BC, int64_t CU, int64_t CA, int64_t CI>
-__device__ __forceinline__ uint32_t lat_reaction(uint32_t *p, const LatArgs &a, uint32_t G,
+__device__ __forceinline__ uint32_t lat_reaction(uint32_t *p, uint32_t (&l)[P], uint32_t (&d)[P],
+                                                 uint32_t (&x)[P], const LatArgs &a, uint32_t G,
                                                  uint64_t e, uint32_t act)
 {
     constexpr int WP = 2 * P;
     const LatShape &sh = a.sh;
-    uint32_t l[P], d[P], x[P];
-    load_site<P>(p, l, d, x);
     uint32_t n[BC];
     event_planes<BC>(n, a.seed, a.net_id, G, e, sh.B_r);
 
@@ -506,17 +520,18 @@ __device__ __forceinline__ uint32_t lat_reaction(uint32_t *p, const LatArgs &a, 
     return ch;
 }
 
-// Hop component out of site p into site p2 (p2 == p: the lattice is one site
-// wide along that axis and the hop changes nothing).  Adds the lanes that
-// moved to *moved and the lanes blocked by a full destination to *blocked.
+// Hop component out of site p into site p2 (planes already loaded; p2 == p:
+// the lattice is one site wide along that axis and the hop changes
+// nothing).  Sets the lanes that moved and the lanes blocked by a full
+// destination.
 template <int P>
-__device__ __forceinline__ void lat_hop(uint32_t *p, uint32_t *p2, bool self, const LatArgs &a,
+__device__ __forceinline__ void lat_hop(uint32_t *p, uint32_t *p2, bool self, uint32_t (&l)[P],
+                                        uint32_t (&d)[P], uint32_t (&x)[P], uint32_t (&l2)[P],
+                                        uint32_t (&d2)[P], uint32_t (&x2)[P], const LatArgs &a,
                                         uint32_t G, uint64_t e, uint32_t act, uint32_t &moved,
                                         uint32_t &blocked)
 {
     static_assert(P <= 4, "hop index from one Philox quad");
-    uint32_t l[P], d[P], x[P];
-    load_site<P>(p, l, d, x);
     uint32_t o[4];
     philox4x32_10((uint32_t)e, (DOM_EVENT << 24) | ((uint32_t)(e >> 32) & 0xFFFFu), G, a.net_id,
                   (uint32_t)a.seed, (uint32_t)(a.seed >> 32), o[0], o[1], o[2], o[3]);
@@ -530,17 +545,6 @@ __device__ __forceinline__ void lat_hop(uint32_t *p, uint32_t *p2, bool self, co
     const uint32_t cAL = less_than_w<P>(j, al);
     const uint32_t any = less_than_w<P>(j, tot) & act;
     const uint32_t sA = hA & act, sL = cAL & ~hA & act, sD = any & ~cAL;
-    uint32_t l2[P], d2[P], x2[P];
-    if (self) {
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            l2[q] = l[q];
-            d2[q] = d[q];
-            x2[q] = x[q];
-        }
-    } else {
-        load_site<P>(p2, l2, d2, x2);
-    }
     uint32_t t2[P], full = ~0u;
     add_w<P>(t2, x2, l2);
     add_w<P>(t2, t2, d2);
@@ -571,36 +575,47 @@ __device__ __noinline__ uint32_t lanes_at(const uint64_t *sE, const uint64_t *sE
     return act;
 }
 
-#ifndef LAT_MIN_WAVES
-#define LAT_MIN_WAVES 2
-#endif
-
-// One workgroup per word: run the events of chunks chunk0 .. chunk0+n_chunks-1
-// layer by layer.
-template <int P, int BC, int64_t CU, int64_t CA, int64_t CI>
-__global__ __launch_bounds__(256, LAT_MIN_WAVES) void lat_event_kernel(LatArgs a)
+// One workgroup per slice of WS consecutive words of a group, BLOCK
+// threads: thread t works on word t mod WS of the slice and on every
+// (BLOCK / WS)-th event of a layer, so the WS words of one event read
+// WS * 12 contiguous planes.  Slices are spread so that the slices of a
+// group run on one XCD (workgroups go to the 8 XCDs in turn), where they
+// share the group's schedule in L2.  Runs the events of chunks chunk0 ..
+// chunk0+n_chunks-1 layer by layer.
+template <int P, int BC, int64_t CU, int64_t CA, int64_t CI, int WS, int BLOCK>
+__global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
 {
     constexpr int NP = 3 * P;
-    const uint64_t w = blockIdx.x;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t g = (uint32_t)(w / LAT_GROUP_WORDS);
-    __shared__ uint64_t sE[32], sEt[32];
-    __shared__ uint32_t sred[2][8];
+    constexpr int NSL = LAT_GROUP_WORDS / WS;   // slices per group
+    constexpr int EV = BLOCK / WS;              // events in flight per workgroup
+    const uint32_t nwg = (uint32_t)(((a.M + 31) / 32 + LAT_GROUP_WORDS - 1) / LAT_GROUP_WORDS) * NSL;
+    const uint32_t per_xcd = (nwg + 7) / 8;
+    const uint32_t v = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (v >= nwg) return;
+    const uint32_t g = v / NSL;
+    const uint64_t w0 = (uint64_t)g * LAT_GROUP_WORDS + (v % NSL) * WS;
+    const uint64_t words = (a.M + 31) / 32;
+    if (w0 >= words) return;
+    const uint32_t tid = threadIdx.x, lw = tid % WS, slot = tid / WS;
+    const uint64_t w = w0 + lw;
+    __shared__ uint64_t sE[WS][32], sEt[WS][32];
+    __shared__ uint32_t sred[2][WS];
 
-    const uint64_t rem = a.M - 32 * w;
-    const uint32_t live = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
-    if (tid < 32) {
-        const bool ok = (live >> tid) & 1u;
-        sE[tid] = ok ? a.E[32 * w + tid] : 0;
-        sEt[tid] = ok ? a.Et[32 * w + tid] : 0;
+    for (uint32_t i = tid; i < WS * 32; i += BLOCK) {
+        const uint64_t r = 32 * w0 + i;
+        const bool ok = r < a.M;
+        sE[i / 32][i % 32] = ok ? a.E[r] : 0;
+        sEt[i / 32][i % 32] = ok ? a.Et[r] : 0;
     }
+    if (tid < 2 * WS) sred[tid / WS][tid % WS] = 0;
     __syncthreads();
-    // window over pending lanes (E < Et): [lo, hi) holds every event of the
-    // word, [blo, bhi) the events every pending lane runs
-    uint64_t lo = ~0ull, hi = 0, blo = 0, bhi = ~0ull;
+    // window of this thread's word over its pending lanes (E < Et): [lo, hi)
+    // holds every event of the word, [blo, bhi) the events every pending
+    // lane runs; [wlo, whi) the union over the slice
+    uint64_t lo = ~0ull, hi = 0, blo = 0, bhi = ~0ull, wlo = ~0ull, whi = 0;
     uint32_t pend = 0;
     for (int l = 0; l < 32; ++l) {
-        const uint64_t e0 = sE[l], e1 = sEt[l];
+        const uint64_t e0 = sE[lw][l], e1 = sEt[lw][l];
         if (e0 < e1) {
             pend |= 1u << l;
             lo = min(lo, e0);
@@ -609,34 +624,71 @@ __global__ __launch_bounds__(256, LAT_MIN_WAVES) void lat_event_kernel(LatArgs a
             bhi = min(bhi, e1);
         }
     }
-    uint32_t *pw = a.planes + w * (uint64_t)a.sh.S * NP;
+    for (int k = 0; k < WS * 32; ++k) {
+        const uint64_t e0 = sE[k / 32][k % 32], e1 = sEt[k / 32][k % 32];
+        if (e0 < e1) {
+            wlo = min(wlo, e0);
+            whi = max(whi, e1);
+        }
+    }
+    const int S = a.sh.S;
     uint32_t n_real = 0, n_blocked = 0;
-    if (pend) {
+    if (whi > wlo) {
         for (uint32_t c = 0; c < a.n_chunks; ++c) {
-            const uint32_t *slot = a.sched + ((uint64_t)g * LAT_NCB + c) * LAT_SLOT;
-            const uint32_t *recs = slot;
-            const uint32_t *offs = slot + 2 * LAT_CH;
+            const uint32_t *slotp = a.sched + ((uint64_t)g * LAT_NCB + c) * LAT_SLOT;
+            const uint32_t *recs = slotp;
+            const uint32_t *offs = slotp + 2 * LAT_CH;
             const uint64_t cbase = a.base + (uint64_t)(a.chunk0 + c) * LAT_CH;
-            if (cbase >= hi || cbase + LAT_CH <= lo) continue;
+            if (cbase >= whi || cbase + LAT_CH <= wlo) continue;
             const uint32_t nl = offs[0];
             for (uint32_t L = 0; L < nl; ++L) {
-                const uint32_t beg = offs[1 + L], end = offs[2 + L];
-                for (uint32_t idx = beg + tid; idx < end; idx += 256) {
-                    const uint32_t rec = recs[idx];
-                    const uint64_t e = cbase + (rec >> 16);
-                    if (e < lo || e >= hi) continue;
-                    const uint32_t act =
-                        (e >= blo && e < bhi) ? pend : lanes_at(sE, sEt, pend, e);
-                    if (!act) continue;
-                    const uint32_t s = (rec >> 3) & 0x1FFFu, kind = rec & 7u;
-                    uint32_t *p = pw + (uint64_t)s * NP;
-                    if (kind == 0) {
-                        n_real += __popc(lat_reaction<P, BC, CU, CA, CI>(p, a, (uint32_t)w, e, act));
+                const uint32_t end = offs[2 + L];
+                // the planes of this thread's next event of the layer are
+                // loaded while the current one computes: events of a layer
+                // touch disjoint sites, so nothing else writes them meanwhile
+                uint32_t idx = offs[1 + L] + slot;
+                uint64_t e = 0;
+                uint32_t s = 0, s2 = 0, kind = 0, act = 0;
+                uint32_t l[P], d[P], x[P], l2[P], d2[P], x2[P];
+                auto fetch = [&](uint32_t i) {
+                    const uint32_t rec = recs[i];
+                    e = cbase + (rec >> 16);
+                    act = 0;
+                    if (e >= lo && e < hi)
+                        act = (e >= blo && e < bhi) ? pend : lanes_at(sE[lw], sEt[lw], pend, e);
+                    s = (rec >> 3) & 0x1FFFu;
+                    kind = rec & 7u;
+                    s2 = kind ? lat_neighbour(a.sh, s, kind - 1) : s;
+                    if (act) {
+                        load_site<P>(site_planes(a.planes, w, s, S, NP), l, d, x);
+                        if (s2 != s) load_site<P>(site_planes(a.planes, w, s2, S, NP), l2, d2, x2);
+                    }
+                };
+                if (idx < end) fetch(idx);
+                while (idx < end) {
+                    const uint64_t e_c = e;
+                    const uint32_t s_c = s, s2_c = s2, kind_c = kind, act_c = act;
+                    uint32_t lc[P], dc[P], xc[P], l2c[P], d2c[P], x2c[P];
+#pragma unroll
+                    for (int q = 0; q < P; ++q) {
+                        lc[q] = l[q];
+                        dc[q] = d[q];
+                        xc[q] = x[q];
+                        l2c[q] = s2_c == s_c ? l[q] : l2[q];
+                        d2c[q] = s2_c == s_c ? d[q] : d2[q];
+                        x2c[q] = s2_c == s_c ? x[q] : x2[q];
+                    }
+                    idx += EV;
+                    if (idx < end) fetch(idx);
+                    if (!act_c) continue;
+                    uint32_t *p = site_planes(a.planes, w, s_c, S, NP);
+                    if (kind_c == 0) {
+                        n_real += __popc(lat_reaction<P, BC, CU, CA, CI>(p, lc, dc, xc, a,
+                                                                         (uint32_t)w, e_c, act_c));
                     } else {
-                        const uint32_t s2 = lat_neighbour(a.sh, s, kind - 1);
                         uint32_t mv, bl;
-                        lat_hop<P>(p, pw + (uint64_t)s2 * NP, s2 == s, a, (uint32_t)w, e, act, mv,
-                                   bl);
+                        lat_hop<P>(p, site_planes(a.planes, w, s2_c, S, NP), s2_c == s_c, lc, dc, xc,
+                                   l2c, d2c, x2c, a, (uint32_t)w, e_c, act_c, mv, bl);
                         n_real += __popc(mv);
                         n_blocked += __popc(bl);
                     }
@@ -646,23 +698,12 @@ __global__ __launch_bounds__(256, LAT_MIN_WAVES) void lat_event_kernel(LatArgs a
         }
     }
     // per-word totals of real events and blocked hops
-    for (int o = 32; o; o >>= 1) {
-        n_real += __shfl_xor((int)n_real, o, 64);
-        n_blocked += __shfl_xor((int)n_blocked, o, 64);
-    }
-    if ((tid & 63) == 0) {
-        sred[0][tid >> 6] = n_real;
-        sred[1][tid >> 6] = n_blocked;
-    }
+    if (n_real) atomicAdd(&sred[0][lw], n_real);
+    if (n_blocked) atomicAdd(&sred[1][lw], n_blocked);
     __syncthreads();
-    if (tid == 0) {
-        uint64_t r = 0, b = 0;
-        for (uint32_t k = 0; k < blockDim.x / 64; ++k) {
-            r += sred[0][k];
-            b += sred[1][k];
-        }
-        a.real[w] += r;
-        a.blocked[w] += b;
+    if (tid < WS && w < words) {
+        a.real[w] += sred[0][tid];
+        a.blocked[w] += sred[1][tid];
     }
 }
 
@@ -676,11 +717,10 @@ __global__ void lat_totals_kernel(const uint32_t *planes, uint64_t M, int S, int
     if (i >= M) return;
     const uint64_t w = i >> 5;
     const uint32_t lane = i & 31;
-    const uint32_t *pw = planes + w * (uint64_t)S * 3 * P;
     int32_t t[3] = {0, 0, 0};
     for (int s = 0; s < S; ++s) {
         uint32_t l[P], d[P], x[P];
-        load_site<P>(pw + (uint64_t)s * 3 * P, l, d, x);
+        load_site<P>(site_planes(planes, w, s, S, 3 * P), l, d, x);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             t[0] += (int32_t)((l[q] >> lane) & 1u) << q;
@@ -703,7 +743,7 @@ __global__ void lat_sites_kernel(const uint32_t *planes, int S, int P, uint64_t 
     const uint64_t i = first + k;
     const uint64_t w = i >> 5;
     const uint32_t lane = i & 31;
-    const uint32_t *p = planes + (w * (uint64_t)S + s) * 3 * P;
+    const uint32_t *p = site_planes(planes, w, s, S, 3 * P);
     for (int x = 0; x < 3; ++x) {
         int32_t v = 0;
         for (int q = 0; q < P; ++q) v |= (int32_t)((p[x * P + q] >> lane) & 1u) << q;
@@ -757,24 +797,29 @@ hipError_t launch_lat_schedule(const LatArgs &a, uint32_t n_groups, hipStream_t 
     return hipGetLastError();
 }
 
-// (id, P, BC, CU, CA, CI): species planes, threshold-plane capacity and the
-// weights of A -> L / A -> D, A + L -> 2L / A + D -> 2D and L + D -> 2A
-// (-1: taken at run time).
+// (id, P, BC, CU, CA, CI, WS, BLOCK): species planes, threshold-plane
+// capacity, the weights of A -> L / A -> D, A + L -> 2L / A + D -> 2D and
+// L + D -> 2A (-1: taken at run time), words per slice and threads per
+// workgroup (512 for the run-time weights, which need more registers).
 #define BWG_LAT_VARIANTS(X)                                                                   \
-    X(0, 4, 19, 246, 2048, 2048) X(1, 4, 19, -1, -1, -1) X(2, 4, 24, -1, -1, -1)              \
-    X(3, 4, 32, -1, -1, -1)
+    X(0, 4, 19, 246, 2048, 2048, 8, 1024) X(1, 4, 19, 246, 2048, 2048, 1, 1024)                \
+    X(2, 4, 19, -1, -1, -1, 8, 512) X(3, 4, 19, -1, -1, -1, 1, 512)                            \
+    X(4, 4, 24, -1, -1, -1, 8, 512) X(5, 4, 24, -1, -1, -1, 1, 512)
 
-#define BWG_LAT_LAUNCH(ID, P_, BC_, CU_, CA_, CI_)                                            \
+// grid: the slices of every group, rounded up to a multiple of the 8 XCDs
+#define BWG_LAT_LAUNCH(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_)                                  \
     static hipError_t lat_launch_##ID(const LatArgs &a, uint64_t words, hipStream_t s)       \
     {                                                                                         \
-        hipLaunchKernelGGL((lat_event_kernel<P_, BC_, CU_, CA_, CI_>), dim3((unsigned)words),   \
-                           dim3(256), 0, s, a);                                               \
+        const uint64_t groups = (words + LAT_GROUP_WORDS - 1) / LAT_GROUP_WORDS;              \
+        const uint64_t nwg = groups * (LAT_GROUP_WORDS / WS_);                                \
+        hipLaunchKernelGGL((lat_event_kernel<P_, BC_, CU_, CA_, CI_, WS_, BL_>),              \
+                           dim3((unsigned)(8 * ((nwg + 7) / 8))), dim3(BL_), 0, s, a);        \
         return hipGetLastError();                                                             \
     }
 BWG_LAT_VARIANTS(BWG_LAT_LAUNCH)
 
 #ifndef __HIP_DEVICE_COMPILE__
-#define BWG_LAT_ROW(ID, P_, BC_, CU_, CA_, CI_) {P_, BC_, CU_, CA_, CI_, lat_launch_##ID},
+#define BWG_LAT_ROW(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_) {P_, BC_, CU_, CA_, CI_, WS_, lat_launch_##ID},
 const LatVariant kLatVariants[] = {BWG_LAT_VARIANTS(BWG_LAT_ROW)};
 const int kLatVariantCount = sizeof(kLatVariants) / sizeof(kLatVariants[0]);
 #endif

@@ -135,14 +135,23 @@ int lat_net_setup(bwg_net *n, const bwg_net_desc *d)
     return BWG_OK;
 }
 
-static const LatVariant *pick_lat_variant(const bwg_net *n)
+// Words per workgroup slice: 8 once there are enough slices to fill the
+// chip (coalesced site records), else one word per workgroup.
+static int lat_slice_words(uint64_t M)
+{
+    const uint64_t words = (M + 31) / 32;
+    return words >= 512 ? 8 : 1;
+}
+
+static const LatVariant *pick_lat_variant(const bwg_net *n, uint64_t M)
 {
     if (!n->lat_gpu) return nullptr;
     const LatShape &sh = n->lsh;
+    const int ws = lat_slice_words(M);
     const LatVariant *best = nullptr;
     for (int i = 0; i < kLatVariantCount; ++i) {
         const LatVariant &v = kLatVariants[i];
-        if (v.P != sh.P || v.bc < sh.B_r + 1) continue;
+        if (v.P != sh.P || v.bc < sh.B_r + 1 || v.ws != ws) continue;
         if (v.cu >= 0 && ((uint64_t)v.cu != sh.cu || (uint64_t)v.ca != sh.ca ||
                           (uint64_t)v.ci != sh.ci))
             continue;
@@ -173,7 +182,7 @@ static LatLayout lat_layout(const bwg_net *n, uint64_t M, uint64_t table_cap)
     LatLayout L{};
     uint64_t off = 0;
     L.planes = off;
-    off = align256(off + words * (uint64_t)sh.S * 3 * sh.P * 4);
+    off = align256(off + groups * LAT_GROUP_WORDS * (uint64_t)sh.S * 3 * sh.P * 4);
     L.E = off;
     off = align256(off + mp * 8);
     L.Et = off;
@@ -198,7 +207,7 @@ static LatLayout lat_layout(const bwg_net *n, uint64_t M, uint64_t table_cap)
 
 int lat_state_bytes(const bwg_net *n, uint64_t M, uint64_t table_cap, uint64_t *bytes)
 {
-    if (!pick_lat_variant(n))
+    if (!pick_lat_variant(n, M))
         return fail(BWG_EUNSUPPORTED, "no lattice event kernel for P=%d, B_r=%d and these weights",
                     n->lsh.P, n->lsh.B_r);
     *bytes = lat_layout(n, M, table_cap).total;
@@ -208,7 +217,7 @@ int lat_state_bytes(const bwg_net *n, uint64_t M, uint64_t table_cap, uint64_t *
 int lat_bind(bwg_ens *e)
 {
     const bwg_net *n = e->net;
-    e->lvar = pick_lat_variant(n);
+    e->lvar = pick_lat_variant(n, e->M);
     const LatLayout L = lat_layout(n, e->M, e->table_cap);
     e->lat = true;
     e->words = (e->M + 31) / 32;

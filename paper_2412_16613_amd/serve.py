@@ -3,11 +3,13 @@
 A request is (arrival time, network, replicas, seed, net id, initial state,
 t_end).  The server admits arrived requests in arrival order while their
 device state fits the HBM budget and a member slot is free; an admitted
-request gets its own device-resident ensemble, its event budgets for the
-whole horizon are drawn at once, and it joins the persistent batch.  Every
-pass runs at most `chunk` events per word of every resident request, so long
-chains yield to newly admitted requests between passes and the work of all
-resident requests overlaps in one launch.  A request completes when its
+request gets its own device-resident ensemble and its event budgets for the
+whole horizon are drawn at once.  Well-mixed requests join the persistent
+batch: every pass runs at most `chunk` events per word of every resident
+request, so long chains yield to newly admitted requests between passes and
+their work overlaps in one launch.  Lattice requests run their own launches
+(at most `lattice_chunk` events of their component sequence per pass) on a
+second stream, beside the persistent launch.  A request completes when its
 pending-event bound reaches zero; its histogram (and, if asked, its counts)
 is read back, the latency (completion - arrival) recorded and its memory
 returned to the budget.
@@ -28,10 +30,12 @@ import paper_2412_16613_amd as bwg
 class Server:
     def __init__(self, hbm_budget=64 << 30, chunk=4096, max_members=1024,
                  max_items=1 << 16, waves=2048, n_bins=256, keep_counts=False,
-                 device="cuda"):
+                 lattice_chunk=1 << 17, device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        self.lattice_chunk = int(lattice_chunk)
+        self.side = None
         self.hbm_budget = int(hbm_budget)
         self.chunk = int(chunk)
         self.max_members = int(max_members)
@@ -44,7 +48,9 @@ class Server:
 
     def _network(self, net):
         key = (net["n_tot"], tuple(net["rates"]), tuple(map(tuple, net["reactants"])),
-               tuple(map(tuple, net["products"])), bool(net.get("exact_integer")))
+               tuple(map(tuple, net["products"])), bool(net.get("exact_integer")),
+               net.get("lx", 0), net.get("ly", 0), tuple(net.get("hop_rates", ())),
+               net.get("site_planes", 0))
         n = self._nets.get(key)
         if n is None:
             n = bwg.Network(net)
@@ -64,7 +70,7 @@ class Server:
         reqs = sorted(requests, key=lambda r: r["arrival"])
         incoming = collections.deque(reqs)
         waiting = collections.deque()
-        active = []           # dicts: req, ens, bytes, admitted
+        active = []           # dicts: req, ens, bytes, items, lattice, admitted
         used_bytes = 0
         used_items = 0
         results = []
@@ -72,6 +78,12 @@ class Server:
         if self.batch is None:
             self.batch = bwg.Batch([], waves=self.waves, max_ensembles=self.max_members,
                                    max_items=self.max_items, device=self.device)
+        if self.side is None:
+            self.side = torch.cuda.Stream(self.device)
+        main = torch.cuda.current_stream(self.device)
+
+        def well_mixed(act):
+            return [a["ens"] for a in act if not a["lattice"]]
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if real_time else None
         sim_now = 0.0
@@ -85,17 +97,21 @@ class Server:
             while waiting and len(active) < self.max_members:
                 r = waiting[0]
                 net = self._network(r["net"])
+                lattice = net.is_lattice
                 ens = bwg.Ensemble(net, r["replicas"], seed=r["seed"], net_id=r["net_id"],
                                    device=self.device)
-                nbytes, items = ens.state_bytes, self._items(r["replicas"])
+                nbytes = ens.state_bytes
+                items = 0 if lattice else self._items(r["replicas"])
                 if active and (used_bytes + nbytes > self.hbm_budget
                                or used_items + items > self.max_items):
                     del ens
                     break
                 waiting.popleft()
-                ens.init(r["init"])
-                ens.schedule(r["t_end"])
-                active.append(dict(req=r, ens=ens, bytes=nbytes, items=items,
+                # lattice ensembles live on the side stream from their first call
+                with torch.cuda.stream(self.side if lattice else main):
+                    ens.init(r["init"])
+                    ens.schedule(r["t_end"])
+                active.append(dict(req=r, ens=ens, bytes=nbytes, items=items, lattice=lattice,
                                    admitted=clock() if real_time else now))
                 used_bytes += nbytes
                 used_items += items
@@ -109,16 +125,23 @@ class Server:
                 continue
             stats["max_active"] = max(stats["max_active"], len(active))
             if changed:
-                self.batch.set_members([a["ens"] for a in active])
-            self.batch.run(self.chunk)
+                self.batch.set_members(well_mixed(active))
+            if any(not a["lattice"] for a in active):
+                self.batch.run(self.chunk)
+            with torch.cuda.stream(self.side):
+                for a in active:
+                    if a["lattice"]:
+                        a["ens"].run(self.lattice_chunk)
             stats["passes"] += 1
             done = [a for a in active if a["ens"].pending() == 0]
             if done:
                 for a in done:
-                    a["hist_dev"] = a["ens"].histogram(self.n_bins)
-                    if self.keep_counts:
-                        a["counts_dev"] = a["ens"].read_counts()
-            torch.cuda.current_stream(self.device).synchronize()
+                    with torch.cuda.stream(self.side if a["lattice"] else main):
+                        a["hist_dev"] = a["ens"].histogram(self.n_bins)
+                        if self.keep_counts:
+                            a["counts_dev"] = a["ens"].read_counts()
+            main.synchronize()
+            self.side.synchronize()
             if not real_time:
                 sim_now += pass_time
             if done:
@@ -136,7 +159,7 @@ class Server:
                     used_bytes -= a["bytes"]
                     used_items -= a["items"]
                 active = [a for a in active if a["ens"].pending() != 0]
-                self.batch.set_members([a["ens"] for a in active])
+                self.batch.set_members(well_mixed(active))
         stats["wall_s"] = (time.perf_counter() - t0)
         self.stats = stats
         return results

@@ -63,6 +63,24 @@ def test_fixed_event_count(lx, ly, M, K):
     check(ens, orc, "step")
 
 
+def test_eight_word_slices_every_replica():
+    """Ensembles of 512 words and more run 8-word slices per workgroup; a
+    ragged last slice and group, all replicas compared."""
+    net = lattice(4, 4)
+    M = 16384 + 1000 + 7
+    ens, orc = pair(net, M, seed=12)
+    ens.step(1500)
+    orc.step(1500)
+    check(ens, orc, "8-word slices, step")
+    ens.advance(1.0)
+    orc.advance(1.0)
+    check(ens, orc, "8-word slices, advance")
+    _, real = ens.read_events()
+    pad = (-M) % 32
+    word = lambda v: np.concatenate([v, np.zeros(pad, v.dtype)]).reshape(-1, 32).sum(1)
+    assert (real.cpu().numpy() == word(orc.real.astype(np.int64))).all()
+
+
 def test_two_advances_and_counters():
     net = lattice(8, 8)
     M = 2048 + 70

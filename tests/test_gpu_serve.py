@@ -58,6 +58,43 @@ def test_served_small_requests_match_oracle(torch):
         np.testing.assert_array_equal(got["counts"], o.counts)
 
 
+def _lattice_requests():
+    reqs = _requests()[:4]
+    lat = [(frank_network(12, lx=8, ly=8, hop=0.1, site_planes=4), 300, 1.5),
+           (frank_network(12, lx=16, ly=12, hop=0.1, site_planes=4), 70, 0.4),
+           (frank_network(12, lx=5, ly=7, k0=0.05, hop=0.3, site_planes=4), 2100, 2.0)]
+    for k, (net, M, t) in enumerate(lat):
+        reqs.append(dict(arrival=0.5 + 0.9 * k, net=net, replicas=M, seed=21, net_id=700 + k,
+                         init=("uniform_site", 9, 15), t_end=t))
+    return reqs
+
+
+def test_lattice_requests_in_the_mix(torch):
+    """Lattice requests run beside the persistent batch on a second stream;
+    every request's histogram and totals equal its run alone, and the
+    lattice ones equal the lattice oracle."""
+    from oracle.lattice import OracleLattice
+    reqs = _lattice_requests()
+    srv = Server(chunk=200, max_members=5, keep_counts=True, lattice_chunk=8192)
+    res = srv.serve(reqs, real_time=False, pass_time=1.0)
+    assert len(res) == len(reqs)
+    assert srv.stats["max_active"] >= 3
+    by_id = {r["id"]: r for r in res}
+    for r in reqs:
+        e = bwg.Ensemble(bwg.Network(r["net"]), r["replicas"], seed=r["seed"],
+                         net_id=r["net_id"])
+        e.init(r["init"]).advance(r["t_end"])
+        got = by_id[r["net_id"]]
+        np.testing.assert_array_equal(got["hist"], e.histogram(256).cpu().numpy())
+        np.testing.assert_array_equal(got["counts"], e.read_counts().cpu().numpy())
+        if r["net"].get("lx"):
+            o = OracleLattice(r["net"], r["replicas"], seed=r["seed"], net_id=r["net_id"],
+                              threads=8)
+            o.init(r["init"])
+            o.advance(r["t_end"])
+            np.testing.assert_array_equal(got["counts"], o.totals())
+
+
 def test_admission_respects_the_memory_budget(torch):
     reqs = _requests()
     one = max(bwg.Ensemble(bwg.Network(r["net"]), r["replicas"]).state_bytes for r in reqs)
