@@ -151,6 +151,8 @@ struct LatArgs {
     uint32_t chunk0;        // first chunk of this pass
     uint32_t n_chunks;      // chunks in this pass (<= LAT_NCB)
     uint32_t net_id;
+    uint32_t g0;            // event kernel: first group of the band
+    uint32_t ng;            // event kernel: groups in the band
     uint32_t pad;
     LatShape sh;
 };
@@ -162,7 +164,7 @@ using LatLaunch = hipError_t (*)(const LatArgs &, uint64_t words, hipStream_t);
 struct LatVariant {
     int P, bc;
     int64_t cu, ca, ci;
-    int ws;
+    int ws, block;
     LatLaunch fn;
 };
 extern const LatVariant kLatVariants[];

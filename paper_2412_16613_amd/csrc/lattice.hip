@@ -578,7 +578,9 @@ __device__ __noinline__ uint32_t lanes_at(const uint64_t *sE, const uint64_t *sE
 // One workgroup per slice of WS consecutive words of a group, BLOCK
 // threads: thread t works on word t mod WS of the slice and on every
 // (BLOCK / WS)-th event of a layer, so the WS words of one event read
-// WS * 12 contiguous planes.  Slices are spread so that the slices of a
+// WS * 12 contiguous planes.  A launch covers the band of groups
+// [a.g0, a.g0 + a.ng): the host sizes bands so that their site planes fit the
+// last-level (infinity) cache.  Slices are spread so that the slices of a
 // group run on one XCD (workgroups go to the 8 XCDs in turn), where they
 // share the group's schedule in L2.  Runs the events of chunks chunk0 ..
 // chunk0+n_chunks-1 layer by layer.
@@ -588,11 +590,11 @@ __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
     constexpr int NP = 3 * P;
     constexpr int NSL = LAT_GROUP_WORDS / WS;   // slices per group
     constexpr int EV = BLOCK / WS;              // events in flight per workgroup
-    const uint32_t nwg = (uint32_t)(((a.M + 31) / 32 + LAT_GROUP_WORDS - 1) / LAT_GROUP_WORDS) * NSL;
+    const uint32_t nwg = a.ng * NSL;
     const uint32_t per_xcd = (nwg + 7) / 8;
     const uint32_t v = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (v >= nwg) return;
-    const uint32_t g = v / NSL;
+    const uint32_t g = a.g0 + v / NSL;
     const uint64_t w0 = (uint64_t)g * LAT_GROUP_WORDS + (v % NSL) * WS;
     const uint64_t words = (a.M + 31) / 32;
     if (w0 >= words) return;
@@ -802,16 +804,16 @@ hipError_t launch_lat_schedule(const LatArgs &a, uint32_t n_groups, hipStream_t 
 // L + D -> 2A (-1: taken at run time), words per slice and threads per
 // workgroup (512 for the run-time weights, which need more registers).
 #define BWG_LAT_VARIANTS(X)                                                                   \
-    X(0, 4, 19, 246, 2048, 2048, 8, 1024) X(1, 4, 19, 246, 2048, 2048, 1, 1024)                \
-    X(2, 4, 19, -1, -1, -1, 8, 512) X(3, 4, 19, -1, -1, -1, 1, 512)                            \
-    X(4, 4, 24, -1, -1, -1, 8, 512) X(5, 4, 24, -1, -1, -1, 1, 512)
+    X(0, 4, 19, 246, 2048, 2048, 4, 1024) X(1, 4, 19, 246, 2048, 2048, 1, 1024)                \
+    X(2, 4, 19, -1, -1, -1, 4, 512) X(3, 4, 19, -1, -1, -1, 1, 512)                            \
+    X(4, 4, 24, -1, -1, -1, 4, 512) X(5, 4, 24, -1, -1, -1, 1, 512)
 
-// grid: the slices of every group, rounded up to a multiple of the 8 XCDs
+// grid: the slices of the band's groups, rounded up to a multiple of the 8 XCDs
 #define BWG_LAT_LAUNCH(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_)                                  \
     static hipError_t lat_launch_##ID(const LatArgs &a, uint64_t words, hipStream_t s)       \
     {                                                                                         \
-        const uint64_t groups = (words + LAT_GROUP_WORDS - 1) / LAT_GROUP_WORDS;              \
-        const uint64_t nwg = groups * (LAT_GROUP_WORDS / WS_);                                \
+        (void)words;                                                                          \
+        const uint64_t nwg = (uint64_t)a.ng * (LAT_GROUP_WORDS / WS_);                        \
         hipLaunchKernelGGL((lat_event_kernel<P_, BC_, CU_, CA_, CI_, WS_, BL_>),              \
                            dim3((unsigned)(8 * ((nwg + 7) / 8))), dim3(BL_), 0, s, a);        \
         return hipGetLastError();                                                             \
@@ -819,7 +821,7 @@ hipError_t launch_lat_schedule(const LatArgs &a, uint32_t n_groups, hipStream_t 
 BWG_LAT_VARIANTS(BWG_LAT_LAUNCH)
 
 #ifndef __HIP_DEVICE_COMPILE__
-#define BWG_LAT_ROW(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_) {P_, BC_, CU_, CA_, CI_, WS_, lat_launch_##ID},
+#define BWG_LAT_ROW(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_) {P_, BC_, CU_, CA_, CI_, WS_, BL_, lat_launch_##ID},
 const LatVariant kLatVariants[] = {BWG_LAT_VARIANTS(BWG_LAT_ROW)};
 const int kLatVariantCount = sizeof(kLatVariants) / sizeof(kLatVariants[0]);
 #endif

@@ -140,7 +140,22 @@ int lat_net_setup(bwg_net *n, const bwg_net_desc *d)
 static int lat_slice_words(uint64_t M)
 {
     const uint64_t words = (M + 31) / 32;
-    return words >= 512 ? 8 : 1;
+    return words >= 512 ? 4 : 1;
+}
+
+// Groups per event launch: at most one workgroup per CU (256), and a band's
+// site planes within 224 MB, so that between two visits of a site the planes
+// stay in the 256 MB last-level cache instead of going to HBM; bands of
+// equal size.
+static uint32_t lat_band_groups(const bwg_net *n, int ws, uint64_t groups)
+{
+    if (ws == 1) return (uint32_t)groups;     // one word per workgroup: no banding
+    const uint64_t per_group = (uint64_t)LAT_GROUP_WORDS * n->lsh.S * 3 * n->lsh.P * 4;
+    const uint64_t by_cus = 256 / (uint64_t)(LAT_GROUP_WORDS / ws);
+    const uint64_t by_cache = (224ull << 20) / per_group;
+    const uint64_t b = std::max<uint64_t>(1, std::min(by_cus, by_cache));
+    const uint64_t bands = (groups + b - 1) / b;
+    return (uint32_t)((groups + bands - 1) / bands);
 }
 
 static const LatVariant *pick_lat_variant(const bwg_net *n, uint64_t M)
@@ -343,12 +358,17 @@ int lat_run(bwg_ens *e, uint64_t max_events, hipStream_t s)
     a.base = e->base;
     a.net_id = e->net_id;
     a.sh = n->lsh;
+    const uint32_t band = lat_band_groups(n, e->lvar->ws, e->groups);
     while (todo) {
         const uint32_t nc = (uint32_t)std::min<uint64_t>(todo, LAT_NCB);
         a.chunk0 = (uint32_t)e->cursor;
         a.n_chunks = nc;
         HIP_TRY(launch_lat_schedule(a, (uint32_t)e->groups, s));
-        HIP_TRY(e->lvar->fn(a, e->words, s));
+        for (uint64_t g0 = 0; g0 < e->groups; g0 += band) {
+            a.g0 = (uint32_t)g0;
+            a.ng = (uint32_t)std::min<uint64_t>(band, e->groups - g0);
+            HIP_TRY(e->lvar->fn(a, e->words, s));
+        }
         e->cursor += nc;
         todo -= nc;
     }

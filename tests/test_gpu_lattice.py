@@ -63,14 +63,15 @@ def test_fixed_event_count(lx, ly, M, K):
     check(ens, orc, "step")
 
 
-def test_eight_word_slices_every_replica():
-    """Ensembles of 512 words and more run 8-word slices per workgroup; a
-    ragged last slice and group, all replicas compared."""
+@pytest.mark.parametrize("M", [16384 + 1000 + 7, 40000 + 5])
+def test_sliced_workgroups_every_replica(M):
+    """Ensembles of 512 words and more run 4-word slices per workgroup and,
+    beyond 16 groups, several launches over bands of groups; ragged last
+    slice and group, all replicas compared."""
     net = lattice(4, 4)
-    M = 16384 + 1000 + 7
     ens, orc = pair(net, M, seed=12)
-    ens.step(1500)
-    orc.step(1500)
+    ens.step(1000)
+    orc.step(1000)
     check(ens, orc, "8-word slices, step")
     ens.advance(1.0)
     orc.advance(1.0)
