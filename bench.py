@@ -44,6 +44,9 @@ CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
 MEASURED_TRAFFIC = {
     "wm_event_kernel": ("a291580fbca6", ("bitops.h", "wm_device.h", "wm_kernel.hip"),
                         34007 * 1024, "profiles/wm_event_kernel_frank1024_2p20.md"),
+    "lat_event_kernel": ("730e9d3e6dcc", ("bitops.h", "lattice.hip"),
+                         (2 * 3993080 + 8341990) * 1024,
+                         "profiles/lat_event_kernel_lattice64x64_2p16.md"),
 }
 
 
@@ -115,7 +118,7 @@ def main():
 
     def make(engine):
         ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], engine=engine,
-                           device=dev)
+                           device=dev, time_kernels=True)
         counts = torch.empty((M, 3), dtype=torch.int32, device=dev)
         hist = torch.empty(256, dtype=torch.int64, device=dev)
         return ens, counts, hist
@@ -129,6 +132,7 @@ def main():
             ens.read_counts(counts)
             ens.histogram(256, hist)
         torch.cuda.synchronize()
+        ens.kernel_time()               # start counting event-kernel launches here
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
@@ -149,10 +153,11 @@ def main():
         wall = time.perf_counter() - wall0
         ms = t0.elapsed_time(t1)
         adv_ms = [x.elapsed_time(y) for x, y in zip(k0, k1)]
+        kt_ms, kt_n = ens.kernel_time()
         st = ens.stats()
         assert int(hist.sum().item()) == M
         return dict(ms=ms, wall=wall, adv_ms=adv_ms, events=st["events_total"],
-                    real=st["real_total"])
+                    real=st["real_total"], kt_ms=kt_ms, kt_n=kt_n)
 
     r = run("bitwise", args.steps, args.warmup)
     ms_step = r["ms"] / args.steps
@@ -161,7 +166,11 @@ def main():
     adv_avg_ms = sum(r["adv_ms"]) / len(r["adv_ms"])
     word_events = events_per_step / 32.0
     slots = word_event_slots(q["b"], q["B"], q["f"], bin(q["c"][0]).count("1") - 1)
-    achieved = slots * word_events / (adv_avg_ms / 1e3)
+    # per event-kernel launch: its share of the step's word-events over its
+    # duration (HIP events around each launch, on the launch stream)
+    launches_per_step = r["kt_n"] / args.steps
+    launch_ms = r["kt_ms"] / r["kt_n"]
+    achieved = slots * word_events / launches_per_step / (launch_ms / 1e3)
     out = {
         "metric": "replica-events/sec (bit-parallel vs plain SSA, 1 GPU)",
         "value": value,
@@ -184,8 +193,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
                      "traffic": measured_traffic("wm_event_kernel"), "traffic_unit": "B/launch",
-                     "kernel": "wm_event_kernel",
-                     "kernel_ms": adv_avg_ms, "slots_per_word_event": slots},
+                     "kernel": "wm_event_kernel", "kernel_ms": launch_ms,
+                     "launches_per_step": launches_per_step, "advance_ms": adv_avg_ms,
+                     "slots_per_word_event": slots},
     }
     if not args.no_plain:
         p = run("plain", max(1, args.steps // 2), 1)
@@ -232,13 +242,15 @@ def bench_lattice(args):
     torch.cuda.set_device(dev)
     network = bwg.Network(net)
     q, li = network.quantized(), network.lattice()
-    ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], device=dev)
+    ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], device=dev,
+                       time_kernels=True)
     counts = torch.empty((M, 3), dtype=torch.int32, device=dev)
     hist = torch.empty(256, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
         ens.init(c["init"]).advance(t_end)
     torch.cuda.synchronize()
+    ens.kernel_time()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     adv = []
@@ -257,6 +269,7 @@ def bench_lattice(args):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     adv_ms = sum(a.elapsed_time(b) for a, b in adv) / len(adv)
+    kt_ms, kt_n = ens.kernel_time()
     st = ens.stats()
     assert int(hist.sum().item()) == M
     events = st["events_total"]
@@ -265,7 +278,9 @@ def bench_lattice(args):
     W_R, W_H = 1 << li["B_r"], ((li["T"] + 1) * li["c_hop"])
     f_r = W_R / (W_R + 4 * W_H)
     slots = f_r * react + (1 - f_r) * hop
-    achieved = slots * (events / 32.0) / (adv_ms / 1e3)
+    launches_per_step = kt_n / args.steps
+    launch_ms = kt_ms / kt_n
+    achieved = slots * (events / 32.0) / launches_per_step / (launch_ms / 1e3)
     out = {
         "metric": "replica-events/sec (bit-parallel lattice, 1 GPU)",
         "value": value, "unit": "replica-events/s", "n_gpus": 1, "steps": args.steps,
@@ -278,9 +293,11 @@ def bench_lattice(args):
                    "reaction_planes": li["B_r"]},
         "real_events_per_s": st["real_total"] * args.steps / (ms / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                     "kernel": "lat_event_kernel (+ lat_schedule_kernel, one pass)",
-                     "kernel_ms": adv_ms, "slots_per_word_event": slots,
+                     "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
+                     "traffic": measured_traffic("lat_event_kernel"), "traffic_unit": "B/launch",
+                     "kernel": "lat_event_kernel", "kernel_ms": launch_ms,
+                     "launches_per_step": launches_per_step, "advance_ms": adv_ms,
+                     "slots_per_word_event": slots,
                      "slots_reaction": react, "slots_hop": hop},
     }
     if not args.no_cpu:

@@ -134,12 +134,17 @@ typedef struct {
     double s, lambda;           /* scale 2^f / k_ref; C / s                   */
 } bwg_lattice_info;
 
+/* flags of bwg_opts */
+#define BWG_OPT_TIME_KERNELS 1u  /* record HIP events around every event-kernel
+                                    launch (bwg_ensemble_kernel_time)         */
+
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */
     int32_t block;               /* threads per block, 0 = default            */
     uint64_t table_capacity;     /* Poisson-table entries, 0 = default 65536  */
     uint64_t events_per_launch;  /* 0 = whole advance in one launch           */
-    uint64_t reserved[4];
+    uint64_t flags;              /* BWG_OPT_*                                 */
+    uint64_t reserved[3];
 } bwg_opts;
 
 typedef struct {
@@ -257,6 +262,14 @@ int bwg_ensemble_read_sites(bwg_ens *ens, uint64_t first, uint64_t count, int32_
 /* Lattice ensembles: hops into full sites so far, per 32-replica word,
  * dev_dst[ceil(M/32)] uint64.  Async. */
 int bwg_ensemble_read_blocked(bwg_ens *ens, uint64_t *dev_dst, void *stream);
+
+/* With BWG_OPT_TIME_KERNELS: waits for the event-kernel launches enqueued
+ * since the last call (wm_event_kernel, plain_event_kernel or
+ * lat_event_kernel; not the budget, schedule or readout kernels) and
+ * returns their summed duration in ms, measured with HIP events on the
+ * launch stream, and their number; then starts a new count.  EINVAL if the
+ * ensemble was created without the flag. */
+int bwg_ensemble_kernel_time(bwg_ens *ens, double *ms, uint64_t *launches);
 
 /* Synchronises the stream and reports totals. */
 int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);

@@ -99,7 +99,8 @@ class Ensemble:
     """Replicas of one network in a caller-owned device buffer."""
 
     def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
-                 device="cuda", events_per_launch=0, table_capacity=0, block=0):
+                 device="cuda", events_per_launch=0, table_capacity=0, block=0,
+                 time_kernels=False):
         import torch
         self.torch = torch
         L = _lib()
@@ -111,6 +112,7 @@ class Ensemble:
         o.block = block
         o.table_capacity = table_capacity
         o.events_per_launch = events_per_launch
+        o.flags = _abi.BWG_OPT_TIME_KERNELS if time_kernels else 0
         self._opts = o
         nbytes = ctypes.c_uint64()
         _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),
@@ -237,6 +239,14 @@ class Ensemble:
                                                    ctypes.c_void_p(real.data_ptr()),
                                                    self._stream()))
         return ev, real
+
+    def kernel_time(self):
+        """(ms, launches) of the event-kernel launches since the last call
+        (ensembles created with time_kernels=True)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        _abi.check(_lib().bwg_ensemble_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def stats(self):
         s = _abi.Stats()

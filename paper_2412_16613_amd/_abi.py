@@ -24,6 +24,7 @@ BWG_INIT_FIXED = 0
 BWG_INIT_MULTINOMIAL = 1
 BWG_INIT_UNIFORM_SITE = 2
 BWG_INIT_SITES = 3
+BWG_OPT_TIME_KERNELS = 1
 
 # Every symbol include/bwg.h declares.
 SYMBOLS = (
@@ -36,6 +37,7 @@ SYMBOLS = (
     "bwg_ensemble_schedule", "bwg_ensemble_run", "bwg_ensemble_pending",
     "bwg_batch_capacity_bytes", "bwg_batch_set_members", "bwg_batch_run",
     "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
+    "bwg_ensemble_kernel_time",
 )
 
 
@@ -68,7 +70,7 @@ class LatticeInfo(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("table_capacity", ctypes.c_uint64), ("events_per_launch", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 4)]
+                ("flags", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -133,6 +135,7 @@ def load():
         "bwg_net_lattice": (i32, [vp, P(LatticeInfo)]),
         "bwg_ensemble_read_sites": (i32, [vp, u64, u64, vp, vp]),
         "bwg_ensemble_read_blocked": (i32, [vp, vp, vp]),
+        "bwg_ensemble_kernel_time": (i32, [vp, P(ctypes.c_double), P(u64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

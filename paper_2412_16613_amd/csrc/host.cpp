@@ -459,6 +459,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->block = o ? o->block : 0;
     e->table_cap = (o && o->table_capacity) ? o->table_capacity : 65536;
     e->epl = o ? o->events_per_launch : 0;
+    e->timed = o && (o->flags & BWG_OPT_TIME_KERNELS);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
     if (n->lat) {
@@ -487,6 +488,57 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
 }
 
 extern "C" void bwg_ensemble_destroy(bwg_ens *e) { delete e; }
+
+static int take_event(bwg_ens *e, hipEvent_t *ev)
+{
+    if (!e->spare.empty()) {
+        *ev = e->spare.back();
+        e->spare.pop_back();
+        return BWG_OK;
+    }
+    HIP_TRY(hipEventCreate(ev));
+    return BWG_OK;
+}
+
+int bwg::mark_begin(bwg_ens *e, hipStream_t s, hipEvent_t *ev)
+{
+    *ev = nullptr;
+    if (!e->timed) return BWG_OK;
+    int rc = take_event(e, ev);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(*ev, s));
+    return BWG_OK;
+}
+
+int bwg::mark_end(bwg_ens *e, hipStream_t s, hipEvent_t ev)
+{
+    if (!e->timed) return BWG_OK;
+    hipEvent_t stop;
+    int rc = take_event(e, &stop);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(stop, s));
+    e->marks.emplace_back(ev, stop);
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_kernel_time(bwg_ens *e, double *ms, uint64_t *launches)
+{
+    if (!e || !ms || !launches) return fail(BWG_EINVAL, "null argument");
+    if (!e->timed) return fail(BWG_EINVAL, "ensemble created without BWG_OPT_TIME_KERNELS");
+    double total = 0;
+    for (auto &m : e->marks) {
+        HIP_TRY(hipEventSynchronize(m.second));
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, m.first, m.second));
+        total += t;
+        e->spare.push_back(m.first);
+        e->spare.push_back(m.second);
+    }
+    *ms = total;
+    *launches = e->marks.size();
+    e->marks.clear();
+    return BWG_OK;
+}
 
 extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts, void *stream)
 {
@@ -564,7 +616,12 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         a.fa = n->shape.fa;
         a.fi = n->shape.fi;
         a.nb_mem = e->nb;
+        hipEvent_t ev = nullptr;
+        int rc = mark_begin(e, s, &ev);
+        if (rc) return rc;
         HIP_TRY(e->var->fn(a, s, e->block));
+        rc = mark_end(e, s, ev);
+        if (rc) return rc;
     } else {
         PlainArgs a{};
         a.counts = e->counts;
@@ -578,7 +635,12 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         a.B = n->q.B;
         a.R = n->R;
         for (int j = 0; j < n->R; ++j) a.rx[j] = n->prx[j];
+        hipEvent_t ev = nullptr;
+        int rc = mark_begin(e, s, &ev);
+        if (rc) return rc;
         HIP_TRY(launch_plain(a, s, e->block));
+        rc = mark_end(e, s, ev);
+        if (rc) return rc;
     }
     note_ran(e, max_events);
     return BWG_OK;

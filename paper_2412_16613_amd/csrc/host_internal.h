@@ -89,6 +89,18 @@ struct bwg_ens {
     int32_t *sites_dev = nullptr;    // [S][3] staging of an initial lattice
     uint64_t emin = 0, emax = 0;     // bounds on min_i E_i and max_i E_i
     uint64_t base = 0, n_chunks = 0, cursor = 0;  // chunk window of the advance
+    // event-kernel timing (BWG_OPT_TIME_KERNELS)
+    bool timed = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;  // recorded, not yet read
+    std::vector<hipEvent_t> spare;
+    ~bwg_ens()
+    {
+        for (auto &m : marks) {
+            (void)hipEventDestroy(m.first);
+            (void)hipEventDestroy(m.second);
+        }
+        for (auto ev : spare) (void)hipEventDestroy(ev);
+    }
 };
 
 
@@ -101,6 +113,11 @@ int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, u
 void note_scheduled(bwg_ens *e, uint64_t kmin, uint64_t kmax);
 // Bookkeeping after a pass that ran up to max_events per word (0: all).
 void note_ran(bwg_ens *e, uint64_t max_events);
+
+// Event-kernel timing: bracket one launch with HIP events when the ensemble
+// was created with BWG_OPT_TIME_KERNELS (no-ops otherwise).
+int mark_begin(bwg_ens *e, hipStream_t s, hipEvent_t *ev);
+int mark_end(bwg_ens *e, hipStream_t s, hipEvent_t ev);
 
 // Lattice networks and ensembles (lattice_host.cpp).
 int lat_net_setup(bwg_net *n, const bwg_net_desc *d);

@@ -367,7 +367,12 @@ int lat_run(bwg_ens *e, uint64_t max_events, hipStream_t s)
         for (uint64_t g0 = 0; g0 < e->groups; g0 += band) {
             a.g0 = (uint32_t)g0;
             a.ng = (uint32_t)std::min<uint64_t>(band, e->groups - g0);
+            hipEvent_t ev = nullptr;
+            int rc = mark_begin(e, s, &ev);
+            if (rc) return rc;
             HIP_TRY(e->lvar->fn(a, e->words, s));
+            rc = mark_end(e, s, ev);
+            if (rc) return rc;
         }
         e->cursor += nc;
         todo -= nc;
