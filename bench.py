@@ -323,23 +323,22 @@ def cpu_baseline_lattice(c, n_rep):
 def bench_batch(args):
     """Uneven batch: 256 Frank networks (N_tot log-uniform 16..4096, replicas
     log-uniform 2^10..2^18, k0 uniform 1e-3..1e-1, t_end uniform 10..200) in
-    one persistent launch, against the same networks one launch each (plain
-    engine and bit-sliced engine)."""
+    one persistent launch, tuned (lanes members, grid, order), against the
+    same networks one launch each (plain engine and bit-sliced engine)."""
     import torch
     import paper_2412_16613_amd as bwg
     from paper_2412_16613_amd import tune
     from workloads import batch_networks
 
     cfg = batch_networks()[: args.batch_nets]
-    items = [(c["net"], c["replicas"], c["t_end"]) for c in cfg]
+    sub = cfg[: args.compare_nets]
     nets = [bwg.Network(c["net"]) for c in cfg]
-    waves, order, timings = tune.tune(items)
 
-    def make(engine, sub):
+    def make(engine, members, lanes=()):
         ens = []
-        for k, c in enumerate(sub):
+        for k, c in enumerate(members):
             e = bwg.Ensemble(nets[k], c["replicas"], seed=c["seed"], net_id=c["net_id"],
-                             engine=engine)
+                             engine="lanes" if k in lanes else engine)
             e.init(c["init"])
             ens.append(e)
         return ens
@@ -354,18 +353,22 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / 1e3
 
-    res = {}
+    res, tuned = {}, {}
 
-    def run_batched(sub, tag):
-        ens = make("bitwise", sub)
-        batch = bwg.Batch(ens, waves=waves, order=order)
-        dt = timed(lambda: batch.advance([c["t_end"] for c in sub]))
+    def run_batched(members, tag):
+        items = [(c["net"], c["replicas"], c["t_end"]) for c in members]
+        t0 = time.perf_counter()
+        tn = tune.tune(items)
+        tuned[tag] = dict(tn, tuning_wall_s=time.perf_counter() - t0)
+        ens = make("bitwise", members, set(tn["lanes"]))
+        batch = bwg.Batch(ens, waves=tn["waves"], order=tn["order"])
+        dt = timed(lambda: batch.advance([c["t_end"] for c in members]))
         ev = sum(e.stats()["events_total"] for e in ens)
-        res[tag] = {"s": dt, "replica_events_per_s": ev / dt, "networks": len(sub)}
+        res[tag] = {"s": dt, "replica_events_per_s": ev / dt, "networks": len(members),
+                    "lanes_members": len(tn["lanes"])}
         return ev
 
     events = run_batched(cfg, "batched")
-    sub = cfg[: args.compare_nets]
     ev_sub = run_batched(sub, "batched_subset")
     for engine in ("bitwise", "plain"):
         ens = make(engine, sub)
@@ -380,8 +383,10 @@ def bench_batch(args):
            "n_gpus": 1, "higher_is_better": True, "dtype": "u32 bit-planes",
            "data": "synthetic",
            "config": {"workload": "uneven batch of %d Frank networks" % len(cfg),
-                      "replica_events": events, "waves": waves, "order": order},
-           "tuning_s": timings, "results": res,
+                      "replica_events": events, "waves": tuned["batched"]["waves"],
+                      "order": tuned["batched"]["order"],
+                      "lanes_members": len(tuned["batched"]["lanes"])},
+           "tuning": tuned, "results": res,
            "speedup_vs_plain_one_per_launch":
                res["batched_subset"]["replica_events_per_s"] /
                res["one_per_launch_plain"]["replica_events_per_s"],

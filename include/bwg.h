@@ -52,6 +52,10 @@ enum {
 /* engines of bwg_opts */
 #define BWG_ENGINE_BITWISE 0   /* bit-sliced words, 32 replicas per lane      */
 #define BWG_ENGINE_PLAIN 1     /* comparator: one replica per thread, int32   */
+#define BWG_ENGINE_LANES 2     /* the bit-plane state and draws of BITWISE, one
+                                  replica per thread: identical results, a
+                                  shorter chain per event, more work per
+                                  replica-event                               */
 
 /* initial-state modes of bwg_ensemble_init */
 #define BWG_INIT_FIXED 0        /* every replica starts from counts[0..S-1]   */
@@ -270,6 +274,11 @@ int bwg_ensemble_read_blocked(bwg_ens *ens, uint64_t *dev_dst, void *stream);
  * launch stream, and their number; then starts a new count.  EINVAL if the
  * ensemble was created without the flag. */
 int bwg_ensemble_kernel_time(bwg_ens *ens, double *ms, uint64_t *launches);
+
+/* Switch an ensemble between BWG_ENGINE_BITWISE and BWG_ENGINE_LANES (same
+ * state layout and random draws, so results do not change); EINVAL for other
+ * engines, lattices or a plain ensemble.  Takes effect at the next launch. */
+int bwg_ensemble_set_engine(bwg_ens *ens, int32_t engine);
 
 /* Synchronises the stream and reports totals. */
 int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);

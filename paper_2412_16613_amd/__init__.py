@@ -19,7 +19,8 @@ import ctypes
 from . import _abi
 from ._abi import BwgError  # noqa: F401
 
-ENGINES = {"bitwise": _abi.BWG_ENGINE_BITWISE, "plain": _abi.BWG_ENGINE_PLAIN}
+ENGINES = {"bitwise": _abi.BWG_ENGINE_BITWISE, "plain": _abi.BWG_ENGINE_PLAIN,
+           "lanes": _abi.BWG_ENGINE_LANES}
 
 
 def _lib():
@@ -233,12 +234,19 @@ class Ensemble:
         per replica (plain)) as int64 tensors."""
         t = self.torch
         ev = t.empty(self.M, dtype=t.int64, device=self.device)
-        nr = self.groups if self.engine == "bitwise" else self.M
+        nr = self.M if self.engine == "plain" else self.groups
         real = t.empty(nr, dtype=t.int64, device=self.device)
         _abi.check(_lib().bwg_ensemble_read_events(self.handle, ctypes.c_void_p(ev.data_ptr()),
                                                    ctypes.c_void_p(real.data_ptr()),
                                                    self._stream()))
         return ev, real
+
+    def set_engine(self, engine):
+        """Switch between the "bitwise" and "lanes" engines (same state and
+        results; the lanes engine runs one replica per thread)."""
+        _abi.check(_lib().bwg_ensemble_set_engine(self.handle, ENGINES[engine]))
+        self.engine = engine
+        return self
 
     def kernel_time(self):
         """(ms, launches) of the event-kernel launches since the last call

@@ -20,6 +20,7 @@ BWG_MAX_REACTIONS = 16
 BWG_EXACT_INTEGER = 1
 BWG_ENGINE_BITWISE = 0
 BWG_ENGINE_PLAIN = 1
+BWG_ENGINE_LANES = 2
 BWG_INIT_FIXED = 0
 BWG_INIT_MULTINOMIAL = 1
 BWG_INIT_UNIFORM_SITE = 2
@@ -37,7 +38,7 @@ SYMBOLS = (
     "bwg_ensemble_schedule", "bwg_ensemble_run", "bwg_ensemble_pending",
     "bwg_batch_capacity_bytes", "bwg_batch_set_members", "bwg_batch_run",
     "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
-    "bwg_ensemble_kernel_time",
+    "bwg_ensemble_kernel_time", "bwg_ensemble_set_engine",
 )
 
 
@@ -136,6 +137,7 @@ def load():
         "bwg_ensemble_read_sites": (i32, [vp, u64, u64, vp, vp]),
         "bwg_ensemble_read_blocked": (i32, [vp, vp, vp]),
         "bwg_ensemble_kernel_time": (i32, [vp, P(ctypes.c_double), P(u64)]),
+        "bwg_ensemble_set_engine": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -1,10 +1,12 @@
 // Batched execution of many ensembles (uneven networks, replica counts and
 // plane widths) in one persistent launch.
 //
-// Work item = (ensemble, 64 consecutive words); one wave takes one item at a
-// time from a device queue ordered longest-first by the host, runs every
-// pending event of its 64 words (one word per lane, the same event loop as
-// the per-ensemble kernel) and takes the next item until the queue is empty.
+// Work item = (ensemble, 64 consecutive words) for bit-sliced members, or
+// (ensemble, 2 consecutive words) for members on the lanes engine (one
+// replica per thread, same results); one wave takes one item at a time from
+// a device queue ordered longest-first by the host, runs every pending event
+// of its words (the same event loops as the per-ensemble kernels) and takes
+// the next item until the queue is empty.
 // Items never depend on each other: each word's events are its own, so the
 // order in which waves take items changes nothing in the results.  Every
 // wave leaves the loop once the queue counter passes the item count.
@@ -39,6 +41,14 @@ __device__ __noinline__ void wm_word_bucket(const WmArgs *ap, uint64_t w, uint64
     wm_word<NB, BC, -1, -1>(a, w);
 }
 
+__device__ __noinline__ void wm_lanes_item(const WmArgs *ap, uint64_t w, uint32_t *sq,
+                                           uint64_t max_events)
+{
+    WmArgs a = *ap;
+    a.max_events = max_events;
+    wm_lanes(a, w, sq);
+}
+
 #define BWG_PERSIST_CASE(id, nb, bc)        \
     case id:                                \
         wm_word_bucket<nb, bc>(&ens[bi.ens].a, w, max_events); \
@@ -50,12 +60,19 @@ __global__ __launch_bounds__(64, 2) void wm_persistent_kernel(const BatchEns *en
                                                               uint32_t *counter,
                                                               uint64_t max_events)
 {
+    __shared__ uint32_t sq[2][32];
     for (;;) {
         uint32_t it = 0;
         if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
         it = __shfl(it, 0);
         if (it >= n_items) break;
         const BatchItem bi = items[it];
+        if (bi.ens & BATCH_ITEM_LANES) {
+            const int half = threadIdx.x >> 5;
+            wm_lanes_item(&ens[bi.ens & ~BATCH_ITEM_LANES].a, (uint64_t)bi.word0 + half, sq[half],
+                          max_events);
+            continue;
+        }
         const int v = ens[bi.ens].variant;
         const uint64_t w = (uint64_t)bi.word0 + threadIdx.x;
         switch (v) {

@@ -59,7 +59,13 @@ static int pick_bucket(const bwg_ens *e)
     return best < 0 ? -1 : kPersistVariants[best].id;
 }
 
-static uint64_t n_items_of(const bwg_ens *e) { return (((e->M + 31) / 32) + 63) / 64; }
+// Words per work item: 64 (one per lane) for bit-sliced members, 2 (one per
+// half wave, one replica per lane) for members on the lanes engine.
+static uint64_t item_words(const bwg_ens *e) { return e->engine == BWG_ENGINE_LANES ? 2 : 64; }
+static uint64_t n_items_of(const bwg_ens *e)
+{
+    return (((e->M + 31) / 32) + item_words(e) - 1) / item_words(e);
+}
 
 static uint64_t layout_bytes(int n, uint64_t items, uint64_t *off_ens, uint64_t *off_budget,
                              uint64_t *off_items, uint64_t *off_counter)
@@ -83,8 +89,8 @@ static int check_members(bwg_ens *const *ens, int32_t n, uint64_t *items)
     for (int k = 0; k < n; ++k) {
         const bwg_ens *e = ens[k];
         if (!e) return fail(BWG_EINVAL, "null ensemble %d", k);
-        if (e->engine != BWG_ENGINE_BITWISE)
-            return fail(BWG_EUNSUPPORTED, "ensemble %d: batches run the bit-sliced engine", k);
+        if (e->engine != BWG_ENGINE_BITWISE && e->engine != BWG_ENGINE_LANES)
+            return fail(BWG_EUNSUPPORTED, "ensemble %d: batches run the bit-plane engines", k);
         if (e->lat)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: lattices run their own launches", k);
         if (pick_bucket(e) < 0)
@@ -145,8 +151,11 @@ static int set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, hipStream_t
         const int bk = pick_bucket(e);
         b->bucket.push_back(bk);
         const PersistVariant &v = kPersistVariants[bk];
-        // per-event issue cost estimate (orders the queue only)
-        b->cost.push_back(100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
+        // per-event issue cost of one item (orders the queue only): a lanes
+        // item makes one Philox call and unpacks B planes per event
+        b->cost.push_back(e->engine == BWG_ENGINE_LANES
+                              ? 140.0 + 3.0 * nt->q.B
+                              : 100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
         BatchEns &d = b->h_ens[k];
         memset(&d, 0, sizeof d);
         WmArgs &a = d.a;
@@ -238,8 +247,10 @@ static int stage_items(bwg_batch *b, hipStream_t s)
         const bwg_ens *e = b->ens[k];
         const double c = b->cost[k] * (double)e->pending;
         const uint64_t words = (e->M + 31) / 32;
-        for (uint64_t w0 = 0; w0 < words; w0 += 64)
-            q.push_back({c, BatchItem{(uint32_t)k, (uint32_t)w0}});
+        const uint64_t step = item_words(e);
+        const uint32_t tag = e->engine == BWG_ENGINE_LANES ? BATCH_ITEM_LANES : 0u;
+        for (uint64_t w0 = 0; w0 < words; w0 += step)
+            q.push_back({c, BatchItem{(uint32_t)k | tag, (uint32_t)w0}});
     }
     if (b->order == 0)
         std::stable_sort(q.begin(), q.end(),

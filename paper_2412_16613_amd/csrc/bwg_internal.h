@@ -78,6 +78,7 @@ extern const WmVariant kWmVariants[];
 extern const int kWmVariantCount;
 
 hipError_t launch_plain(const PlainArgs &a, hipStream_t s, int block);
+hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s);
 
 // ---- batches ----
 struct BatchEns {
@@ -86,9 +87,10 @@ struct BatchEns {
     int32_t pad;
 };
 struct BatchItem {
-    uint32_t ens;           // index into the BatchEns array
-    uint32_t word0;         // first of 64 words
+    uint32_t ens;           // index into the BatchEns array, | BATCH_ITEM_LANES
+    uint32_t word0;         // first of 64 words (2 words for a lanes item)
 };
+constexpr uint32_t BATCH_ITEM_LANES = 0x80000000u;
 struct BatchBudget {
     const uint64_t *T;      // Poisson table on the device (len 0: no events)
     uint64_t len;

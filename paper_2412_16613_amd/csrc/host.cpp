@@ -374,7 +374,7 @@ static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_ca
     L.wp = (words + 63) / 64 * 64;
     const uint64_t mp = 32 * L.wp;
     uint64_t off = 0;
-    if (engine == BWG_ENGINE_BITWISE) {
+    if (engine != BWG_ENGINE_PLAIN) {
         L.planes = off;
         off = align256(off + 3ull * (uint64_t)n->q.b * L.wp * 4);
         L.counts = ~0ull;
@@ -388,7 +388,7 @@ static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_ca
     L.Et = off;
     off = align256(off + mp * 8);
     L.real = off;
-    off = align256(off + (engine == BWG_ENGINE_BITWISE ? L.wp : mp) * 8);
+    off = align256(off + (engine != BWG_ENGINE_PLAIN ? L.wp : mp) * 8);
     L.table = off;
     off = align256(off + table_cap * 8);
     L.scratch = off;
@@ -401,7 +401,7 @@ static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_ca
 static int check_engine(const bwg_net *n, int engine, const WmVariant **v)
 {
     *v = nullptr;
-    if (engine == BWG_ENGINE_BITWISE) {
+    if (engine == BWG_ENGINE_BITWISE || engine == BWG_ENGINE_LANES) {
         if (!n->shape_ok)
             return fail(BWG_EUNSUPPORTED,
                         "network is not of the Frank family the bit-sliced kernel implements");
@@ -473,7 +473,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->bytes = buf_bytes;
     e->wp = L.wp;
     e->nb = n->q.b;  // planes per species in memory
-    if (e->engine == BWG_ENGINE_BITWISE)
+    if (e->engine != BWG_ENGINE_PLAIN)
         e->planes = (uint32_t *)(e->buf + L.planes);
     else
         e->counts = (int32_t *)(e->buf + L.counts);
@@ -488,6 +488,16 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
 }
 
 extern "C" void bwg_ensemble_destroy(bwg_ens *e) { delete e; }
+
+extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (e->lat) return fail(BWG_EINVAL, "lattices have one engine");
+    if (e->engine == BWG_ENGINE_PLAIN || (engine != BWG_ENGINE_BITWISE && engine != BWG_ENGINE_LANES))
+        return fail(BWG_EINVAL, "only the bit-sliced and lanes engines share a state layout");
+    e->engine = engine;
+    return BWG_OK;
+}
 
 static int take_event(bwg_ens *e, hipEvent_t *ev)
 {
@@ -561,7 +571,7 @@ extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts
     } else if (mode != BWG_INIT_MULTINOMIAL) {
         return fail(BWG_EINVAL, "unknown init mode %d", mode);
     }
-    if (e->engine == BWG_ENGINE_BITWISE) {
+    if (e->engine != BWG_ENGINE_PLAIN) {
         if (mode == BWG_INIT_FIXED)
             HIP_TRY(launch_init_fixed(e->planes, e->nb, e->wp, e->M, c, e->E, e->Et, e->real, s));
         else
@@ -599,7 +609,7 @@ void bwg::note_ran(bwg_ens *e, uint64_t max_events)
 static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
 {
     const bwg_net *n = e->net;
-    if (e->engine == BWG_ENGINE_BITWISE) {
+    if (e->engine != BWG_ENGINE_PLAIN) {
         WmArgs a{};
         a.planes = e->planes;
         a.E = e->E;
@@ -619,7 +629,10 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         hipEvent_t ev = nullptr;
         int rc = mark_begin(e, s, &ev);
         if (rc) return rc;
-        HIP_TRY(e->var->fn(a, s, e->block));
+        if (e->engine == BWG_ENGINE_LANES)
+            HIP_TRY(launch_wm_lanes(a, s));
+        else
+            HIP_TRY(e->var->fn(a, s, e->block));
         rc = mark_end(e, s, ev);
         if (rc) return rc;
     } else {
@@ -751,7 +764,7 @@ extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)
     if (!e || !dst) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
     if (e->lat) return lat_read_counts(e, dst, s);
-    if (e->engine == BWG_ENGINE_BITWISE)
+    if (e->engine != BWG_ENGINE_PLAIN)
         HIP_TRY(launch_read_counts_planes(e->planes, e->nb, e->wp, e->M, dst, s));
     else
         HIP_TRY(launch_read_counts_plain(e->counts, e->M, dst, s));
@@ -764,7 +777,7 @@ extern "C" int bwg_ensemble_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst,
     if (n_bins < 1 || n_bins > 16384) return fail(BWG_EINVAL, "n_bins %d out of range", n_bins);
     hipStream_t s = (hipStream_t)stream;
     if (e->lat) return lat_histogram(e, n_bins, dst, s);
-    HIP_TRY(launch_histogram(e->engine == BWG_ENGINE_BITWISE ? e->planes : nullptr, e->counts,
+    HIP_TRY(launch_histogram(e->engine != BWG_ENGINE_PLAIN ? e->planes : nullptr, e->counts,
                              e->nb, e->wp, e->M, e->net->n_tot, n_bins, dst, s));
     return BWG_OK;
 }
@@ -776,7 +789,7 @@ extern "C" int bwg_ensemble_read_events(bwg_ens *e, uint64_t *dev_events, uint64
     hipStream_t s = (hipStream_t)stream;
     if (dev_events) HIP_TRY(launch_copy_u64(e->E, dev_events, e->M, s));
     if (dev_real) {
-        if (e->engine == BWG_ENGINE_BITWISE)
+        if (e->engine != BWG_ENGINE_PLAIN)
             HIP_TRY(launch_copy_u64(e->real, dev_real, (e->M + 31) / 32, s));
         else
             HIP_TRY(launch_copy_u64(e->real, dev_real, e->M, s));
@@ -789,7 +802,7 @@ extern "C" int bwg_ensemble_stats(bwg_ens *e, void *stream, bwg_stats *out)
     if (!e || !out) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_sum_u64(e->E, e->M, e->scratch, 0, s));
-    HIP_TRY(launch_sum_u64(e->real, e->engine == BWG_ENGINE_BITWISE ? (e->M + 31) / 32 : e->M,
+    HIP_TRY(launch_sum_u64(e->real, e->engine != BWG_ENGINE_PLAIN ? (e->M + 31) / 32 : e->M,
                            e->scratch, 1, s));
     uint64_t h[2];
     HIP_TRY(hipMemcpyAsync(h, e->scratch, sizeof h, hipMemcpyDeviceToHost, s));

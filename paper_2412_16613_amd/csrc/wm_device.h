@@ -301,3 +301,115 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
 }
 
 }  // namespace bwg
+
+namespace bwg {
+
+// One word of an ensemble with one replica per thread ("lanes" engine): the
+// 32 threads of one half of a wave hold the word's 32 replicas as int32
+// counts, unpacked from the bit planes at the start and packed back at the
+// end.  Every event draws the same EVENT planes as wm_word (thread q < 8 of
+// the half makes the Philox call of plane-quad q and shares it through sq,
+// this half's LDS), and each thread compares its own threshold with the
+// cumulative weights in integer arithmetic; the result is bit for bit the
+// one wm_word gives.  The work per event is a few hundred instructions for
+// 32 replicas instead of about 1200 for the bit-sliced word, so a word's
+// chain of events finishes several times sooner at a higher cost per
+// replica-event: the choice for long chains on few replicas.
+__device__ __forceinline__ void wm_lanes(const WmArgs &a, const uint64_t w, uint32_t *sq)
+{
+    if (w >= a.n_words) return;
+    const int l = threadIdx.x & 31;
+    const int hv = (threadIdx.x >> 5) & 1;
+    const uint64_t i = 32 * w + (uint64_t)l;
+    const bool live = i < a.M;
+    const uint64_t E0 = live ? a.E[i] : 0, T0 = live ? a.Etgt[i] : 0;
+    const bool mine = live && E0 < T0;
+    // word window over pending lanes, as in wm_word
+    uint64_t lo = mine ? E0 : ~0ull, hi = mine ? T0 : 0;
+    for (int o = 16; o; o >>= 1) {
+        const uint64_t lo2 = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)lo, o, 32) |
+                             ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(lo >> 32), o, 32) << 32);
+        const uint64_t hi2 = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)hi, o, 32) |
+                             ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(hi >> 32), o, 32) << 32);
+        lo = lo2 < lo ? lo2 : lo;
+        hi = hi2 > hi ? hi2 : hi;
+    }
+    if (hi == 0) lo = hi = 0;
+    if (a.max_events && hi > lo + a.max_events) hi = lo + a.max_events;
+
+    const int nbm = a.nb_mem;
+    int32_t cL = 0, cD = 0, cA = 0;
+    for (int q = 0; q < nbm; ++q) {
+        cL |= (int32_t)((a.planes[((uint64_t)0 * nbm + q) * a.wp + w] >> l) & 1u) << q;
+        cD |= (int32_t)((a.planes[((uint64_t)1 * nbm + q) * a.wp + w] >> l) & 1u) << q;
+        cA |= (int32_t)((a.planes[((uint64_t)2 * nbm + q) * a.wp + w] >> l) & 1u) << q;
+    }
+    const int B = a.B;
+    const int nq = (B + 3) / 4;
+    const uint64_t cu = a.cu;
+    const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
+    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    uint32_t nreal = 0;
+    for (uint64_t e = lo; e < hi; ++e) {
+        if (l < nq) {
+            uint32_t o0, o1, o2, o3;
+            philox4x32_10((uint32_t)e,
+                          (DOM_EVENT << 24) | ((uint32_t)l << 16) | ((uint32_t)(e >> 32) & 0xFFFFu),
+                          (uint32_t)w, a.net_id, k0, k1, o0, o1, o2, o3);
+            sq[4 * l + 0] = o0;
+            sq[4 * l + 1] = o1;
+            sq[4 * l + 2] = o2;
+            sq[4 * l + 3] = o3;
+        }
+        __builtin_amdgcn_wave_barrier();
+        uint64_t n = 0;
+        for (int q = 0; q < B; ++q) n |= (uint64_t)((sq[q] >> l) & 1u) << q;
+        __builtin_amdgcn_wave_barrier();
+        const bool act = mine && E0 <= e && e < T0;
+        if (act) {
+            const uint64_t U = cu * (uint64_t)cA;
+            const uint64_t S2 = 2 * U;
+            const uint64_t S3 = S2 + (has_a ? ((uint64_t)cA * (uint64_t)cL) << a.fa : 0);
+            const uint64_t S4 = S3 + (has_a ? ((uint64_t)cA * (uint64_t)cD) << a.fa : 0);
+            const uint64_t S5 = S4 + (has_i ? ((uint64_t)cL * (uint64_t)cD) << a.fi : 0);
+            if (n < U) {
+                cL += 1;
+                cA -= 1;
+                ++nreal;
+            } else if (n < S2) {
+                cD += 1;
+                cA -= 1;
+                ++nreal;
+            } else if (n < S3) {
+                cL += 1;
+                cA -= 1;
+                ++nreal;
+            } else if (n < S4) {
+                cD += 1;
+                cA -= 1;
+                ++nreal;
+            } else if (n < S5) {
+                cL -= 1;
+                cD -= 1;
+                cA += 2;
+                ++nreal;
+            }
+        }
+    }
+    // pack the counts back into the planes of the word (lane 0 of the half stores)
+    for (int q = 0; q < nbm; ++q) {
+        const uint32_t bl = (uint32_t)(__ballot((cL >> q) & 1) >> (32 * hv));
+        const uint32_t bd = (uint32_t)(__ballot((cD >> q) & 1) >> (32 * hv));
+        const uint32_t ba = (uint32_t)(__ballot((cA >> q) & 1) >> (32 * hv));
+        if (l == 0) {
+            a.planes[((uint64_t)0 * nbm + q) * a.wp + w] = bl;
+            a.planes[((uint64_t)1 * nbm + q) * a.wp + w] = bd;
+            a.planes[((uint64_t)2 * nbm + q) * a.wp + w] = ba;
+        }
+    }
+    if (live) a.E[i] = hi < E0 ? E0 : (hi > T0 ? T0 : hi);
+    for (int o = 16; o; o >>= 1) nreal += (uint32_t)__shfl_xor((int)nreal, o, 32);
+    if (l == 0) a.real[w] += nreal;
+}
+
+}  // namespace bwg

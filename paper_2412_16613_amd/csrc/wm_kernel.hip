@@ -61,6 +61,21 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
     X(12, 28, -1, -1)                                                         \
     X(14, 32, -1, -1)
 
+// Lanes engine: 8 words per 256-thread block, one replica per thread.
+__global__ __launch_bounds__(256) void wm_lanes_kernel(WmArgs a)
+{
+    __shared__ uint32_t sq[8][32];
+    const int half = threadIdx.x >> 5;
+    wm_lanes(a, 8 * (uint64_t)blockIdx.x + half, sq[half]);
+}
+
+hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
+{
+    const uint64_t grid = (a.n_words + 7) / 8;
+    hipLaunchKernelGGL(wm_lanes_kernel, dim3((uint32_t)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 #define BWG_WM_INST(nb, bc, fa, cu) \
     template __global__ void wm_event_kernel<nb, bc, fa, cu>(WmArgs);
 BWG_WM_VARIANTS(BWG_WM_INST)

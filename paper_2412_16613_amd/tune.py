@@ -1,22 +1,36 @@
 """Autotuner for batched launches.
 
-Chooses the persistent grid size (wavefronts) and the queue order of a batch
-by timing one short advance of the actual batch for each candidate, and
-remembers the choice in a JSON cache keyed by the batch's shape (networks'
-plane widths, replica counts and horizons, rounded).  Tuning never changes
-results: every candidate runs the same per-replica chains, so the timing runs
-use scratch copies of the ensembles.
+Chooses, for a batch of networks, (1) which members run on the lanes engine
+(one replica per thread, 64 replicas per wavefront) instead of bit-sliced
+words (2048 replicas per wavefront), (2) the persistent grid size in
+wavefronts and (3) the queue order, by timing one short advance of the
+actual batch for each candidate, and remembers the choice in a JSON cache
+keyed by the batch's shape (networks, replica counts and horizons, rounded).
+
+The lanes engine draws the same random planes and applies the same integer
+comparisons as the bit-sliced one, so no choice changes any result: the
+timing runs use scratch ensembles, and the tuned batch gives bit for bit
+what any other configuration gives.
+
+Why lanes: a batch finishes when its longest word chain does.  A bit-sliced
+word runs its replicas' events one after another at ~1200 VALU slots per
+event, while a lanes item runs the same events at a few hundred per event
+(for 64 replicas).  Members whose chain (events per replica x cost per
+event) exceeds the average work per wavefront by a factor theta move to
+lanes; theta is tuned.
 """
 
 import hashlib
 import json
+import math
 import os
 import time
 
 CACHE = os.environ.get("BWG_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                     "tune_cache.json"))
-CANDIDATES = [(w, o) for w in (1024, 2048, 3072, 4096) for o in (0,)] + [(2048, 1)]
+GRIDS = [(w, o) for w in (1024, 2048, 3072, 4096) for o in (0,)] + [(2048, 1)]
+THETAS = [None, 4.0, 2.0, 1.0, 0.5, 0.25]
 
 
 def signature(items):
@@ -25,7 +39,7 @@ def signature(items):
     for net, M, t in items:
         h.update(("%d:%s:%d:%.3g;" % (net["n_tot"], ",".join("%.4g" % k for k in net["rates"]),
                                        M, t)).encode())
-    return h.hexdigest()[:16]
+    return h.hexdigest()[:17]
 
 
 def _load():
@@ -43,35 +57,77 @@ def _save(d):
     os.replace(tmp, CACHE)
 
 
+def lanes_members(items, quantized, theta, waves=2048):
+    """Members to run on the lanes engine for threshold theta (None: none).
+    Cost model (issue slots): a bit-sliced word pays ~100 per Philox quad plus
+    the selection and updates per event; the model only ranks members."""
+    if theta is None:
+        return []
+    chain, word_cost, work = [], [], 0.0
+    for (net, M, t), q in zip(items, quantized):
+        ev = q["Lambda"] * t
+        c = 100.0 * math.ceil(q["B"] / 4) + 8 * q["B"] + 40 * q["b"]
+        words = (M + 31) // 32
+        chain.append(ev * c)
+        word_cost.append(c)
+        work += ev * c * math.ceil(words / 64)
+    per_wave = work / waves
+    return [k for k, ch in enumerate(chain) if ch > theta * per_wave]
+
+
+def _time(bwg, torch, items, nets, waves, order, lanes, horizon_scale, device):
+    ens = []
+    for k, (net, M, _) in enumerate(items):
+        e = bwg.Ensemble(nets[k], M, seed=12345, net_id=k, device=device,
+                         engine="lanes" if k in lanes else "bitwise")
+        e.init_fixed((0, 0, net["n_tot"]))
+        ens.append(e)
+    b = bwg.Batch(ens, waves=waves, order=order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.advance([t * horizon_scale for _, _, t in items])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del b, ens
+    return dt
+
+
 def tune(items, horizon_scale=0.02, device="cuda", force=False):
-    """Return (waves, order, timings) for a batch described by items."""
+    """Return dict(waves, order, lanes, timings) for a batch described by items."""
     import torch
     import paper_2412_16613_amd as bwg
     key = signature(items)
     cache = _load()
     if key in cache and not force:
-        c = cache[key]
-        return c["waves"], c["order"], c.get("timings", {})
+        return cache[key]
     nets = [bwg.Network(net) for net, _, _ in items]
+    quantized = [n.quantized() for n in nets]
     timings = {}
-    for waves, order in CANDIDATES:
-        ens = []
-        for k, (net, M, _) in enumerate(items):
-            e = bwg.Ensemble(nets[k], M, seed=12345, net_id=k, device=device)
-            e.init_fixed((0, 0, net["n_tot"]))
-            ens.append(e)
-        b = bwg.Batch(ens, waves=waves, order=order)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.advance([t * horizon_scale for _, _, t in items])
-        torch.cuda.synchronize()
-        timings["%d/%d" % (waves, order)] = time.perf_counter() - t0
-        del b, ens
-    best = min(timings, key=timings.get)
-    waves, order = (int(x) for x in best.split("/"))
-    cache[key] = {"waves": waves, "order": order, "timings": timings}
+    best = None
+    seen = set()
+    for theta in THETAS:
+        lanes = lanes_members(items, quantized, theta)
+        sig = tuple(lanes)
+        if sig in seen:
+            continue
+        seen.add(sig)
+        dt = _time(bwg, torch, items, nets, 2048, 0, set(lanes), horizon_scale, device)
+        timings["theta=%s/2048/0" % theta] = dt
+        if best is None or dt < best[0]:
+            best = (dt, lanes)
+    lanes = best[1]
+    choice = (best[0], 2048, 0)
+    for waves, order in GRIDS:
+        if (waves, order) == (2048, 0):
+            continue
+        dt = _time(bwg, torch, items, nets, waves, order, set(lanes), horizon_scale, device)
+        timings["%d/%d" % (waves, order)] = dt
+        if dt < choice[0]:
+            choice = (dt, waves, order)
+    out = {"waves": choice[1], "order": choice[2], "lanes": lanes, "timings": timings}
+    cache[key] = out
     try:
         _save(cache)
     except OSError:
         pass
-    return waves, order, timings
+    return out

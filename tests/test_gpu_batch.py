@@ -136,3 +136,29 @@ def test_uneven_batch_workload_sample(torch):
     for e, (_, _, t) in zip(alone, mix):
         e.advance(t)
     _assert_same(_state(torch, batched), _state(torch, alone))
+
+
+def test_batch_with_lanes_members_equals_alone(torch):
+    """Members on the lanes engine (2-word items, one replica per thread)
+    beside bit-sliced members give the same results as each alone."""
+    mix = MIX[:6]
+    alone = _ensembles(mix, seed=8)
+    for e, (_, _, t) in zip(alone, mix):
+        e.advance(t)
+    ref = _state(torch, alone)
+    ens = _ensembles(mix, seed=8)
+    for k in (0, 3, 5):
+        ens[k].set_engine("lanes")
+    b = bwg.Batch(ens, waves=512)
+    b.advance([t for _, _, t in mix])
+    _assert_same(_state(torch, ens), ref)
+    # and capped passes
+    ens = _ensembles(mix, seed=8)
+    for k in (1, 3):
+        ens[k].set_engine("lanes")
+    b = bwg.Batch(ens, waves=256)
+    for e, (_, _, t) in zip(ens, mix):
+        e.schedule(t)
+    while any(e.pending() for e in ens):
+        b.run(400)
+    _assert_same(_state(torch, ens), ref)

@@ -67,11 +67,11 @@ def group_sums(x, M):
 def check_parity(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0):
     _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl)
     counts, ev, real, ens = gpu_run(torch, net, M, init, schedule, seed, net_id, engine, epl)
-    draw = ssa.DRAW_EVENT if engine == "bitwise" else ssa.DRAW_PLAIN
+    draw = ssa.DRAW_PLAIN if engine == "plain" else ssa.DRAW_EVENT
     o = oracle_run(net, M, init, schedule, seed, net_id, draw)
     np.testing.assert_array_equal(counts, o.counts)
     np.testing.assert_array_equal(ev, o.E)
-    if engine == "bitwise":
+    if engine != "plain":
         np.testing.assert_array_equal(real, group_sums(o.real, M))
     else:
         np.testing.assert_array_equal(real, o.real)
@@ -224,3 +224,46 @@ def test_full_size_well_mixed_workload_sampled(torch):
         E.init(c["init"])
         E.advance(c["t_end"])
         np.testing.assert_array_equal(counts[first:first + 16], E.counts)
+
+
+# ---- lanes engine: one replica per thread on the bit-plane state ------------
+
+@pytest.mark.parametrize("n_tot,M,sched", [
+    (32, 1024, [("advance", 50.0)]),
+    (100, 1000, [("advance", 2.0), ("advance", 5.5)]),
+    (1024, 333, [("step", 3000)]),
+    (12, 65, [("advance", 40.0), ("step", 77)]),
+])
+def test_lanes_engine_matches_oracle(torch, n_tot, M, sched):
+    check_parity(torch, frank_network(n_tot), M, ("fixed", (0, 0, n_tot)), sched, seed=4,
+                 net_id=3, engine="lanes")
+
+
+def test_lanes_engine_paper_network_and_chunking(torch):
+    check_parity(torch, paper_network(32), 200, ("multinomial",), [("step", 4000)], seed=2,
+                 engine="lanes")
+    check_parity(torch, frank_network(64), 97, ("fixed", (0, 0, 64)), [("advance", 8.0)],
+                 engine="lanes", epl=700)
+
+
+def test_switching_engines_mid_run_changes_nothing(torch):
+    net = frank_network(200, k0=0.03)
+    M = 2000
+    a = bwg.Ensemble(bwg.Network(net), M, seed=9, net_id=1)
+    b = bwg.Ensemble(bwg.Network(net), M, seed=9, net_id=1, engine="lanes")
+    for e in (a, b):
+        e.init_fixed((0, 0, 200))
+    a.advance(1.0)
+    b.advance(1.0)
+    b.set_engine("bitwise")
+    a.set_engine("lanes")
+    a.schedule(3.0)
+    b.schedule(3.0)
+    while a.pending() or b.pending():
+        a.run(500)
+        b.run(300)
+    for x, y in ((a.read_counts(), b.read_counts()), (a.read_events()[0], b.read_events()[0]),
+                 (a.read_events()[1], b.read_events()[1])):
+        np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+    with pytest.raises(bwg.BwgError):
+        bwg.Ensemble(bwg.Network(net), 10, engine="plain").set_engine("lanes")
