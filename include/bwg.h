@@ -280,6 +280,13 @@ int bwg_ensemble_kernel_time(bwg_ens *ens, double *ms, uint64_t *launches);
  * engines, lattices or a plain ensemble.  Takes effect at the next launch. */
 int bwg_ensemble_set_engine(bwg_ens *ens, int32_t engine);
 
+/* In batches, run the last n_words words of a bit-sliced ensemble (rounded so
+ * that the bit-sliced part is whole 64-word items) as lanes items of the same
+ * persistent launch: the two kinds of item fill the SIMDs that one wave per
+ * 64 words would leave idle.  Results do not change.  The ensemble's own
+ * launches are not affected.  EINVAL for lattices and the plain engine. */
+int bwg_ensemble_set_lanes_words(bwg_ens *ens, uint64_t n_words);
+
 /* Synchronises the stream and reports totals. */
 int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);
 

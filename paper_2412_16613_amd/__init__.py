@@ -248,6 +248,11 @@ class Ensemble:
         self.engine = engine
         return self
 
+    def set_lanes_words(self, n_words):
+        """In batches, run the last n_words words as lanes items."""
+        _abi.check(_lib().bwg_ensemble_set_lanes_words(self.handle, int(n_words)))
+        return self
+
     def kernel_time(self):
         """(ms, launches) of the event-kernel launches since the last call
         (ensembles created with time_kernels=True)."""

@@ -31,21 +31,56 @@ namespace bwg {
     X(9, 12, 32)                \
     X(10, 14, 32)
 
+// The descriptor fields are the same for every lane of the wave; arguments
+// of an out-of-line function are not known to be, so they are made
+// wave-uniform (scalar registers, uniform branches on shifts and weights).
+__device__ __forceinline__ uint32_t uni32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    return (uint64_t)uni32((uint32_t)v) | ((uint64_t)uni32((uint32_t)(v >> 32)) << 32);
+}
+template <typename T>
+__device__ __forceinline__ T *uniptr(T *p)
+{
+    return (T *)uni64((uint64_t)p);
+}
+__device__ __forceinline__ WmArgs uniform_args(const WmArgs *ap, uint64_t max_events)
+{
+    WmArgs a = *ap;
+    a.planes = uniptr(a.planes);
+    a.E = uniptr(a.E);
+    a.Etgt = uniptr(a.Etgt);
+    a.real = uniptr(a.real);
+    a.wp = uni64(a.wp);
+    a.n_words = uni64(a.n_words);
+    a.M = uni64(a.M);
+    a.seed = uni64(a.seed);
+    a.max_events = uni64(max_events);
+    a.net_id = uni32(a.net_id);
+    a.B = (int32_t)uni32((uint32_t)a.B);
+    a.cu = uni32(a.cu);
+    a.fa = (int32_t)uni32((uint32_t)a.fa);
+    a.fi = (int32_t)uni32((uint32_t)a.fi);
+    a.nb_mem = (int32_t)uni32((uint32_t)a.nb_mem);
+    return a;
+}
+
 // One out-of-line function per bucket, so that each gets its own register
 // allocation instead of the union of all of them.
 template <int NB, int BC>
 __device__ __noinline__ void wm_word_bucket(const WmArgs *ap, uint64_t w, uint64_t max_events)
 {
-    WmArgs a = *ap;
-    a.max_events = max_events;
+    const WmArgs a = uniform_args(ap, max_events);
     wm_word<NB, BC, -1, -1>(a, w);
 }
 
 __device__ __noinline__ void wm_lanes_item(const WmArgs *ap, uint64_t w, uint32_t *sq,
                                            uint64_t max_events)
 {
-    WmArgs a = *ap;
-    a.max_events = max_events;
+    const WmArgs a = uniform_args(ap, max_events);
     wm_lanes(a, w, sq);
 }
 

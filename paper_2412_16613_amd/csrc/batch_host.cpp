@@ -15,7 +15,8 @@ using namespace bwg;
 struct bwg_batch {
     std::vector<bwg_ens *> ens;
     std::vector<int> bucket;       // persistent-kernel plane bucket per member
-    std::vector<double> cost;      // issue cost of one event of one word, per member
+    std::vector<double> cost;      // issue cost of one event of a 64-word item, per member
+    std::vector<double> lane_cost; // the same for a 2-word lanes item
     int waves = 0;
     int order = 0;
     int cap_ens = 0;
@@ -59,12 +60,21 @@ static int pick_bucket(const bwg_ens *e)
     return best < 0 ? -1 : kPersistVariants[best].id;
 }
 
-// Words per work item: 64 (one per lane) for bit-sliced members, 2 (one per
-// half wave, one replica per lane) for members on the lanes engine.
-static uint64_t item_words(const bwg_ens *e) { return e->engine == BWG_ENGINE_LANES ? 2 : 64; }
+// Work items of a member: words [0, split) in items of 64 (one word per
+// lane, bit-sliced), words [split, words) in items of 2 (one per half wave,
+// one replica per lane: the lanes engine).  split is 0 for members on the
+// lanes engine and a multiple of 64 otherwise.
+static uint64_t lanes_split(const bwg_ens *e)
+{
+    const uint64_t words = (e->M + 31) / 32;
+    if (e->engine == BWG_ENGINE_LANES) return 0;
+    if (e->lanes_words >= words) return 0;
+    return (words - e->lanes_words + 63) / 64 * 64;
+}
 static uint64_t n_items_of(const bwg_ens *e)
 {
-    return (((e->M + 31) / 32) + item_words(e) - 1) / item_words(e);
+    const uint64_t words = (e->M + 31) / 32, split = std::min(lanes_split(e), words);
+    return (split + 63) / 64 + (words - split + 1) / 2;
 }
 
 static uint64_t layout_bytes(int n, uint64_t items, uint64_t *off_ens, uint64_t *off_budget,
@@ -144,6 +154,7 @@ static int set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, hipStream_t
     b->ens.assign(ens, ens + n);
     b->bucket.clear();
     b->cost.clear();
+    b->lane_cost.clear();
     b->n_items = items;
     for (int k = 0; k < n; ++k) {
         const bwg_ens *e = ens[k];
@@ -153,9 +164,8 @@ static int set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, hipStream_t
         const PersistVariant &v = kPersistVariants[bk];
         // per-event issue cost of one item (orders the queue only): a lanes
         // item makes one Philox call and unpacks B planes per event
-        b->cost.push_back(e->engine == BWG_ENGINE_LANES
-                              ? 140.0 + 3.0 * nt->q.B
-                              : 100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
+        b->cost.push_back(100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
+        b->lane_cost.push_back(140.0 + 3.0 * nt->q.B);
         BatchEns &d = b->h_ens[k];
         memset(&d, 0, sizeof d);
         WmArgs &a = d.a;
@@ -245,12 +255,13 @@ static int stage_items(bwg_batch *b, hipStream_t s)
     q.reserve(b->n_items);
     for (size_t k = 0; k < b->ens.size(); ++k) {
         const bwg_ens *e = b->ens[k];
-        const double c = b->cost[k] * (double)e->pending;
-        const uint64_t words = (e->M + 31) / 32;
-        const uint64_t step = item_words(e);
-        const uint32_t tag = e->engine == BWG_ENGINE_LANES ? BATCH_ITEM_LANES : 0u;
-        for (uint64_t w0 = 0; w0 < words; w0 += step)
-            q.push_back({c, BatchItem{(uint32_t)k | tag, (uint32_t)w0}});
+        const uint64_t words = (e->M + 31) / 32, split = std::min(lanes_split(e), words);
+        const double cw = b->cost[k] * (double)e->pending;
+        const double cl = b->lane_cost[k] * (double)e->pending;
+        for (uint64_t w0 = 0; w0 < split; w0 += 64)
+            q.push_back({cw, BatchItem{(uint32_t)k, (uint32_t)w0}});
+        for (uint64_t w0 = split; w0 < words; w0 += 2)
+            q.push_back({cl, BatchItem{(uint32_t)k | BATCH_ITEM_LANES, (uint32_t)w0}});
     }
     if (b->order == 0)
         std::stable_sort(q.begin(), q.end(),

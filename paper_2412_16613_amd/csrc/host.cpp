@@ -489,6 +489,15 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
 
 extern "C" void bwg_ensemble_destroy(bwg_ens *e) { delete e; }
 
+extern "C" int bwg_ensemble_set_lanes_words(bwg_ens *e, uint64_t n_words)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (e->lat || e->engine == BWG_ENGINE_PLAIN)
+        return fail(BWG_EINVAL, "only bit-plane well-mixed ensembles split their words");
+    e->lanes_words = n_words;
+    return BWG_OK;
+}
+
 extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)
 {
     if (!e) return fail(BWG_EINVAL, "null ensemble");

@@ -79,6 +79,7 @@ struct bwg_ens {
     uint64_t lag = 0;      // bound on how far a word's lanes can be apart
     uint64_t pending = 0;  // bound on the events any word still has to run
     bool inited = false;
+    uint64_t lanes_words = 0;  // in batches: trailing words run as lanes items
     // lattice ensembles
     bool lat = false;
     const bwg::LatVariant *lvar = nullptr;

@@ -162,3 +162,19 @@ def test_batch_with_lanes_members_equals_alone(torch):
     while any(e.pending() for e in ens):
         b.run(400)
     _assert_same(_state(torch, ens), ref)
+
+
+def test_split_members_equal_alone(torch):
+    """A bit-sliced member whose trailing words run as lanes items of the same
+    persistent launch gives the same results."""
+    net = frank_network(300, k0=0.003)
+    M = 64 * 32 * 3 + 45          # 3 whole 64-word items and a ragged tail
+    alone = bwg.Ensemble(bwg.Network(net), M, seed=6, net_id=44)
+    alone.init_fixed((0, 0, 300)).advance(2.0)
+    ref = _state(torch, [alone])
+    for lw in (1, 64, 100, 10 ** 6):
+        e = bwg.Ensemble(bwg.Network(net), M, seed=6, net_id=44)
+        e.init_fixed((0, 0, 300))
+        e.set_lanes_words(lw)
+        bwg.Batch([e], waves=300).advance([2.0])
+        _assert_same(_state(torch, [e]), ref)
