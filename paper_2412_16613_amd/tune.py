@@ -15,9 +15,10 @@ what any other configuration gives.
 Why lanes: a batch finishes when its longest word chain does.  A bit-sliced
 word runs its replicas' events one after another at ~1200 VALU slots per
 event, while a lanes item runs the same events at a few hundred per event
-(for 64 replicas).  Members whose chain (events per replica x cost per
-event) exceeds the average work per wavefront by a factor theta move to
-lanes; theta is tuned.
+(for 64 replicas), at about five times the work per replica-event.  The
+candidates move the k longest chains (events per replica x cost per event)
+to lanes, k = 0, 1, 2, 3, 4, 6, 8, 12; each is timed on a tenth of the
+horizons (both the longest chain and the total work scale with it).
 """
 
 import hashlib
@@ -30,7 +31,7 @@ CACHE = os.environ.get("BWG_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                     "tune_cache.json"))
 GRIDS = [(w, o) for w in (1024, 2048, 3072, 4096) for o in (0,)] + [(2048, 1)]
-THETAS = [None, 4.0, 2.0, 1.0, 0.5, 0.25]
+TOP_K = [0, 1, 2, 3, 4, 6, 8, 12]
 
 
 def signature(items):
@@ -57,22 +58,15 @@ def _save(d):
     os.replace(tmp, CACHE)
 
 
-def lanes_members(items, quantized, theta, waves=2048):
-    """Members to run on the lanes engine for threshold theta (None: none).
-    Cost model (issue slots): a bit-sliced word pays ~100 per Philox quad plus
-    the selection and updates per event; the model only ranks members."""
-    if theta is None:
-        return []
-    chain, word_cost, work = [], [], 0.0
+def chain_order(items, quantized):
+    """Members by decreasing word chain: expected events per replica times
+    the issue cost of one bit-sliced event (~100 slots per Philox quad plus
+    the selection and updates); the model only ranks members."""
+    chain = []
     for (net, M, t), q in zip(items, quantized):
         ev = q["Lambda"] * t
-        c = 100.0 * math.ceil(q["B"] / 4) + 8 * q["B"] + 40 * q["b"]
-        words = (M + 31) // 32
-        chain.append(ev * c)
-        word_cost.append(c)
-        work += ev * c * math.ceil(words / 64)
-    per_wave = work / waves
-    return [k for k, ch in enumerate(chain) if ch > theta * per_wave]
+        chain.append(ev * (100.0 * math.ceil(q["B"] / 4) + 8 * q["B"] + 40 * q["b"]))
+    return sorted(range(len(items)), key=lambda k: -chain[k])
 
 
 def _time(bwg, torch, items, nets, waves, order, lanes, horizon_scale, device):
@@ -92,7 +86,7 @@ def _time(bwg, torch, items, nets, waves, order, lanes, horizon_scale, device):
     return dt
 
 
-def tune(items, horizon_scale=0.02, device="cuda", force=False):
+def tune(items, horizon_scale=0.1, device="cuda", force=False):
     """Return dict(waves, order, lanes, timings) for a batch described by items."""
     import torch
     import paper_2412_16613_amd as bwg
@@ -104,15 +98,14 @@ def tune(items, horizon_scale=0.02, device="cuda", force=False):
     quantized = [n.quantized() for n in nets]
     timings = {}
     best = None
-    seen = set()
-    for theta in THETAS:
-        lanes = lanes_members(items, quantized, theta)
-        sig = tuple(lanes)
-        if sig in seen:
-            continue
-        seen.add(sig)
+    by_chain = chain_order(items, quantized)
+    _time(bwg, torch, items, nets, 2048, 0, set(), horizon_scale, device)   # warm caches
+    for k in TOP_K:
+        if k > len(items):
+            break
+        lanes = sorted(by_chain[:k])
         dt = _time(bwg, torch, items, nets, 2048, 0, set(lanes), horizon_scale, device)
-        timings["theta=%s/2048/0" % theta] = dt
+        timings["lanes=%d/2048/0" % k] = dt
         if best is None or dt < best[0]:
             best = (dt, lanes)
     lanes = best[1]
