@@ -43,7 +43,6 @@ DOM_BUDGET = 2
 DOM_INIT = 3
 DOM_PLAIN = 4
 DOM_COMPONENT = 5
-DOM_HOP = 6
 
 
 def event_plane_words(seed, net_id, group, event, n_planes):
@@ -92,3 +91,22 @@ def init_words(seed, net_id, replica, chunk):
     """128 random bits for initial-state draws of one replica."""
     ctr = (chunk & _M32, DOM_INIT << 24, replica & _M32, net_id & _M32)
     return philox4x32(ctr, seed_key(seed))
+
+
+DOM_SHARED = 6
+
+
+def shared_threshold(seed, net_id, e, Z):
+    """n shared by every replica at event e: uniform on [0, Z) by 32-bit
+    multiply-shift with rejection (Lemire) on output 0 of the SHARED draw;
+    counter (e low 32, 6 << 24 | attempt << 16 | e bits 32..47, 0, net_id);
+    the 256th attempt is taken as it is."""
+    thresh = (2 ** 32 - Z) % Z
+    m = 0
+    for attempt in range(256):
+        out = philox4x32((e & 0xFFFFFFFF, (DOM_SHARED << 24) | (attempt << 16) | ((e >> 32) & 0xFFFF),
+                          0, net_id), seed_key(seed))
+        m = out[0] * Z
+        if (m & 0xFFFFFFFF) >= thresh:
+            break
+    return m >> 32

@@ -64,13 +64,18 @@ def _validate(net):
 def _max_total_weight(net, c):
     """max over the simplex sum N = n_tot of sum_j c_j h_j(N), by enumeration
     of every state (int64; the guard keeps products far from overflow)."""
+    return _total_weight_range(net, c)[1]
+
+
+def _total_weight_range(net, c):
+    """(min, max) over the simplex sum N = n_tot of sum_j c_j h_j(N)."""
     S = len(net["species"])
     n = net["n_tot"]
     if S != 3:
         raise ValueError("enumeration implemented for 3 species")
     if max(c + [1]) * (n + 1) * (n + 1) >= (1 << 60):
         raise ValueError("weights too large for the enumeration")
-    best = 0
+    best, least = 0, None
     for n0 in range(n + 1):
         n1 = np.arange(0, n - n0 + 1, dtype=np.int64)
         n2 = (n - n0) - n1
@@ -87,7 +92,8 @@ def _max_total_weight(net, c):
                     h = h * (col * (col - 1) // 2)
             tot = tot + cj * h
         best = max(best, int(tot.max()))
-    return best
+        least = int(tot.min()) if least is None else min(least, int(tot.min()))
+    return least, best
 
 
 def quantize(net, precision_bits=7, max_total=None):
@@ -117,13 +123,20 @@ def quantize(net, precision_bits=7, max_total=None):
                 break
         else:
             raise ValueError("no scale reaches the precision")
+    min_total = None
     if max_total is None:
-        max_total = _max_total_weight(net, c)
+        min_total, max_total = _total_weight_range(net, c)
     B = max(1, (max_total - 1).bit_length()) if max_total > 1 else 1
     W = 1 << B
     Lam = math.ldexp(1.0, B) / s
     b = max(1, int(net["n_tot"]).bit_length())
-    return dict(c=c, f=f, s=s, B=B, W=W, Lambda=Lam, b=b, max_total=max_total)
+    # Z of the shared-threshold variant: the total weight when it is the same
+    # in every state (the paper's ghost reactions make it N(N-1)/2, Eq. (9)),
+    # else W; None when it does not fit 32 bits
+    z = max_total if (min_total is not None and min_total == max_total and max_total > 0) else W
+    z_shared = z if z < (1 << 32) else None
+    return dict(c=c, f=f, s=s, B=B, W=W, Lambda=Lam, b=b, max_total=max_total,
+                z_shared=z_shared)
 
 
 def weights(net, q, counts):

@@ -29,6 +29,13 @@
  *   INIT   (3): c0 = chunk, c2 = replica.
  *   PLAIN  (4): c0 = (event/4) low 32, hi16 = bits 32..47 of event/4,
  *               c2 = replica; n = out[event mod 4] mod 2^B.
+ *   SHARED (6): the paper's variant in which one n serves every copy at an
+ *               event (Sec. 4, the remark after the bitwise step; Sec. 6):
+ *               c0 = event low 32, quad field = attempt, c2 = 0; n uniform
+ *               on [0, Z) by 32-bit multiply-shift with rejection on out0
+ *               (the 256th attempt is taken as it is).  Z is the constant
+ *               total weight when the ghost reactions make it state
+ *               independent (the paper's Z, Eq. (9)), else W.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -47,11 +54,11 @@ typedef struct {
     int32_t products[ORC_MAX_R][ORC_MAX_S];
     int64_t c[ORC_MAX_R];
     int32_t B;
-    int32_t pad;
+    uint32_t z_shared;   /* Z of the SHARED draw */
     int64_t n_tot;
 } orc_net;
 
-enum { ORC_DRAW_EVENT = 1, ORC_DRAW_PLAIN = 4 };
+enum { ORC_DRAW_EVENT = 1, ORC_DRAW_PLAIN = 4, ORC_DRAW_SHARED = 6 };
 
 /* ---- Philox4x32-10 ---------------------------------------------------- */
 static void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -102,6 +109,21 @@ static uint32_t draw_plain(uint64_t seed, uint32_t net_id, uint64_t i,
            (uint32_t)i, net_id, seed, out);
     uint32_t v = out[e & 3u];
     return B >= 32 ? v : (v & ((1u << B) - 1u));
+}
+
+/* n shared by every replica at event e: uniform on [0, Z). */
+uint32_t orc_draw_shared(uint64_t seed, uint32_t net_id, uint64_t e, uint32_t Z)
+{
+    const uint32_t thresh = (uint32_t)(0u - Z) % Z;
+    uint64_t m = 0;
+    uint32_t out[4];
+    for (uint32_t attempt = 0; attempt < 256; ++attempt) {
+        philox((uint32_t)e, (6u << 24) | (attempt << 16) | (uint32_t)((e >> 32) & 0xFFFFu), 0u,
+               net_id, seed, out);
+        m = (uint64_t)out[0] * Z;
+        if ((uint32_t)m >= thresh) break;
+    }
+    return (uint32_t)(m >> 32);
 }
 
 /* h_j(N): product over reactants of C(N_X, r_X), r_X in {0,1,2}. */
@@ -187,7 +209,9 @@ int orc_wm_run(const orc_net *net, uint64_t seed, uint32_t net_id,
             uint64_t e = E0[k] + t;
             uint32_t thr = draw_mode == ORC_DRAW_PLAIN
                                ? draw_plain(seed, net_id, i, e, net->B)
-                               : draw_event(seed, net_id, i, e, net->B);
+                               : draw_mode == ORC_DRAW_SHARED
+                                     ? orc_draw_shared(seed, net_id, e, net->z_shared)
+                                     : draw_event(seed, net_id, i, e, net->B);
             int r = one_event(net, N, thr);
             if (r == -2) { bad = 1; break; }
             if (r >= 0 && changes_state(net, r)) ++nreal;

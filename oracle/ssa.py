@@ -24,6 +24,7 @@ _MAX_S, _MAX_R = 8, 16
 
 DRAW_EVENT = 1
 DRAW_PLAIN = 4
+DRAW_SHARED = 6
 
 
 def build(force=True):
@@ -44,7 +45,7 @@ class _Net(ctypes.Structure):
                 ("reactants", (ctypes.c_int32 * _MAX_S) * _MAX_R),
                 ("products", (ctypes.c_int32 * _MAX_S) * _MAX_R),
                 ("c", ctypes.c_int64 * _MAX_R), ("B", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("n_tot", ctypes.c_int64)]
+                ("z_shared", ctypes.c_uint32), ("n_tot", ctypes.c_int64)]
 
 
 _lib = None
@@ -68,6 +69,8 @@ def lib():
         L.orc_philox.argtypes = [P(u32), u64, P(u32)]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_select.argtypes = [P(_Net), P(i32), u32]
+        L.orc_draw_shared.argtypes = [u64, u32, u64, u32]
+        L.orc_draw_shared.restype = u32
         L.orc_select.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -89,6 +92,7 @@ def c_net(net, q):
             cn.products[j][x] = net["products"][j][x]
         cn.c[j] = q["c"][j]
     cn.B = q["B"]
+    cn.z_shared = q.get("z_shared") or 0
     cn.n_tot = net["n_tot"]
     return cn
 
@@ -121,6 +125,11 @@ def run_events(net, q, seed, net_id, first, counts, E0, K, draw=DRAW_EVENT,
         raise AssertionError("oracle invariant violated (negative count or "
                              "molecule count not conserved)")
     return counts, real, traj
+
+
+def draw_shared(seed, net_id, e, Z):
+    """n shared by every replica at event e (SHARED draw), uniform on [0, Z)."""
+    return lib().orc_draw_shared(seed, net_id, e, Z)
 
 
 def select(net, q, counts, n):
@@ -232,6 +241,8 @@ def py_events(net, q, seed, net_id, replica, counts, E0, K, draw=DRAW_EVENT):
     for e in range(E0, E0 + K):
         if draw == DRAW_PLAIN:
             n = _ph.plain_threshold(seed, net_id, replica, e, q["B"])
+        elif draw == DRAW_SHARED:
+            n = _ph.shared_threshold(seed, net_id, e, q["z_shared"])
         else:
             n = _ph.event_threshold(seed, net_id, replica, e, q["B"])
         w = weights(net, q, N)

@@ -352,3 +352,87 @@ def test_histogram_rule():
     # ee = +1 -> last bin; ee = -1 -> bin 0; ee = 0 -> bin 128; ee = 0.2 -> 153
     assert h[255] == 1 and h[0] == 1 and h[128] == 2 and h[153] == 1
     assert h.sum() == len(counts)
+
+
+# ---- shared-threshold variant (one n for every copy) --------------------------
+
+def test_shared_draw_is_uniform_on_z():
+    for Z in (7, 496):
+        n = np.array([ssa.draw_shared(11, 3, e, Z) for e in range(20 * Z if Z < 100 else 24800)])
+        assert n.max() < Z
+        bins = min(Z, 16)
+        obs = np.bincount((n * bins) // Z, minlength=bins)
+        exp = np.array([sum(1 for v in range(Z) if (v * bins) // Z == b) for b in range(bins)],
+                       float) * len(n) / Z
+        assert chi2_pvalue(obs, exp) > 1e-3
+
+
+def test_shared_z_is_the_paper_total():
+    """With the ghost reactions the total weight is N(N-1)/2 in every state
+    (Eq. (9)); Z of the shared draw is that total, else W."""
+    for n in (6, 32, 100):
+        q = quantize(paper_network(n))
+        assert q["z_shared"] == n * (n - 1) // 2
+    q = quantize(frank_network(64))
+    assert q["z_shared"] == q["W"]
+
+
+def _paper_chain_law(n_tot, start, K):
+    """Exact law after K events of the paper's iteration on [0, Z): reaction r
+    with probability a_r / Z, a_r the propensities of Eq. (7) with k = 1
+    (the ghosts keep the state)."""
+    from fractions import Fraction
+    Z = n_tot * (n_tot - 1) // 2
+    states = [(l, d, n_tot - l - d) for l in range(n_tot + 1) for d in range(n_tot + 1 - l)]
+    idx = {s: i for i, s in enumerate(states)}
+    p = [Fraction(0)] * len(states)
+    p[idx[start]] = Fraction(1)
+    for _ in range(K):
+        new = [Fraction(0)] * len(states)
+        for i, (l, d, a) in enumerate(states):
+            if not p[i]:
+                continue
+            moves = [(a * l, (l + 1, d, a - 1)), (a * d, (l, d + 1, a - 1)),
+                     (l * d, (l - 1, d - 1, a + 2))]
+            stay = Z - sum(w for w, _ in moves)
+            new[i] += p[i] * Fraction(stay, Z)
+            for w, s in moves:
+                if w:
+                    new[idx[s]] += p[i] * Fraction(w, Z)
+        p = new
+    return states, np.array([float(v) for v in p])
+
+
+def test_shared_threshold_law_of_one_copy():
+    """Each copy of the shared-threshold iteration is the paper's chain:
+    independent seeds give independent samples of its exact law."""
+    net = paper_network(6)
+    q = quantize(net)
+    start, K = (2, 2, 2), 12
+    states, p = _paper_chain_law(6, start, K)
+    idx = {s: i for i, s in enumerate(states)}
+    obs = np.zeros(len(states))
+    for seed in range(3000):
+        o = ssa.OracleEnsemble(net, 1, seed=seed, draw=ssa.DRAW_SHARED, q=q)
+        o.init(("fixed", start))
+        o.step(K)
+        obs[idx[tuple(int(v) for v in o.counts[0])]] += 1
+    assert chi2_pvalue(obs, p * 3000) > 1e-3
+
+
+def test_shared_threshold_is_one_number_per_event():
+    """Every copy compares the same n at an event (C and pure Python agree),
+    and copies from one state stay identical."""
+    net = paper_network(32)
+    q = quantize(net)
+    o = ssa.OracleEnsemble(net, 40, seed=5, draw=ssa.DRAW_SHARED, q=q)
+    o.init(("multinomial",))
+    start = o.counts.copy()
+    o.step(300)
+    for k in (0, 7, 39):
+        got, _ = ssa.py_events(net, q, 5, 0, k, list(start[k]), 0, 300, ssa.DRAW_SHARED)
+        assert list(o.counts[k]) == got
+    same = ssa.OracleEnsemble(net, 8, seed=5, draw=ssa.DRAW_SHARED, q=q)
+    same.init(("fixed", (10, 10, 12)))
+    same.step(500)
+    assert (same.counts == same.counts[0]).all()
