@@ -42,8 +42,8 @@ VALU_PEAK = 256 * 128 * 2.4e9   # 32-bit lane-slots/s: 256 CUs x 128 lanes/clk x
 # kernel -> (sha1 prefix of its sources, sources, bytes per launch, summary file).
 CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
 MEASURED_TRAFFIC = {
-    "wm_event_kernel": ("a291580fbca6", ("bitops.h", "wm_device.h", "wm_kernel.hip"),
-                        34007 * 1024, "profiles/wm_event_kernel_frank1024_2p20.md"),
+    "wm_event_kernel": ("1ee90bed23d7", ("bitops.h", "wm_device.h", "wm_kernel.hip"),
+                        (2 * 10667 + 12672) * 1024, "profiles/wm_event_kernel_frank1024_2p20.md"),
     "lat_event_kernel": ("730e9d3e6dcc", ("bitops.h", "lattice.hip"),
                          (2 * 3993080 + 8341990) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
@@ -74,9 +74,15 @@ def main():
     ap.add_argument("--cpu-replicas", type=int, default=65536)
     ap.add_argument("--cpu-replicas-lattice", type=int, default=64)
     ap.add_argument("--workload", default="well-mixed",
-                    choices=["well-mixed", "lattice", "batch", "serve"],
+                    choices=["well-mixed", "lattice", "batch", "serve", "gain"],
                     help="lattice: 64x64 compartments, 2^16 replicas; batch: the 256 uneven "
-                         "networks in one persistent launch")
+                         "networks in one persistent launch; gain: the paper's Q(N) sweep")
+    ap.add_argument("--gain-n", default="8,16,32,64,128,256,512,1024",
+                    help="gain: molecule counts N_tot of the paper's network")
+    ap.add_argument("--gain-replicas", type=int, default=1 << 22)
+    ap.add_argument("--gain-steps", type=int, default=100000)
+    ap.add_argument("--gain-repeats", type=int, default=3,
+                    help="gain: timed steps of T per bit-parallel mode (median taken)")
     ap.add_argument("--batch-nets", type=int, default=256)
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
@@ -108,6 +114,8 @@ def main():
         return bench_lattice(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "gain":
+        return bench_gain(args)
 
     c = config("c1")
     net, M, t_end = c["net"], c["replicas"], c["t_end"]
@@ -418,6 +426,72 @@ def bench_serve(args):
                       "chunk_events": args.chunk, "lattice_chunk_events": srv.lattice_chunk},
            "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
            "summary": s}
+    print(json.dumps(out))
+
+
+def bench_gain(args):
+    """The paper's gain experiment (Sec. 5, Efficiency gain) on the GPU.
+
+    For the paper's network (three reactions, unit weights, ghosts making the
+    total N(N-1)/2) at each N_tot: M replicas from independent multinomial
+    starts, T iterations each (a fixed number of steps, no time), run by
+    (1) the plain engine, one replica per thread with its own random number
+    per step (the serial algorithm run M times), (2) the bit-parallel engine
+    with a random threshold per replica, and (3) the bit-parallel engine with
+    one shared threshold on [0, Z) per step (the paper's variant).  Q is the
+    plain engine's time over the bit-parallel one's (median of the repeats;
+    each repeat continues the same replicas for another T steps)."""
+    import torch
+    import paper_2412_16613_amd as bwg
+    from workloads import paper_network
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    M, T = args.gain_replicas, args.gain_steps
+    modes = (("plain", "plain", False), ("bitwise", "bitwise", False),
+             ("shared", "bitwise", True))
+    rows = []
+    for N in [int(x) for x in args.gain_n.split(",")]:
+        network = bwg.Network(paper_network(N))
+        q = network.quantized()
+        row = {"n_tot": N, "B": q["B"], "b": q["b"], "Z": q["z_shared"]}
+        for name, engine, shared in modes:
+            ens = bwg.Ensemble(network, M, seed=1, net_id=N, engine=engine, device=dev,
+                               shared_threshold=shared, time_kernels=True)
+            ens.init(("multinomial",))
+            ens.step(max(1, T // 100))                   # warm-up
+            torch.cuda.synchronize()
+            ens.kernel_time()
+            runs = []
+            # the plain engine's time varies by well under 1 % between runs
+            for _ in range(1 if engine == "plain" else args.gain_repeats):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                ens.step(T)
+                b.record()
+                torch.cuda.synchronize()
+                runs.append(a.elapsed_time(b) / 1e3)
+            s = sorted(runs)[len(runs) // 2]
+            kt_ms, kt_n = ens.kernel_time()
+            row[name] = {"s": s, "runs_s": runs, "replica_steps_per_s": M * T / s,
+                         "kernel_ms": kt_ms / kt_n, "launches": kt_n}
+            del ens
+        for name in ("bitwise", "shared"):
+            row["Q_" + name] = row["plain"]["s"] / row[name]["s"]
+        rows.append(row)
+        print("gain N=%d: plain %.3f s, bitwise %.3f s, shared %.3f s, Q %.2f / %.2f"
+              % (N, row["plain"]["s"], row["bitwise"]["s"], row["shared"]["s"],
+                 row["Q_bitwise"], row["Q_shared"]), file=sys.stderr, flush=True)
+    last = rows[-1]
+    out = {"metric": "gain Q = plain-SSA time / bit-parallel shared-threshold time "
+                     "(same replicas and steps, 1 GPU)",
+           "value": last["Q_shared"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "u32 bit-planes", "data": "synthetic",
+           "config": {"workload": "paper's Frank network with ghosts, multinomial start, "
+                                  "%d replicas, T=%d steps, N_tot in %s"
+                                  % (M, T, args.gain_n),
+                      "value_at_n_tot": last["n_tot"]},
+           "rows": rows}
     print(json.dumps(out))
 
 

@@ -110,6 +110,9 @@ typedef struct {
     double s;
     double lambda;
     int64_t max_total;    /* max_N sum_j w_j(N)                               */
+    int64_t z_shared;     /* Z of BWG_OPT_SHARED_THRESHOLD: sum_j w_j(N) if it
+                             is the same for every N (ghost reactions, Eq. (9)),
+                             else 2^B; 0 if Z >= 2^32                          */
 } bwg_qnet;
 
 /*
@@ -141,10 +144,25 @@ typedef struct {
 /* flags of bwg_opts */
 #define BWG_OPT_TIME_KERNELS 1u  /* record HIP events around every event-kernel
                                     launch (bwg_ensemble_kernel_time)         */
+/* The paper's shared-threshold variant (Sec. 4, after the bitwise step; the
+ * speed-up it measures in Sec. 6): at event e every replica compares the
+ * same n, uniform on [0, z_shared), against its own cumulative weights, so
+ * one random number serves all replicas.  The replicas stay exact marginal
+ * copies of the chain but are no longer independent of each other.  Only
+ * for the bit-sliced and lanes engines on well-mixed networks (EUNSUPPORTED
+ * otherwise; ERANGE when z_shared is 0); such an ensemble moves only by
+ * bwg_ensemble_step (advance, schedule and batches return EUNSUPPORTED),
+ * since with z_shared < 2^B the event rate z_shared / s differs from lambda.
+ * A step runs in launches of at most 2 * table_capacity events (and at most
+ * events_per_launch, if set), each after a fill of its thresholds into the
+ * ensemble's table region. */
+#define BWG_OPT_SHARED_THRESHOLD 2u
 
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */
-    int32_t block;               /* threads per block, 0 = default            */
+    int32_t block;               /* threads per block of the event kernels:
+                                    0 (default), 64, 128, 192 or 256 (EINVAL
+                                    otherwise)                               */
     uint64_t table_capacity;     /* Poisson-table entries, 0 = default 65536  */
     uint64_t events_per_launch;  /* 0 = whole advance in one launch           */
     uint64_t flags;              /* BWG_OPT_*                                 */

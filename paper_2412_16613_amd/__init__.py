@@ -73,7 +73,8 @@ class Network:
         _abi.check(_lib().bwg_net_quantized(self.handle, ctypes.byref(q)))
         R = q.n_reactions
         return dict(c=list(q.c[:R]), f=q.f, B=q.B, W=1 << q.B, b=q.b, s=q.s,
-                    Lambda=q.lambda_, max_total=q.max_total, gpu_ok=bool(q.gpu_ok))
+                    Lambda=q.lambda_, max_total=q.max_total, gpu_ok=bool(q.gpu_ok),
+                    z_shared=q.z_shared or None)
 
     def lattice(self):
         """Integer form of a lattice network (bwg_net_lattice)."""
@@ -101,7 +102,7 @@ class Ensemble:
 
     def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
                  device="cuda", events_per_launch=0, table_capacity=0, block=0,
-                 time_kernels=False):
+                 time_kernels=False, shared_threshold=False):
         import torch
         self.torch = torch
         L = _lib()
@@ -113,7 +114,8 @@ class Ensemble:
         o.block = block
         o.table_capacity = table_capacity
         o.events_per_launch = events_per_launch
-        o.flags = _abi.BWG_OPT_TIME_KERNELS if time_kernels else 0
+        o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
+                   (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0))
         self._opts = o
         nbytes = ctypes.c_uint64()
         _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),

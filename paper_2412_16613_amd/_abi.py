@@ -26,6 +26,7 @@ BWG_INIT_MULTINOMIAL = 1
 BWG_INIT_UNIFORM_SITE = 2
 BWG_INIT_SITES = 3
 BWG_OPT_TIME_KERNELS = 1
+BWG_OPT_SHARED_THRESHOLD = 2
 
 # Every symbol include/bwg.h declares.
 SYMBOLS = (
@@ -58,7 +59,7 @@ class QNet(ctypes.Structure):
                 ("c", ctypes.c_int64 * BWG_MAX_REACTIONS), ("f", ctypes.c_int32),
                 ("B", ctypes.c_int32), ("b", ctypes.c_int32), ("gpu_ok", ctypes.c_int32),
                 ("s", ctypes.c_double), ("lambda_", ctypes.c_double),
-                ("max_total", ctypes.c_int64)]
+                ("max_total", ctypes.c_int64), ("z_shared", ctypes.c_int64)]
 
 
 class LatticeInfo(ctypes.Structure):

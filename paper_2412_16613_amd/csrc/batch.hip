@@ -65,6 +65,7 @@ __device__ __forceinline__ WmArgs uniform_args(const WmArgs *ap, uint64_t max_ev
     a.fa = (int32_t)uni32((uint32_t)a.fa);
     a.fi = (int32_t)uni32((uint32_t)a.fi);
     a.nb_mem = (int32_t)uni32((uint32_t)a.nb_mem);
+    a.zs = 0;  // batches hold no shared-threshold members
     return a;
 }
 

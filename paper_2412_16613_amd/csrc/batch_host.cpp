@@ -101,6 +101,8 @@ static int check_members(bwg_ens *const *ens, int32_t n, uint64_t *items)
         if (!e) return fail(BWG_EINVAL, "null ensemble %d", k);
         if (e->engine != BWG_ENGINE_BITWISE && e->engine != BWG_ENGINE_LANES)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: batches run the bit-plane engines", k);
+        if (e->zs)
+            return fail(BWG_EUNSUPPORTED, "ensemble %d: shared-threshold ensembles move by step", k);
         if (e->lat)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: lattices run their own launches", k);
         if (pick_bucket(e) < 0)

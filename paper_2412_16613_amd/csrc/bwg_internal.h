@@ -13,6 +13,7 @@ enum : uint32_t {
     DOM_INIT = 3,
     DOM_PLAIN = 4,
     DOM_COMPONENT = 5,
+    DOM_SHARED = 6,
 };
 
 // Frank-family structure recognised for the bit-sliced kernel: the reaction
@@ -48,7 +49,9 @@ struct WmArgs {
     uint32_t cu;
     int32_t fa, fi;
     int32_t nb_mem;         // count planes per species in memory (<= NB)
-    int32_t pad;
+    uint32_t zs;            // shared threshold on [0, zs) for every replica (0: per replica)
+    const uint32_t *ztab;   // shared thresholds of events [zbase, zbase + zlen)
+    uint64_t zbase, zlen;
 };
 
 struct PlainArgs {
@@ -79,6 +82,9 @@ extern const int kWmVariantCount;
 
 hipError_t launch_plain(const PlainArgs &a, hipStream_t s, int block);
 hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s);
+// Shared thresholds of events [e0, e0 + len) into tab (len uint32).
+hipError_t launch_shared_fill(uint32_t *tab, uint64_t e0, uint64_t len, uint64_t seed,
+                              uint32_t net_id, uint32_t Z, hipStream_t s);
 
 // ---- batches ----
 struct BatchEns {

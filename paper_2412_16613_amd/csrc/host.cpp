@@ -55,10 +55,11 @@ static int64_t comb_h(const int32_t *r, const int64_t *N, int S)
     return v;
 }
 
-// Largest total weight over every state with n_tot molecules (3 species).
-static int64_t max_total_weight(const bwg_net &n)
+// Smallest and largest total weight over every state with n_tot molecules
+// (3 species).
+static void total_weight_range(const bwg_net &n, int64_t *lo, int64_t *hi)
 {
-    int64_t best = 0;
+    int64_t best = 0, least = INT64_MAX;
     const int64_t N = n.n_tot;
     int64_t st[3];
     for (int64_t a = 0; a <= N; ++a)
@@ -70,8 +71,10 @@ static int64_t max_total_weight(const bwg_net &n)
             for (int j = 0; j < n.R; ++j)
                 if (n.q.c[j]) t += n.q.c[j] * comb_h(&n.reac[j * n.S], st, n.S);
             if (t > best) best = t;
+            if (t < least) least = t;
         }
-    return best;
+    *lo = least;
+    *hi = best;
 }
 
 static int ilog2_exact(int64_t c)  // log2 of a power of two, else -2
@@ -266,7 +269,8 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
             q.c[j] = (int64_t)c;
         }
     }
-    q.max_total = max_total_weight(*n);
+    int64_t min_total;
+    total_weight_range(*n, &min_total, &q.max_total);
     int B = 1;
     while (B < 63 && (1ll << B) < q.max_total) ++B;
     if (B > 32) {
@@ -279,6 +283,10 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     while ((1ll << b) <= n->n_tot) ++b;
     q.b = b;
     q.lambda = std::ldexp(1.0, B) / q.s;
+    // shared-threshold range: the total weight when no state changes it (the
+    // ghost reactions of Eq. (9) make it N(N-1)/2), else 2^B; 0 past 32 bits
+    const int64_t z = (min_total == q.max_total && q.max_total > 0) ? q.max_total : (1ll << B);
+    q.z_shared = z < (1ll << 32) ? z : 0;
     classify(*n);
     classify_plain(*n);
     q.gpu_ok = n->shape_ok ? 1 : 0;
@@ -425,6 +433,16 @@ extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_
     if (M == 0 || M >= (1ull << 32)) return fail(BWG_EINVAL, "replica count out of range");
     const int engine = o ? o->engine : BWG_ENGINE_BITWISE;
     const uint64_t cap = (o && o->table_capacity) ? o->table_capacity : 65536;
+    if (o && (o->block < 0 || o->block > 256 || o->block % 64))
+        return fail(BWG_EINVAL, "block %d: the event kernels take 64, 128, 192 or 256 threads",
+                    o->block);
+    if (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) {
+        if (n->lat || engine == BWG_ENGINE_PLAIN)
+            return fail(BWG_EUNSUPPORTED,
+                        "shared thresholds run on the well-mixed bit-plane engines");
+        if (!n->q.z_shared)
+            return fail(BWG_ERANGE, "shared-threshold range beyond 32 bits");
+    }
     if (n->lat) {
         if (engine != BWG_ENGINE_BITWISE)
             return fail(BWG_EUNSUPPORTED, "lattices run on the bit-sliced engine only");
@@ -460,6 +478,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->table_cap = (o && o->table_capacity) ? o->table_capacity : 65536;
     e->epl = o ? o->events_per_launch : 0;
     e->timed = o && (o->flags & BWG_OPT_TIME_KERNELS);
+    e->zs = (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) ? (uint32_t)n->q.z_shared : 0;
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
     if (n->lat) {
@@ -595,6 +614,7 @@ extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts
     e->adv = 0;
     e->lag = 0;
     e->pending = 0;
+    e->zE = 0;
     e->inited = true;
     return BWG_OK;
 }
@@ -635,6 +655,11 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         a.fa = n->shape.fa;
         a.fi = n->shape.fi;
         a.nb_mem = e->nb;
+        a.zs = e->zs;
+        a.ztab = (const uint32_t *)e->table;
+        a.zbase = e->zbase;
+        a.zlen = e->zs ? e->zlen : 0;
+        if (a.zs && !a.zlen) return fail(BWG_EINVAL, "shared thresholds not staged");
         hipEvent_t ev = nullptr;
         int rc = mark_begin(e, s, &ev);
         if (rc) return rc;
@@ -668,10 +693,34 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
     return BWG_OK;
 }
 
+// Shared-threshold ensembles move in lockstep (every replica at event zE):
+// run up to max_events (0: all) of the pending events in launches of at most
+// the table's capacity, each preceded by the fill of its thresholds.
+static int run_shared(bwg_ens *e, uint64_t max_events, hipStream_t s)
+{
+    uint64_t todo = e->pending;
+    if (max_events && max_events < todo) todo = max_events;
+    uint64_t cap = e->table_cap * 2;  // uint32 thresholds in the table region
+    if (e->epl && e->epl < cap) cap = e->epl;
+    while (todo) {
+        const uint64_t len = todo < cap ? todo : cap;
+        HIP_TRY(launch_shared_fill((uint32_t *)e->table, e->zE, len, e->seed, e->net_id, e->zs,
+                                   s));
+        e->zbase = e->zE;
+        e->zlen = len;
+        const int rc = launch_events(e, len, s);
+        if (rc) return rc;
+        e->zE += len;
+        todo -= len;
+    }
+    return BWG_OK;
+}
+
 // Enqueue the event launches of a scheduled advance or step: enough launches
 // of events_per_launch (if set) to cover the pending bound.
 static int run_events(bwg_ens *e, hipStream_t s)
 {
+    if (e->zs) return run_shared(e, 0, s);
     if (!e->epl) return launch_events(e, 0, s);
     while (e->pending) {
         int rc = launch_events(e, e->epl, s);
@@ -684,6 +733,7 @@ int bwg::schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *km
                            uint64_t *kmax_out)
 {
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
+    if (e->zs) return fail(BWG_EUNSUPPORTED, "shared-threshold ensembles move by bwg_ensemble_step");
     if (!(t_end >= e->t_now)) return fail(BWG_EINVAL, "t_end %g before t_now %g", t_end, e->t_now);
     if (e->adv >= (1ull << 48)) return fail(BWG_ERANGE, "advance index overflow");
     const double mu = e->net->q.lambda * (t_end - e->t_now);
@@ -728,6 +778,7 @@ extern "C" int bwg_ensemble_run(bwg_ens *e, uint64_t max_events, void *stream)
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     if (e->lat) return lat_run(e, max_events, (hipStream_t)stream);
+    if (e->zs) return run_shared(e, max_events, (hipStream_t)stream);
     return launch_events(e, max_events, (hipStream_t)stream);
 }
 

@@ -80,6 +80,9 @@ struct bwg_ens {
     uint64_t pending = 0;  // bound on the events any word still has to run
     bool inited = false;
     uint64_t lanes_words = 0;  // in batches: trailing words run as lanes items
+    uint32_t zs = 0;           // shared-threshold range (0: a threshold per replica)
+    uint64_t zE = 0;           // with zs: the event every replica has reached
+    uint64_t zbase = 0, zlen = 0;  // with zs: events whose thresholds the table holds
     // lattice ensembles
     bool lat = false;
     const bwg::LatVariant *lvar = nullptr;

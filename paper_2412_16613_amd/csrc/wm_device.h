@@ -8,6 +8,33 @@
 
 namespace bwg {
 
+// The threshold every replica compares at event e in the shared-threshold
+// variant (the paper's single n per iteration, Sec. 4): uniform on [0, Z)
+// from output 0 of SHARED draws by 32-bit multiply-shift, rejecting the low
+// halves below 2^32 mod Z (thresh); the 256th attempt is kept as it is.
+__device__ __forceinline__ uint32_t shared_threshold(uint64_t seed, uint32_t net_id, uint64_t e,
+                                                     uint32_t Z, uint32_t thresh)
+{
+    uint64_t m = 0;
+    for (uint32_t attempt = 0; attempt < 256; ++attempt) {
+        uint32_t o0, o1, o2, o3;
+        philox4x32_10((uint32_t)e, (DOM_SHARED << 24) | (attempt << 16) | ((uint32_t)(e >> 32) & 0xFFFFu),
+                      0u, net_id, (uint32_t)seed, (uint32_t)(seed >> 32), o0, o1, o2, o3);
+        m = (uint64_t)o0 * Z;
+        if ((uint32_t)m >= thresh) break;
+    }
+    return (uint32_t)(m >> 32);
+}
+
+// Shared threshold of event e from the table the host fills before each
+// launch: shared-threshold replicas move in lockstep, so every word's window
+// is the table's [zbase, zbase + zlen).  The index is clamped to the table.
+__device__ __forceinline__ uint32_t shared_at(const WmArgs &a, uint64_t e)
+{
+    const uint64_t k = e - a.zbase;
+    return a.ztab[k < a.zlen ? k : a.zlen - 1];
+}
+
 // ---- subtraction of a shifted operand ------------------------------------
 // d -= p << SH over planes [SH, BC); returns the final borrow.  Planes below
 // SH are untouched (the operand is zero there).
@@ -62,8 +89,9 @@ __device__ __forceinline__ uint32_t lane_mask(const uint64_t *E, const uint64_t 
 
 // One word (32 replicas) of an ensemble: run its pending events.
 // NB count planes, BC = 4 * (quads of threshold planes), FA product shift
-// (-1: run time), CU unimolecular weight (-1: run time).
-template <int NB, int BC, int FA, int CU>
+// (-1: run time), CU unimolecular weight (-1: run time); SH: one shared
+// threshold per event (a.zs != 0) instead of per-replica draws.
+template <int NB, int BC, int FA, int CU, bool SH = false>
 __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
 {
     static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
@@ -138,6 +166,7 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
         uint32_t lastm[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
+        uint32_t nv_next = SH ? shared_at(a, lo) : 0u;
         uint64_t nreal = 0;
 
         for (uint64_t e = lo; e < hi; ++e) {
@@ -147,6 +176,15 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
             // call with plane-quad q / 4; planes at or above B are zero
             uint32_t n[BC];
             const uint32_t e_lo = (uint32_t)e, e_hi = (uint32_t)(e >> 32) & 0xFFFFu;
+            if constexpr (SH) {
+                // one n for every replica: plane q is all ones where bit q is
+                // set; the next event's n is loaded while this one runs
+                const uint32_t nv = nv_next;
+                if (e + 1 < hi) nv_next = shared_at(a, e + 1);
+#pragma unroll
+                for (int q = 0; q < BC; ++q)
+                    n[q] = q < 32 ? (uint32_t)((int32_t)(nv << (31 - q)) >> 31) : 0u;
+            } else
 #pragma unroll
             for (int q4 = 0; q4 < BC / 4; ++q4) {
                 uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
@@ -349,8 +387,27 @@ __device__ __forceinline__ void wm_lanes(const WmArgs &a, const uint64_t w, uint
     const uint64_t cu = a.cu;
     const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t zs = a.zs;
     uint32_t nreal = 0;
     for (uint64_t e = lo; e < hi; ++e) {
+        if (zs) {
+            // shared threshold: the same n for every thread
+            const uint64_t n = shared_at(a, e);
+            const bool act = mine && E0 <= e && e < T0;
+            if (act) {
+                const uint64_t U = cu * (uint64_t)cA;
+                const uint64_t S2 = 2 * U;
+                const uint64_t S3 = S2 + (has_a ? ((uint64_t)cA * (uint64_t)cL) << a.fa : 0);
+                const uint64_t S4 = S3 + (has_a ? ((uint64_t)cA * (uint64_t)cD) << a.fa : 0);
+                const uint64_t S5 = S4 + (has_i ? ((uint64_t)cL * (uint64_t)cD) << a.fi : 0);
+                const int r = n < U ? 0 : n < S2 ? 1 : n < S3 ? 2 : n < S4 ? 3 : n < S5 ? 4 : -1;
+                cL += (r == 0 || r == 2) - (r == 4);
+                cD += (r == 1 || r == 3) - (r == 4);
+                cA += (r == 4) * 2 - (r >= 0 && r < 4);
+                nreal += r >= 0;
+            }
+            continue;
+        }
         if (l < nq) {
             uint32_t o0, o1, o2, o3;
             philox4x32_10((uint32_t)e,

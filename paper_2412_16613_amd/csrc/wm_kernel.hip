@@ -30,19 +30,27 @@
 
 namespace bwg {
 
-template <int NB, int BC, int FA, int CU>
+template <int NB, int BC, int FA, int CU, bool SH>
 __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
 {
-    wm_word<NB, BC, FA, CU>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    wm_word<NB, BC, FA, CU, SH>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int NB, int BC, int FA, int CU>
 hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
 {
-    if (block <= 0) block = 128;
+    // 128-thread blocks leave two SIMDs of a CU to other blocks, which pays
+    // while there are fewer words than one wave per SIMD; from 1024 waves on,
+    // 256-thread blocks (one wave per SIMD of a CU) keep the waves spread
+    // evenly when the occupancy would let some CUs take more than their share
+    if (block <= 0) block = a.n_words >= 65536 ? 256 : 128;
     const uint64_t grid = (a.n_words + block - 1) / block;
-    hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU>), dim3((uint32_t)grid), dim3(block), 0,
-                       s, a);
+    if (a.zs)
+        hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU, true>), dim3((uint32_t)grid),
+                           dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU, false>), dim3((uint32_t)grid),
+                           dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
@@ -52,7 +60,15 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
     /* compile-time shift and weight of the named workloads */               \
     X(6, 20, 9, 164)   /* N_tot = 32, k0 = 0.01, k1 = k2 = 1/32 */           \
     X(11, 24, 4, 164)  /* N_tot = 1024 */                                     \
-    X(6, 12, 0, 0)     /* paper network, N_tot <= 63 */                       \
+    /* the paper's network (unit weights, no conversions) by N_tot */        \
+    X(4, 8, 0, 0)      /* N_tot <= 15 */                                      \
+    X(5, 8, 0, 0)      /* N_tot <= 23 */                                      \
+    X(6, 12, 0, 0)     /* N_tot <= 63 */                                      \
+    X(7, 12, 0, 0)     /* N_tot <= 91 */                                      \
+    X(8, 16, 0, 0)     /* N_tot <= 255 */                                     \
+    X(9, 16, 0, 0)     /* N_tot <= 362 */                                     \
+    X(10, 20, 0, 0)    /* N_tot <= 1023 */                                    \
+    X(11, 20, 0, 0)    /* N_tot <= 1448 */                                    \
     /* run-time shifts and weights, any Frank-family network in budget */     \
     X(4, 20, -1, -1)                                                          \
     X(6, 20, -1, -1)                                                          \
@@ -69,6 +85,23 @@ __global__ __launch_bounds__(256) void wm_lanes_kernel(WmArgs a)
     wm_lanes(a, 8 * (uint64_t)blockIdx.x + half, sq[half]);
 }
 
+// Shared thresholds of events e0 .. e0 + len - 1, one thread per event.
+__global__ __launch_bounds__(256) void shared_fill_kernel(uint32_t *tab, uint64_t e0, uint64_t len,
+                                                          uint64_t seed, uint32_t net_id, uint32_t Z)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < len) tab[k] = shared_threshold(seed, net_id, e0 + k, Z, (0u - Z) % Z);
+}
+
+hipError_t launch_shared_fill(uint32_t *tab, uint64_t e0, uint64_t len, uint64_t seed,
+                              uint32_t net_id, uint32_t Z, hipStream_t s)
+{
+    if (len == 0) return hipSuccess;
+    hipLaunchKernelGGL(shared_fill_kernel, dim3((uint32_t)((len + 255) / 256)), dim3(256), 0, s,
+                       tab, e0, len, seed, net_id, Z);
+    return hipGetLastError();
+}
+
 hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
 {
     const uint64_t grid = (a.n_words + 7) / 8;
@@ -76,8 +109,9 @@ hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-#define BWG_WM_INST(nb, bc, fa, cu) \
-    template __global__ void wm_event_kernel<nb, bc, fa, cu>(WmArgs);
+#define BWG_WM_INST(nb, bc, fa, cu)                                     \
+    template __global__ void wm_event_kernel<nb, bc, fa, cu, false>(WmArgs); \
+    template __global__ void wm_event_kernel<nb, bc, fa, cu, true>(WmArgs);
 BWG_WM_VARIANTS(BWG_WM_INST)
 
 #ifndef __HIP_DEVICE_COMPILE__

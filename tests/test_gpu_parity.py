@@ -28,9 +28,11 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def gpu_run(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0):
+def gpu_run(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0,
+            shared=False):
     n = bwg.Network(net)
-    ens = bwg.Ensemble(n, M, seed=seed, net_id=net_id, engine=engine, events_per_launch=epl)
+    ens = bwg.Ensemble(n, M, seed=seed, net_id=net_id, engine=engine, events_per_launch=epl,
+                       shared_threshold=shared)
     ens.init(init)
     for op, v in schedule:
         if op == "advance":
@@ -64,10 +66,13 @@ def group_sums(x, M):
     return out
 
 
-def check_parity(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0):
-    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl)
-    counts, ev, real, ens = gpu_run(torch, net, M, init, schedule, seed, net_id, engine, epl)
-    draw = ssa.DRAW_PLAIN if engine == "plain" else ssa.DRAW_EVENT
+def check_parity(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0,
+                 shared=False):
+    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl, shared)
+    counts, ev, real, ens = gpu_run(torch, net, M, init, schedule, seed, net_id, engine, epl,
+                                    shared)
+    draw = (ssa.DRAW_PLAIN if engine == "plain" else
+            ssa.DRAW_SHARED if shared else ssa.DRAW_EVENT)
     o = oracle_run(net, M, init, schedule, seed, net_id, draw)
     np.testing.assert_array_equal(counts, o.counts)
     np.testing.assert_array_equal(ev, o.E)
@@ -267,3 +272,77 @@ def test_switching_engines_mid_run_changes_nothing(torch):
         np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
     with pytest.raises(bwg.BwgError):
         bwg.Ensemble(bwg.Network(net), 10, engine="plain").set_engine("lanes")
+
+
+# ---- shared threshold: one n on [0, Z) for every replica (Sec. 4) ----------
+
+@pytest.mark.parametrize("net,M,init,sched,engine,epl", [
+    (paper_network(32), 1000, ("multinomial",), [("step", 3000)], "bitwise", 0),
+    (paper_network(100), 333, ("fixed", (30, 30, 40)), [("step", 5000)], "lanes", 0),
+    (paper_network(32), 200, ("multinomial",), [("step", 1500), ("step", 7)], "lanes", 700),
+    (paper_network(1024), 97, ("multinomial",), [("step", 2000)], "bitwise", 500),
+    (frank_network(64), 700, ("fixed", (0, 0, 64)), [("step", 2000), ("step", 77)], "bitwise", 0),
+    (frank_network(12), 65, ("fixed", (0, 0, 12)), [("step", 900)], "lanes", 0),
+])
+def test_shared_threshold_matches_oracle(torch, net, M, init, sched, engine, epl):
+    """Z = N(N-1)/2 for the paper's network with ghosts, Z = W without them."""
+    check_parity(torch, net, M, init, sched, seed=6, net_id=9, engine=engine, epl=epl,
+                 shared=True)
+
+
+def test_shared_threshold_launches_and_capped_runs(torch):
+    """Steps longer than the threshold table (2 x table_capacity events) run
+    in several fill + event launches; events_per_launch caps them further."""
+    net = paper_network(48)
+    for kw in (dict(table_capacity=1000), dict(table_capacity=4096, events_per_launch=777)):
+        n = bwg.Network(net)
+        e = bwg.Ensemble(n, 300, seed=8, net_id=2, shared_threshold=True, **kw)
+        e.init(("multinomial",))
+        e.step(5001)
+        e.step(3)
+        o = oracle_run(net, 300, ("multinomial",), [("step", 5001), ("step", 3)], seed=8,
+                       net_id=2, draw=ssa.DRAW_SHARED)
+        np.testing.assert_array_equal(e.read_counts().cpu().numpy(), o.counts)
+        np.testing.assert_array_equal(e.read_events()[0].cpu().numpy(), o.E)
+
+
+def test_shared_threshold_copies_from_one_state_stay_equal(torch):
+    net = paper_network(64)
+    counts, _, _, _ = gpu_run(torch, net, 3000, ("fixed", (20, 20, 24)), [("step", 4000)],
+                              seed=1, shared=True)
+    assert (counts == counts[0]).all()
+
+
+def test_shared_threshold_full_size_sampled(torch):
+    """The gain workload's launch: the paper's network at N = 1024 with its
+    ghosts, 2^22 replicas from a multinomial start, 10^5 steps (one table
+    fill and one event launch); 3 blocks of 16 replicas against the oracle."""
+    net = paper_network(1024)
+    M, T = 1 << 22, 100000
+    counts, ev, _, _ = gpu_run(torch, net, M, ("multinomial",), [("step", T)], seed=3,
+                               net_id=1, shared=True)
+    assert (ev == T).all()
+    assert (counts.sum(1) == 1024).all()
+    for first in (0, M // 2 + 5, M - 16):
+        o = ssa.OracleEnsemble(net, M, seed=3, net_id=1, draw=ssa.DRAW_SHARED, first=first,
+                               count=16)
+        o.init(("multinomial",))
+        o.step(T)
+        np.testing.assert_array_equal(counts[first:first + 16], o.counts)
+
+
+def test_shared_threshold_rejections(torch):
+    net = bwg.Network(paper_network(32))
+    e = bwg.Ensemble(net, 100, shared_threshold=True)
+    e.init(("multinomial",))
+    for call in (lambda: e.advance(1.0), lambda: e.schedule(1.0),
+                 lambda: bwg.Batch([e])):
+        with pytest.raises(bwg.BwgError):
+            call()
+    with pytest.raises(bwg.BwgError):
+        bwg.Ensemble(net, 100, engine="plain", shared_threshold=True)
+    lat = bwg.Network(frank_network(12, lx=4, ly=4, hop=0.1, site_planes=4))
+    with pytest.raises(bwg.BwgError):
+        bwg.Ensemble(lat, 100, shared_threshold=True)
+    e.step(10)                       # still usable after the refusals
+    assert (e.read_events()[0].cpu().numpy() == 10).all()

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def _qcmp(net):
     q_lib = bwg.Network(net).quantized()
     q_orc = quantize(net)
-    for k in ("c", "f", "B", "b", "s", "Lambda", "max_total"):
+    for k in ("c", "f", "B", "b", "s", "Lambda", "max_total", "z_shared"):
         assert q_lib[k] == q_orc[k], (k, q_lib[k], q_orc[k])
     return q_lib
 
@@ -140,6 +140,32 @@ def test_state_bytes_scale_with_replicas():
     assert sizes[3] >= (3 * 11 * 4 + 16 * 32) * (1 << 15)
     b = ctypes.c_uint64()
     assert _abi.load().bwg_ensemble_state_bytes(n.handle, 0, None, ctypes.byref(b)) == _abi.BWG_EINVAL
+
+
+def test_options_are_checked_before_any_device_work():
+    """Block sizes beyond the kernels' launch bounds and shared thresholds
+    where no kernel implements them are refused by the size query."""
+    import ctypes
+    L = _abi.load()
+
+    def rc(net, **kw):
+        o = _abi.Opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        b = ctypes.c_uint64()
+        return L.bwg_ensemble_state_bytes(net.handle, 1000, ctypes.byref(o), ctypes.byref(b))
+
+    n = bwg.Network(paper_network(32))
+    for block in (0, 64, 128, 192, 256):
+        assert rc(n, block=block) == _abi.BWG_OK
+    for block in (-64, 32, 100, 320, 512, 1024):
+        assert rc(n, block=block) == _abi.BWG_EINVAL
+    shared = _abi.BWG_OPT_SHARED_THRESHOLD
+    assert rc(n, flags=shared) == _abi.BWG_OK
+    assert rc(n, flags=shared, engine=_abi.BWG_ENGINE_LANES) == _abi.BWG_OK
+    assert rc(n, flags=shared, engine=_abi.BWG_ENGINE_PLAIN) == _abi.BWG_EUNSUPPORTED
+    lat = bwg.Network(frank_network(12, lx=4, ly=4, hop=0.1, site_planes=4))
+    assert rc(lat, flags=shared) == _abi.BWG_EUNSUPPORTED
 
 
 # ---- lattices ----------------------------------------------------------------
