@@ -42,8 +42,8 @@ VALU_PEAK = 256 * 128 * 2.4e9   # 32-bit lane-slots/s: 256 CUs x 128 lanes/clk x
 # kernel -> (sha1 prefix of its sources, sources, bytes per launch, summary file).
 CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
 MEASURED_TRAFFIC = {
-    "wm_event_kernel": ("1ee90bed23d7", ("bitops.h", "wm_device.h", "wm_kernel.hip"),
-                        (2 * 10667 + 12672) * 1024, "profiles/wm_event_kernel_frank1024_2p20.md"),
+    "wm_pc_kernel": ("837ac034d700", ("bitops.h", "wm_device.h", "wm_kernel.hip"),
+                     int((2 * 10671.5 + 12672) * 1024), "profiles/wm_pc_kernel_frank1024_2p20.md"),
     "lat_event_kernel": ("730e9d3e6dcc", ("bitops.h", "lattice.hip"),
                          (2 * 3993080 + 8341990) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
@@ -200,8 +200,8 @@ def main():
         "replica_time_per_s": M * t_end * args.steps / (r["ms"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
-                     "traffic": measured_traffic("wm_event_kernel"), "traffic_unit": "B/launch",
-                     "kernel": "wm_event_kernel", "kernel_ms": launch_ms,
+                     "traffic": measured_traffic("wm_pc_kernel"), "traffic_unit": "B/launch",
+                     "kernel": "wm_pc_kernel", "kernel_ms": launch_ms,
                      "launches_per_step": launches_per_step, "advance_ms": adv_avg_ms,
                      "slots_per_word_event": slots},
     }

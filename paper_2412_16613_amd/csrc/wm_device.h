@@ -87,6 +87,265 @@ __device__ __forceinline__ uint32_t lane_mask(const uint64_t *E, const uint64_t 
     return m;
 }
 
+// ---- pieces of one word's event loop ---------------------------------------
+
+// Event window of a word over its pending lanes (E_l < Etgt_l): every
+// pending event lies in [lo, hi) and every pending lane is active at the
+// events of [blo, bhi); a lane that has finished its budget never limits it.
+struct WordWindow {
+    uint64_t lo, hi, blo, bhi;
+    uint32_t pend;
+};
+
+__device__ __forceinline__ WordWindow word_window(const WmArgs &a, const uint64_t *E,
+                                                  const uint64_t *T, uint32_t live)
+{
+    WordWindow v{~0ull, 0, 0, ~0ull, 0u};
+    for (int l = 0; l < 32; ++l) {
+        if (!((live >> l) & 1u)) continue;
+        const uint64_t x = E[l], y = T[l];
+        if (x >= y) continue;
+        v.pend |= 1u << l;
+        v.lo = x < v.lo ? x : v.lo;
+        v.blo = x > v.blo ? x : v.blo;
+        v.hi = y > v.hi ? y : v.hi;
+        v.bhi = y < v.bhi ? y : v.bhi;
+    }
+    if (!v.pend) v.lo = v.hi = 0;
+    if (a.max_events && v.hi > v.lo + a.max_events) v.hi = v.lo + a.max_events;
+    return v;
+}
+
+// Occupancies of word w (species order L, D, A); planes at or above the
+// stored count are zero.
+template <int NB>
+__device__ __forceinline__ void load_word(const WmArgs &a, uint64_t w, uint32_t (&L)[NB],
+                                          uint32_t (&D)[NB], uint32_t (&A)[NB])
+{
+    const uint32_t *pl = a.planes;
+    const int nbm = a.nb_mem;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const bool in = q < nbm;
+        L[q] = in ? pl[((uint64_t)0 * nbm + q) * a.wp + w] : 0u;
+        D[q] = in ? pl[((uint64_t)1 * nbm + q) * a.wp + w] : 0u;
+        A[q] = in ? pl[((uint64_t)2 * nbm + q) * a.wp + w] : 0u;
+    }
+}
+
+// Pair counts and the unimolecular weight U = cu N_A, recomputed once per
+// launch from the occupancies.
+template <int NB, int BC, int WP>
+__device__ __forceinline__ void init_weights(const uint32_t (&L)[NB], const uint32_t (&D)[NB],
+                                             const uint32_t (&A)[NB], uint32_t cu,
+                                             uint32_t (&PAL)[WP], uint32_t (&PAD)[WP],
+                                             uint32_t (&PLD)[WP], uint32_t (&U)[BC])
+{
+    mul_planes<NB, WP>(PAL, A, L);
+    mul_planes<NB, WP>(PAD, A, D);
+    mul_planes<NB, WP>(PLD, L, D);
+#pragma unroll
+    for (int q = 0; q < BC; ++q) U[q] = 0;
+#pragma unroll
+    for (int k = 0; k < BC; ++k) {
+        if ((cu >> k) & 1u) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = k; q < BC; ++q) {
+                const uint32_t v = (q - k < NB) ? A[q - k] : 0u;
+                const uint32_t s = BWG_OP3(U[q], v, c, L_XOR3);
+                c = BWG_OP3(U[q], v, c, L_MAJ);
+                U[q] = s;
+            }
+        }
+    }
+}
+
+// Threshold planes of event e for word G from Philox: plane q is output
+// q mod 4 of the call with plane-quad q / 4; planes at or above B are zero
+// (lastm masks the last of the nq quads in use).
+template <int BC>
+__device__ __forceinline__ void philox_planes(uint32_t (&n)[BC], uint64_t e, uint32_t G,
+                                              uint32_t net_id, uint32_t k0, uint32_t k1, int nq,
+                                              const uint32_t (&lastm)[4])
+{
+    const uint32_t e_lo = (uint32_t)e, e_hi = (uint32_t)(e >> 32) & 0xFFFFu;
+#pragma unroll
+    for (int q4 = 0; q4 < BC / 4; ++q4) {
+        uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+        if (q4 < nq)
+            philox4x32_10(e_lo, (DOM_EVENT << 24) | ((uint32_t)q4 << 16) | e_hi, G, net_id, k0, k1,
+                          o0, o1, o2, o3);
+        if (q4 == nq - 1) {
+            o0 &= lastm[0];
+            o1 &= lastm[1];
+            o2 &= lastm[2];
+            o3 &= lastm[3];
+        }
+        n[4 * q4 + 0] = o0;
+        n[4 * q4 + 1] = o1;
+        n[4 * q4 + 2] = o2;
+        n[4 * q4 + 3] = o3;
+    }
+}
+
+// One event of a word given its threshold planes n (consumed): selection
+// (b)-(d), occupancy update (e) and product update (f) for the lanes in act.
+template <int NB, int BC, int FA, int CU, int WP, int WD>
+__device__ __forceinline__ void word_event(const WmArgs &a, uint32_t (&n)[BC], uint32_t act,
+                                           uint32_t cu, bool has_a, bool has_i,
+                                           uint32_t (&L)[NB], uint32_t (&D)[NB],
+                                           uint32_t (&A)[NB], uint32_t (&PAL)[WP],
+                                           uint32_t (&PAD)[WP], uint32_t (&PLD)[WP],
+                                           uint32_t (&U)[BC], uint64_t &nreal)
+{
+    // (b)-(d) cumulative weights and first crossing
+    uint32_t br = 0;
+#pragma unroll
+    for (int q = 0; q < BC; ++q) br = BWG_OP3(n[q], U[q], br, L_BORROW);
+    const uint32_t lt1 = br;  // n < U
+    br = 0;                   // n -= 2U (in place)
+#pragma unroll
+    for (int q = 1; q < BC; ++q) {
+        const uint32_t v = U[q - 1];
+        const uint32_t nb = BWG_OP3(n[q], v, br, L_BORROW);
+        n[q] = BWG_OP3(n[q], v, br, L_XOR3);
+        br = nb;
+    }
+    const uint32_t lt2 = br;  // n < 2U
+    uint32_t lt3 = lt2, lt4 = lt2, lt5;
+    if (has_a) {
+        lt3 = lt2 | sub_w<FA, BC, WP, true>(a.fa, n, PAL);
+        lt4 = lt3 | sub_w<FA, BC, WP, true>(a.fa, n, PAD);
+    }
+    lt5 = lt4;
+    if (has_i) lt5 = lt4 | sub_w<FA, BC, WP, false>(a.fi, n, PLD);
+
+    const uint32_t mL = (lt1 | (lt3 & ~lt2)) & act;
+    const uint32_t mD = ((lt2 & ~lt1) | (lt4 & ~lt3)) & act;
+    const uint32_t mI = (lt5 & ~lt4) & act;
+    const uint32_t mLD = mL | mD;
+    nreal += (uint32_t)__builtin_popcount(mLD | mI);
+
+    // (e) occupancies: keep the pre-event values for the products
+    uint32_t L2[NB], D2[NB], A2[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        L2[q] = L[q];
+        D2[q] = D[q];
+        A2[q] = A[q];
+    }
+    add_pm1<NB>(L2, mL, mI);
+    add_pm1<NB>(D2, mD, mI);
+    add_m1_p2<NB>(A2, mLD, mI);
+
+    // (f) products: P_AX += dA * X' + dX * A;  P_LD += dL * D' + dD * L
+    {
+        uint32_t t[WD];
+        const uint32_t mLI = mL | mI, mDI = mD | mI;
+        // P_AL
+        {
+            uint32_t c = mLD;
+#pragma unroll
+            for (int q = 0; q < WD; ++q) {
+                const uint32_t xq = q < NB ? L2[q] : 0u;
+                const uint32_t xm = (q >= 1 && q - 1 < NB) ? L2[q - 1] : 0u;
+                const uint32_t t1 = BWG_OP3(mI, xm, BWG_OP3(mLD, xq, 0u, L_ANDNOT), L_ANDOR);
+                const uint32_t t2 = q < NB ? BWG_OP3(A[q], mLI, mI, L_ANDXOR) : mI;
+                t[q] = BWG_OP3(t1, t2, c, L_XOR3);
+                c = BWG_OP3(t1, t2, c, L_MAJ);
+            }
+            add_sext<WP, WD>(PAL, t, mI);
+        }
+        // P_AD
+        {
+            uint32_t c = mLD;
+#pragma unroll
+            for (int q = 0; q < WD; ++q) {
+                const uint32_t xq = q < NB ? D2[q] : 0u;
+                const uint32_t xm = (q >= 1 && q - 1 < NB) ? D2[q - 1] : 0u;
+                const uint32_t t1 = BWG_OP3(mI, xm, BWG_OP3(mLD, xq, 0u, L_ANDNOT), L_ANDOR);
+                const uint32_t t2 = q < NB ? BWG_OP3(A[q], mDI, mI, L_ANDXOR) : mI;
+                t[q] = BWG_OP3(t1, t2, c, L_XOR3);
+                c = BWG_OP3(t1, t2, c, L_MAJ);
+            }
+            add_sext<WP, WD>(PAD, t, mI);
+        }
+        // P_LD
+        {
+            uint32_t c = mI;
+#pragma unroll
+            for (int q = 0; q < WD; ++q) {
+                const uint32_t t1 = q < NB ? BWG_OP3(D2[q], mLI, mI, L_ANDXOR) : mI;
+                const uint32_t t2 = q < NB ? BWG_OP3(L[q], mDI, mI, L_ANDXOR) : mI;
+                t[q] = BWG_OP3(t1, t2, c, L_XOR3);
+                c = BWG_OP3(t1, t2, c, L_MAJ);
+            }
+            add_sext<WP, WD>(PLD, t, mI);
+        }
+    }
+    // U += cu * dA with dA = -1 on mLD, +2 on mI: addend planes are the
+    // bits of -cu (two's complement, the +1 as carry-in) on mLD and of
+    // 2 cu on mI
+    if (cu) {
+        uint32_t c = mLD;
+#pragma unroll
+        for (int q = 0; q < BC; ++q) {
+            uint32_t v;
+            if constexpr (CU >= 0) {
+                constexpr uint32_t ncu = ~(uint32_t)CU, dcu = 2u * (uint32_t)CU;
+                const bool bn = (ncu >> q) & 1u, bd = (dcu >> q) & 1u;
+                v = bn ? (bd ? (mLD | mI) : mLD) : (bd ? mI : 0u);
+            } else {
+                const uint32_t neg = ((cu >> q) & 1u) ? 0u : mLD;
+                const uint32_t dbl = (q >= 1 && ((cu >> (q - 1)) & 1u)) ? mI : 0u;
+                v = neg | dbl;
+            }
+            const uint32_t s = BWG_OP3(U[q], v, c, L_XOR3);
+            if (q + 1 < BC) c = BWG_OP3(U[q], v, c, L_MAJ);
+            U[q] = s;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        L[q] = L2[q];
+        D[q] = D2[q];
+        A[q] = A2[q];
+    }
+}
+
+// Occupancies and per-replica event counts back to memory after a launch
+// that ran the word's events up to hi.
+template <int NB>
+__device__ __forceinline__ void store_word(const WmArgs &a, uint64_t w, uint32_t live,
+                                           uint64_t hi, const uint32_t (&L)[NB],
+                                           const uint32_t (&D)[NB], const uint32_t (&A)[NB])
+{
+    uint32_t *po = a.planes;
+    const int nbm = a.nb_mem;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if (q < nbm) {
+            po[((uint64_t)0 * nbm + q) * a.wp + w] = L[q];
+            po[((uint64_t)1 * nbm + q) * a.wp + w] = D[q];
+            po[((uint64_t)2 * nbm + q) * a.wp + w] = A[q];
+        }
+    }
+    uint64_t *Ew = a.E + 32 * w;
+    const uint64_t *T = a.Etgt + 32 * w;
+    for (int l = 0; l < 32; ++l) {
+        if (!((live >> l) & 1u)) continue;
+        const uint64_t x = Ew[l], y = T[l];
+        Ew[l] = hi < x ? x : (hi > y ? y : hi);
+    }
+}
+
+__device__ __forceinline__ uint32_t live_lanes(const WmArgs &a, uint64_t w)
+{
+    const uint64_t rem = a.M - 32 * w;
+    return rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+}
+
 // One word (32 replicas) of an ensemble: run its pending events.
 // NB count planes, BC = 4 * (quads of threshold planes), FA product shift
 // (-1: run time), CU unimolecular weight (-1: run time); SH: one shared
@@ -99,65 +358,19 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
     constexpr int WD = NB + 2;                             // product-delta planes
     if (w >= a.n_words) return;
 
-    const uint64_t rem = a.M - 32 * w;
-    const uint32_t live = rem >= 32 ? 0xFFFFFFFFu : ((1u << rem) - 1u);
+    const uint32_t live = live_lanes(a, w);
     const uint64_t *E = a.E + 32 * w;
     const uint64_t *T = a.Etgt + 32 * w;
+    const WordWindow win = word_window(a, E, T, live);
+    const uint64_t lo = win.lo, hi = win.hi;
 
-    // event window of this word over its pending lanes (E_l < Etgt_l); a
-    // lane that has finished its budget never limits the window
-    uint64_t lo = ~0ull, hi = 0, blo = 0, bhi = ~0ull;
-    uint32_t pend = 0;
-    for (int l = 0; l < 32; ++l) {
-        if (!((live >> l) & 1u)) continue;
-        const uint64_t x = E[l], y = T[l];
-        if (x >= y) continue;
-        pend |= 1u << l;
-        lo = x < lo ? x : lo;
-        blo = x > blo ? x : blo;
-        hi = y > hi ? y : hi;
-        bhi = y < bhi ? y : bhi;
-    }
-    if (!pend) lo = hi = 0;
-    if (a.max_events && hi > lo + a.max_events) hi = lo + a.max_events;
-
-    // load occupancies (species order L, D, A); planes at or above the
-    // stored count are zero
     uint32_t L[NB], D[NB], A[NB];
-    const uint32_t *pl = a.planes;
-    const int nbm = a.nb_mem;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const bool in = q < nbm;
-        L[q] = in ? pl[((uint64_t)0 * nbm + q) * a.wp + w] : 0u;
-        D[q] = in ? pl[((uint64_t)1 * nbm + q) * a.wp + w] : 0u;
-        A[q] = in ? pl[((uint64_t)2 * nbm + q) * a.wp + w] : 0u;
-    }
+    load_word<NB>(a, w, L, D, A);
 
     if (lo < hi) {
-        // pair counts and the unimolecular weight, recomputed once per launch
-        uint32_t PAL[WP], PAD[WP], PLD[WP];
-        mul_planes<NB, WP>(PAL, A, L);
-        mul_planes<NB, WP>(PAD, A, D);
-        mul_planes<NB, WP>(PLD, L, D);
-        uint32_t U[BC];
-#pragma unroll
-        for (int q = 0; q < BC; ++q) U[q] = 0;
+        uint32_t PAL[WP], PAD[WP], PLD[WP], U[BC];
         const uint32_t cu = CU >= 0 ? (uint32_t)CU : a.cu;
-#pragma unroll
-        for (int k = 0; k < BC; ++k) {
-            if ((cu >> k) & 1u) {
-                uint32_t c = 0;
-#pragma unroll
-                for (int q = k; q < BC; ++q) {
-                    const uint32_t v = (q - k < NB) ? A[q - k] : 0u;
-                    const uint32_t s = BWG_OP3(U[q], v, c, L_XOR3);
-                    c = BWG_OP3(U[q], v, c, L_MAJ);
-                    U[q] = s;
-                }
-            }
-        }
-        // per-plane constants of U's update: -cu (minus the +1) and 2 cu
+        init_weights<NB, BC, WP>(L, D, A, cu, PAL, PAD, PLD, U);
         const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
         const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
         const uint32_t G = (uint32_t)w;
@@ -170,12 +383,10 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
         uint64_t nreal = 0;
 
         for (uint64_t e = lo; e < hi; ++e) {
-            const uint32_t act = (e >= blo && e < bhi) ? pend : lane_mask(E, T, pend, e);
-
-            // (a) threshold planes: plane q is output q mod 4 of the Philox
-            // call with plane-quad q / 4; planes at or above B are zero
+            const uint32_t act =
+                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+            // (a) threshold planes
             uint32_t n[BC];
-            const uint32_t e_lo = (uint32_t)e, e_hi = (uint32_t)(e >> 32) & 0xFFFFu;
             if constexpr (SH) {
                 // one n for every replica: plane q is all ones where bit q is
                 // set; the next event's n is loaded while this one runs
@@ -184,157 +395,134 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
 #pragma unroll
                 for (int q = 0; q < BC; ++q)
                     n[q] = q < 32 ? (uint32_t)((int32_t)(nv << (31 - q)) >> 31) : 0u;
-            } else
-#pragma unroll
-            for (int q4 = 0; q4 < BC / 4; ++q4) {
-                uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-                if (q4 < nq)
-                    philox4x32_10(e_lo, (DOM_EVENT << 24) | ((uint32_t)q4 << 16) | e_hi, G,
-                                  a.net_id, k0, k1, o0, o1, o2, o3);
-                if (q4 == nq - 1) {
-                    o0 &= lastm[0];
-                    o1 &= lastm[1];
-                    o2 &= lastm[2];
-                    o3 &= lastm[3];
-                }
-                n[4 * q4 + 0] = o0;
-                n[4 * q4 + 1] = o1;
-                n[4 * q4 + 2] = o2;
-                n[4 * q4 + 3] = o3;
+            } else {
+                philox_planes<BC>(n, e, G, a.net_id, k0, k1, nq, lastm);
             }
-
-            // (b)-(d) cumulative weights and first crossing
-            uint32_t br = 0;
-#pragma unroll
-            for (int q = 0; q < BC; ++q) br = BWG_OP3(n[q], U[q], br, L_BORROW);
-            const uint32_t lt1 = br;  // n < U
-            br = 0;                   // n -= 2U (in place)
-#pragma unroll
-            for (int q = 1; q < BC; ++q) {
-                const uint32_t v = U[q - 1];
-                const uint32_t nb = BWG_OP3(n[q], v, br, L_BORROW);
-                n[q] = BWG_OP3(n[q], v, br, L_XOR3);
-                br = nb;
-            }
-            const uint32_t lt2 = br;  // n < 2U
-            uint32_t lt3 = lt2, lt4 = lt2, lt5;
-            if (has_a) {
-                lt3 = lt2 | sub_w<FA, BC, WP, true>(a.fa, n, PAL);
-                lt4 = lt3 | sub_w<FA, BC, WP, true>(a.fa, n, PAD);
-            }
-            lt5 = lt4;
-            if (has_i) lt5 = lt4 | sub_w<FA, BC, WP, false>(a.fi, n, PLD);
-
-            const uint32_t mL = (lt1 | (lt3 & ~lt2)) & act;
-            const uint32_t mD = ((lt2 & ~lt1) | (lt4 & ~lt3)) & act;
-            const uint32_t mI = (lt5 & ~lt4) & act;
-            const uint32_t mLD = mL | mD;
-            nreal += (uint32_t)__builtin_popcount(mLD | mI);
-
-            // (e) occupancies: keep the pre-event values for the products
-            uint32_t L2[NB], D2[NB], A2[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                L2[q] = L[q];
-                D2[q] = D[q];
-                A2[q] = A[q];
-            }
-            add_pm1<NB>(L2, mL, mI);
-            add_pm1<NB>(D2, mD, mI);
-            add_m1_p2<NB>(A2, mLD, mI);
-
-            // (f) products: P_AX += dA * X' + dX * A;  P_LD += dL * D' + dD * L
-            {
-                uint32_t t[WD];
-                const uint32_t mLI = mL | mI, mDI = mD | mI;
-                // P_AL
-                {
-                    uint32_t c = mLD;
-#pragma unroll
-                    for (int q = 0; q < WD; ++q) {
-                        const uint32_t xq = q < NB ? L2[q] : 0u;
-                        const uint32_t xm = (q >= 1 && q - 1 < NB) ? L2[q - 1] : 0u;
-                        const uint32_t t1 = BWG_OP3(mI, xm, BWG_OP3(mLD, xq, 0u, L_ANDNOT), L_ANDOR);
-                        const uint32_t t2 = q < NB ? BWG_OP3(A[q], mLI, mI, L_ANDXOR) : mI;
-                        t[q] = BWG_OP3(t1, t2, c, L_XOR3);
-                        c = BWG_OP3(t1, t2, c, L_MAJ);
-                    }
-                    add_sext<WP, WD>(PAL, t, mI);
-                }
-                // P_AD
-                {
-                    uint32_t c = mLD;
-#pragma unroll
-                    for (int q = 0; q < WD; ++q) {
-                        const uint32_t xq = q < NB ? D2[q] : 0u;
-                        const uint32_t xm = (q >= 1 && q - 1 < NB) ? D2[q - 1] : 0u;
-                        const uint32_t t1 = BWG_OP3(mI, xm, BWG_OP3(mLD, xq, 0u, L_ANDNOT), L_ANDOR);
-                        const uint32_t t2 = q < NB ? BWG_OP3(A[q], mDI, mI, L_ANDXOR) : mI;
-                        t[q] = BWG_OP3(t1, t2, c, L_XOR3);
-                        c = BWG_OP3(t1, t2, c, L_MAJ);
-                    }
-                    add_sext<WP, WD>(PAD, t, mI);
-                }
-                // P_LD
-                {
-                    uint32_t c = mI;
-#pragma unroll
-                    for (int q = 0; q < WD; ++q) {
-                        const uint32_t t1 = q < NB ? BWG_OP3(D2[q], mLI, mI, L_ANDXOR) : mI;
-                        const uint32_t t2 = q < NB ? BWG_OP3(L[q], mDI, mI, L_ANDXOR) : mI;
-                        t[q] = BWG_OP3(t1, t2, c, L_XOR3);
-                        c = BWG_OP3(t1, t2, c, L_MAJ);
-                    }
-                    add_sext<WP, WD>(PLD, t, mI);
-                }
-            }
-            // U += cu * dA with dA = -1 on mLD, +2 on mI: addend planes are the
-            // bits of -cu (two's complement, the +1 as carry-in) on mLD and of
-            // 2 cu on mI
-            if (cu) {
-                uint32_t c = mLD;
-#pragma unroll
-                for (int q = 0; q < BC; ++q) {
-                    uint32_t v;
-                    if constexpr (CU >= 0) {
-                        constexpr uint32_t ncu = ~(uint32_t)CU, dcu = 2u * (uint32_t)CU;
-                        const bool bn = (ncu >> q) & 1u, bd = (dcu >> q) & 1u;
-                        v = bn ? (bd ? (mLD | mI) : mLD) : (bd ? mI : 0u);
-                    } else {
-                        const uint32_t neg = ((cu >> q) & 1u) ? 0u : mLD;
-                        const uint32_t dbl = (q >= 1 && ((cu >> (q - 1)) & 1u)) ? mI : 0u;
-                        v = neg | dbl;
-                    }
-                    const uint32_t s = BWG_OP3(U[q], v, c, L_XOR3);
-                    if (q + 1 < BC) c = BWG_OP3(U[q], v, c, L_MAJ);
-                    U[q] = s;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                L[q] = L2[q];
-                D[q] = D2[q];
-                A[q] = A2[q];
-            }
+            word_event<NB, BC, FA, CU, WP, WD>(a, n, act, cu, has_a, has_i, L, D, A, PAL, PAD,
+                                               PLD, U, nreal);
         }
         a.real[w] += nreal;
     }
+    store_word<NB>(a, w, live, hi, L, D, A);
+}
 
-    // store occupancies and the new per-replica event counts
-    uint32_t *po = a.planes;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        if (q < nbm) {
-            po[((uint64_t)0 * nbm + q) * a.wp + w] = L[q];
-            po[((uint64_t)1 * nbm + q) * a.wp + w] = D[q];
-            po[((uint64_t)2 * nbm + q) * a.wp + w] = A[q];
-        }
+// 64-bit maximum over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+    for (int o = 32; o; o >>= 1) {
+        const uint64_t u = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)v, o) |
+                           ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o) << 32);
+        v = u > v ? u : v;
     }
-    uint64_t *Ew = a.E + 32 * w;
-    for (int l = 0; l < 32; ++l) {
-        if (!((live >> l) & 1u)) continue;
-        const uint64_t x = Ew[l], y = T[l];
-        Ew[l] = hi < x ? x : (hi > y ? y : hi);
+    return v;
+}
+
+// Producer/consumer form of wm_word for launches with fewer words than the
+// chip has SIMDs.  A workgroup of four waves serves 128 words in two groups
+// of 64: waves 0 and 1 draw the Philox threshold planes of their group's
+// events into the group's ring in LDS, waves 2 and 3 run selection and
+// updates on them, so a word's chain of events is split over two waves (and
+// two SIMDs: the waves of a workgroup are spread over the CU's SIMDs).  A
+// ring holds 2 halves of PH events; at step s the producer fills half s mod 2
+// with events [s PH, (s+1) PH) of every word's window while the consumer runs
+// the events of half (s-1) mod 2, and a barrier separates the steps.  The
+// step count is the workgroup's largest window, so every wave meets every
+// barrier.  Results are those of wm_word.
+template <int NB, int BC, int FA, int CU, int PH>
+__device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4][64],
+                                           uint64_t *wave_span)
+{
+    static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
+    constexpr int WP = 2 * NB - 2 > 1 ? 2 * NB - 2 : 2;
+    constexpr int WD = NB + 2;
+    const int lane = threadIdx.x & 63;
+    const int grp = (threadIdx.x >> 6) & 1;
+    const bool producer = threadIdx.x < 128;
+    ring += grp * 2 * PH;
+    const uint64_t w = (uint64_t)blockIdx.x * 128 + grp * 64 + lane;
+    // words past the end take part in every barrier with an empty window
+    const bool valid = w < a.n_words;
+    const uint32_t live = valid ? live_lanes(a, w) : 0u;
+    const uint64_t *E = a.E + 32 * (valid ? w : 0);
+    const uint64_t *T = a.Etgt + 32 * (valid ? w : 0);
+    const WordWindow win = word_window(a, E, T, live);
+    const uint64_t lo = win.lo, hi = win.hi;
+    {
+        const uint64_t m = wave_max_u64(hi - lo);
+        if (lane == 0) wave_span[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    uint64_t span = wave_span[0];
+    for (int i = 1; i < 4; ++i) span = wave_span[i] > span ? wave_span[i] : span;
+    const uint64_t nsteps = (span + PH - 1) / PH;
+    const int nq = (a.B + 3) / 4;
+
+    if (producer) {
+        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+        const uint32_t G = (uint32_t)w;
+        uint32_t lastm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
+        for (uint64_t s = 0; s <= nsteps; ++s) {
+            if (s < nsteps) {
+                const int half = (int)(s & 1) * PH;
+                for (int j = 0; j < PH; ++j) {
+                    const uint64_t e = lo + s * PH + j;
+                    if (e < hi) {
+                        uint32_t n[BC];
+                        philox_planes<BC>(n, e, G, a.net_id, k0, k1, nq, lastm);
+#pragma unroll
+                        for (int q4 = 0; q4 < BC / 4; ++q4)
+                            if (q4 < nq)
+                                ring[half + j][q4][lane] =
+                                    make_uint4(n[4 * q4], n[4 * q4 + 1], n[4 * q4 + 2], n[4 * q4 + 3]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    uint32_t L[NB], D[NB], A[NB];
+    if (valid) {
+        load_word<NB>(a, w, L, D, A);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) L[q] = D[q] = A[q] = 0u;
+    }
+    uint32_t PAL[WP], PAD[WP], PLD[WP], U[BC];
+    const uint32_t cu = CU >= 0 ? (uint32_t)CU : a.cu;
+    init_weights<NB, BC, WP>(L, D, A, cu, PAL, PAD, PLD, U);
+    const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
+    uint64_t nreal = 0;
+    for (uint64_t s = 0; s <= nsteps; ++s) {
+        if (s >= 1) {
+            const int half = (int)((s - 1) & 1) * PH;
+            for (int j = 0; j < PH; ++j) {
+                const uint64_t e = lo + (s - 1) * PH + j;
+                if (e < hi) {
+                    const uint32_t act =
+                        (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+                    uint32_t n[BC];
+#pragma unroll
+                    for (int q4 = 0; q4 < BC / 4; ++q4) {
+                        const uint4 v = q4 < nq ? ring[half + j][q4][lane] : make_uint4(0, 0, 0, 0);
+                        n[4 * q4 + 0] = v.x;
+                        n[4 * q4 + 1] = v.y;
+                        n[4 * q4 + 2] = v.z;
+                        n[4 * q4 + 3] = v.w;
+                    }
+                    word_event<NB, BC, FA, CU, WP, WD>(a, n, act, cu, has_a, has_i, L, D, A, PAL,
+                                                       PAD, PLD, U, nreal);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        if (lo < hi) a.real[w] += nreal;
+        store_word<NB>(a, w, live, hi, L, D, A);
     }
 }
 

@@ -36,9 +36,35 @@ __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
     wm_word<NB, BC, FA, CU, SH>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Producer/consumer form: four waves per 128 words, events handed over
+// through two rings of 2 x PH events of threshold planes in LDS (PH x BC KiB
+// in all, at most 128 KiB: the form runs at most 256 workgroups, one per
+// CU).  PH as measured best on the named workloads (3, 4, 6 and 8 tried).
+template <int BC>
+constexpr int pc_half()
+{
+    return BC == 20 ? 6 : 4;
+}
+
+template <int NB, int BC, int FA, int CU>
+__global__ __launch_bounds__(256) void wm_pc_kernel(WmArgs a)
+{
+    constexpr int PH = pc_half<BC>();
+    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];
+    __shared__ uint64_t wave_span[4];
+    wm_word_pc<NB, BC, FA, CU, PH>(a, ring, wave_span);
+}
+
 template <int NB, int BC, int FA, int CU>
 hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
 {
+    // with at most one wave of 64 words per SIMD pair half the chip would
+    // idle: split each word's events over a producer and a consumer wave
+    if (block <= 0 && !a.zs && a.n_words <= 32768) {
+        hipLaunchKernelGGL((wm_pc_kernel<NB, BC, FA, CU>), dim3((uint32_t)((a.n_words + 127) / 128)),
+                           dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     // 128-thread blocks leave two SIMDs of a CU to other blocks, which pays
     // while there are fewer words than one wave per SIMD; from 1024 waves on,
     // 256-thread blocks (one wave per SIMD of a CU) keep the waves spread
@@ -111,7 +137,8 @@ hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
 
 #define BWG_WM_INST(nb, bc, fa, cu)                                     \
     template __global__ void wm_event_kernel<nb, bc, fa, cu, false>(WmArgs); \
-    template __global__ void wm_event_kernel<nb, bc, fa, cu, true>(WmArgs);
+    template __global__ void wm_event_kernel<nb, bc, fa, cu, true>(WmArgs); \
+    template __global__ void wm_pc_kernel<nb, bc, fa, cu>(WmArgs);
 BWG_WM_VARIANTS(BWG_WM_INST)
 
 #ifndef __HIP_DEVICE_COMPILE__

@@ -29,10 +29,10 @@ def _say(*a):
 
 
 def gpu_run(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0,
-            shared=False):
+            shared=False, block=0):
     n = bwg.Network(net)
     ens = bwg.Ensemble(n, M, seed=seed, net_id=net_id, engine=engine, events_per_launch=epl,
-                       shared_threshold=shared)
+                       shared_threshold=shared, block=block)
     ens.init(init)
     for op, v in schedule:
         if op == "advance":
@@ -67,10 +67,10 @@ def group_sums(x, M):
 
 
 def check_parity(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0,
-                 shared=False):
-    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl, shared)
+                 shared=False, block=0):
+    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl, shared, block)
     counts, ev, real, ens = gpu_run(torch, net, M, init, schedule, seed, net_id, engine, epl,
-                                    shared)
+                                    shared, block)
     draw = (ssa.DRAW_PLAIN if engine == "plain" else
             ssa.DRAW_SHARED if shared else ssa.DRAW_EVENT)
     o = oracle_run(net, M, init, schedule, seed, net_id, draw)
@@ -189,6 +189,24 @@ def test_error_paths(torch):
         ens.init_fixed((0, 0, 31))  # does not sum to N_tot
     with pytest.raises(bwg.BwgError):
         ens.histogram(0)
+
+
+# ---- the two forms of the bit-sliced word kernel ----------------------------
+# With the default block and at most 32768 words a launch runs the producer/
+# consumer form (per 128 words two waves draw threshold planes into LDS and
+# two run the events); an explicit block size selects the one-wave-per-word
+# form.  The cases cover partial workgroups, a workgroup whose second group
+# of 64 words is empty, and words with different event windows.
+
+@pytest.mark.parametrize("block", [0, 64, 128, 256])
+@pytest.mark.parametrize("net,M,init,sched,epl", [
+    (frank_network(32), 64 * 32 * 3 + 17, ("fixed", (0, 0, 32)), [("advance", 30.0)], 0),
+    (frank_network(1024), 4096 + 5, ("fixed", (0, 0, 1024)), [("advance", 0.4), ("step", 99)], 0),
+    (paper_network(100), 31, ("multinomial",), [("step", 2500)], 333),
+    (frank_network(200, k0=0.03), 2048, ("multinomial",), [("advance", 2.0), ("advance", 2.5)], 1000),
+])
+def test_word_kernel_forms_match_oracle(torch, block, net, M, init, sched, epl):
+    check_parity(torch, net, M, init, sched, seed=12, net_id=4, epl=epl, block=block)
 
 
 # ---- comparator engine -----------------------------------------------------------
