@@ -35,7 +35,10 @@
  *               on [0, Z) by 32-bit multiply-shift with rejection on out0
  *               (the 256th attempt is taken as it is).  Z is the constant
  *               total weight when the ghost reactions make it state
- *               independent (the paper's Z, Eq. (9)), else W.
+ *               independent (the paper's Z, Eq. (9)), else W.  An advance
+ *               of this variant draws one BUDGET for every copy, at replica
+ *               index 0xFFFFFFFF, with mean (Z / s) (t_end - t_now): the
+ *               paper's single time step shared by the copies (Eq. (12)).
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -25,6 +25,9 @@ _MAX_S, _MAX_R = 8, 16
 DRAW_EVENT = 1
 DRAW_PLAIN = 4
 DRAW_SHARED = 6
+# Replica index of the one budget draw that every copy shares in the
+# shared-threshold variant (no replica has it: ensembles hold < 2^32).
+SHARED_BUDGET_REPLICA = 0xFFFFFFFF
 
 
 def build(force=True):
@@ -195,15 +198,29 @@ class OracleEnsemble:
         self.t_now = 0.0
         self.advance_index = 0
 
+    def event_rate(self):
+        """Events per unit time: Lambda = W / s; in the shared-threshold
+        variant Z / s (the paper's constant total propensity, Eqs. (9), (12)),
+        both divisions in binary64."""
+        if self.draw == DRAW_SHARED:
+            return self.q["z_shared"] / self.q["s"]
+        return self.q["Lambda"]
+
     def mean_events(self, t_end):
-        """mu = Lambda * (t_end - t_now) in binary64, in that order."""
-        return self.q["Lambda"] * (t_end - self.t_now)
+        """mu = rate * (t_end - t_now) in binary64, in that order."""
+        return self.event_rate() * (t_end - self.t_now)
 
     def advance(self, t_end, traj_len=0):
         if t_end < self.t_now:
             raise ValueError("t_end before the current time")
         mu = self.mean_events(t_end)
-        if mu > 0.0:
+        if mu > 0.0 and self.draw == DRAW_SHARED:
+            # one time step for every copy (the paper's shared tau): a single
+            # budget, drawn at the reserved replica index
+            k = budgets(self.seed, self.net_id, self.advance_index, SHARED_BUDGET_REPLICA, 1,
+                        poisson_table(mu))[0]
+            K = np.full(self.n, k, dtype=np.uint64)
+        elif mu > 0.0:
             K = budgets(self.seed, self.net_id, self.advance_index, self.first,
                         self.n, poisson_table(mu))
         else:

@@ -436,3 +436,63 @@ def test_shared_threshold_is_one_number_per_event():
     same.init(("fixed", (10, 10, 12)))
     same.step(500)
     assert (same.counts == same.counts[0]).all()
+
+
+def _paper_chain_time_law(n_tot, start, t):
+    """Law at time t of the paper's continuous-time chain (rates A L, A D,
+    L D with k = 1; the ghosts change nothing): exp(Q t) applied to the
+    start, Q written from the three reactions."""
+    from scipy.linalg import expm
+    states = [(l, d, n_tot - l - d) for l in range(n_tot + 1) for d in range(n_tot + 1 - l)]
+    idx = {s: i for i, s in enumerate(states)}
+    Q = np.zeros((len(states), len(states)))
+    for i, (l, d, a) in enumerate(states):
+        for w, s in ((a * l, (l + 1, d, a - 1)), (a * d, (l, d + 1, a - 1)),
+                     (l * d, (l - 1, d - 1, a + 2))):
+            if w:
+                Q[idx[s], i] += w
+                Q[i, i] -= w
+    p0 = np.zeros(len(states))
+    p0[idx[start]] = 1.0
+    return states, expm(Q * t) @ p0
+
+
+def test_shared_time_law_of_one_copy():
+    """With one shared budget per advance (the paper's shared tau) at rate
+    Z / s, each copy is the paper's continuous-time chain: 3000 independent
+    seeds against exp(Q t) from (2, 2, 2) at N = 6, t = 0.25 (two advances)."""
+    net = paper_network(6)
+    q = quantize(net)
+    start, t = (2, 2, 2), 0.25
+    states, p = _paper_chain_time_law(6, start, t)
+    idx = {s: i for i, s in enumerate(states)}
+    obs = np.zeros(len(states))
+    for seed in range(3000):
+        o = ssa.OracleEnsemble(net, 1, seed=seed, draw=ssa.DRAW_SHARED, q=q)
+        o.init(("fixed", start))
+        o.advance(0.1)
+        o.advance(t)
+        obs[idx[tuple(int(v) for v in o.counts[0])]] += 1
+    assert chi2_pvalue(obs, p * 3000) > 1e-3
+
+
+def test_shared_budget_is_one_poisson_number_per_advance():
+    """Every copy runs the same number of events in an advance, Poisson with
+    mean (Z / s) (t_end - t_now): 2000 seeds against the Poisson law."""
+    net = paper_network(10)
+    q = quantize(net)
+    rate = 45.0                               # Z = 10 * 9 / 2, s = 1
+    assert q["z_shared"] / q["s"] == rate
+    ks = []
+    for seed in range(2000):
+        o = ssa.OracleEnsemble(net, 20, seed=seed, draw=ssa.DRAW_SHARED, q=q)
+        o.init(("multinomial",))
+        o.advance(0.2)
+        assert (o.E == o.E[0]).all()
+        ks.append(int(o.E[0]))
+    ks = np.array(ks)
+    kmax = ks.max() + 1
+    obs = np.bincount(ks, minlength=kmax + 1)
+    exp = stats.poisson.pmf(np.arange(kmax + 1), rate * 0.2) * len(ks)
+    exp[-1] += stats.poisson.sf(kmax, rate * 0.2) * len(ks)
+    assert chi2_pvalue(obs, exp) > 1e-3
