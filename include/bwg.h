@@ -145,17 +145,18 @@ typedef struct {
 #define BWG_OPT_TIME_KERNELS 1u  /* record HIP events around every event-kernel
                                     launch (bwg_ensemble_kernel_time)         */
 /* The paper's shared-threshold variant (Sec. 4, after the bitwise step; the
- * speed-up it measures in Sec. 6): at event e every replica compares the
- * same n, uniform on [0, z_shared), against its own cumulative weights, so
- * one random number serves all replicas.  The replicas stay exact marginal
- * copies of the chain but are no longer independent of each other.  Only
- * for the bit-sliced and lanes engines on well-mixed networks (EUNSUPPORTED
- * otherwise; ERANGE when z_shared is 0); such an ensemble moves only by
- * bwg_ensemble_step (advance, schedule and batches return EUNSUPPORTED),
- * since with z_shared < 2^B the event rate z_shared / s differs from lambda.
- * A step runs in launches of at most 2 * table_capacity events (and at most
- * events_per_launch, if set), each after a fill of its thresholds into the
- * ensemble's table region. */
+ * gain it measures in Sec. 5): at event e every replica compares the same n,
+ * uniform on [0, z_shared), against its own cumulative weights, so one random
+ * number serves all replicas; and an advance draws one event budget for all
+ * of them (the paper's single time step per iteration, Eq. (12)), Poisson with
+ * mean (z_shared / s) (t_end - t_now): events arrive at the paper's constant
+ * total propensity instead of lambda.  The replicas stay exact marginal copies
+ * of the chain but are no longer independent of each other, and they move in
+ * lockstep.  Only for the bit-sliced and lanes engines on well-mixed networks
+ * (EUNSUPPORTED otherwise; ERANGE when z_shared is 0); batches refuse such
+ * ensembles (EUNSUPPORTED).  A step or advance runs in launches of at most
+ * 2 * table_capacity events (and at most events_per_launch, if set), each
+ * after a fill of its thresholds into the ensemble's table region. */
 #define BWG_OPT_SHARED_THRESHOLD 2u
 
 typedef struct {

@@ -729,13 +729,79 @@ static int run_events(bwg_ens *e, hipStream_t s)
     return BWG_OK;
 }
 
+// Philox4x32-10 on the host (Salmon et al., SC'11): the same rounds as the
+// device function, for the one budget a shared-threshold advance draws.
+static void host_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed,
+                        uint32_t out[4])
+{
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// The budget every replica of a shared-threshold ensemble runs in an advance
+// (the paper's one time step for all copies): one BUDGET draw at the
+// reserved replica index 0xFFFFFFFF, inverted through the Poisson table.
+static uint64_t shared_budget(const bwg_ens *e, const Table *t)
+{
+    uint32_t o[4];
+    host_philox((uint32_t)e->adv, (DOM_BUDGET << 24) | ((uint32_t)(e->adv >> 32) & 0xFFFFu),
+                0xFFFFFFFFu, e->net_id, e->seed, o);
+    const uint64_t u = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+    const uint64_t *T = t->host;
+    uint64_t lo = 0, hi = t->len;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (T[mid] <= u)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (uint64_t)(t->k_lo + (int64_t)lo);
+}
+
 int bwg::schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin_out,
                            uint64_t *kmax_out)
 {
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
-    if (e->zs) return fail(BWG_EUNSUPPORTED, "shared-threshold ensembles move by bwg_ensemble_step");
     if (!(t_end >= e->t_now)) return fail(BWG_EINVAL, "t_end %g before t_now %g", t_end, e->t_now);
     if (e->adv >= (1ull << 48)) return fail(BWG_ERANGE, "advance index overflow");
+    if (e->zs) {
+        // events arrive at rate Z / s, one budget for every replica; the
+        // replicas stay in lockstep only if the last budget has run
+        if (e->pending) return fail(BWG_EINVAL, "shared thresholds: run the pending events first");
+        const double mu = ((double)e->zs / e->net->q.s) * (t_end - e->t_now);
+        uint64_t K = 0;
+        if (mu > 0) {
+            const Table *t;
+            const int rc = get_table(e->net, mu, &t);
+            if (rc) return rc;
+            K = shared_budget(e, t);
+        }
+        HIP_TRY(launch_budget(nullptr, 0, 0, K, 0, e->seed, e->net_id, e->adv_dev, e->M, e->E,
+                              e->Et, s));
+        HIP_TRY(launch_add_u64(e->adv_dev, 1, s));
+        e->t_now = t_end;
+        e->adv += 1;
+        *kmin_out = *kmax_out = K;
+        return BWG_OK;
+    }
     const double mu = e->net->q.lambda * (t_end - e->t_now);
     uint64_t kmin = 0, kmax = 0;
     if (mu > 0) {
@@ -813,6 +879,8 @@ extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
         const int rc = lat_step_schedule(e, n_events, s);
         return rc ? rc : lat_run(e, 0, s);
     }
+    if (e->zs && e->pending)
+        return fail(BWG_EINVAL, "shared thresholds: run the pending events first");
     HIP_TRY(launch_budget(nullptr, 0, 0, n_events, 0, e->seed, e->net_id, e->adv_dev, e->M, e->E,
                           e->Et, s));
     note_scheduled(e, n_events, n_events);

@@ -349,14 +349,62 @@ def test_shared_threshold_full_size_sampled(torch):
         np.testing.assert_array_equal(counts[first:first + 16], o.counts)
 
 
+@pytest.mark.parametrize("net,M,sched,engine,epl,cap", [
+    (paper_network(32), 1000, [("advance", 20.0)], "bitwise", 0, 0),
+    (paper_network(100), 333, [("advance", 0.5), ("step", 77), ("advance", 1.25)], "lanes", 0, 0),
+    (paper_network(64), 200, [("advance", 3.0), ("advance", 3.0), ("advance", 4.5)], "bitwise",
+     700, 0),
+    (paper_network(24), 97, [("advance", 40.0)], "bitwise", 0, 1000),
+    (frank_network(64), 700, [("advance", 2.0), ("step", 10)], "bitwise", 0, 0),
+])
+def test_shared_time_matches_oracle(torch, net, M, sched, engine, epl, cap):
+    """Advances of a shared-threshold ensemble: one budget for every replica
+    at rate Z / s, run in launches of at most 2 x table_capacity events."""
+    _say("shared time", net["n_tot"], M, sched, engine, epl, cap)
+    n = bwg.Network(net)
+    e = bwg.Ensemble(n, M, seed=5, net_id=8, engine=engine, events_per_launch=epl,
+                     table_capacity=cap, shared_threshold=True)
+    e.init(("multinomial",))
+    o = ssa.OracleEnsemble(net, M, seed=5, net_id=8, draw=ssa.DRAW_SHARED)
+    o.init(("multinomial",))
+    for op, v in sched:
+        getattr(e, op)(v)
+        getattr(o, op)(v)
+    ev, real = e.read_events()
+    np.testing.assert_array_equal(e.read_counts().cpu().numpy(), o.counts)
+    np.testing.assert_array_equal(ev.cpu().numpy(), o.E)
+    np.testing.assert_array_equal(real.cpu().numpy().astype(np.uint64), group_sums(o.real, M))
+    assert (o.E == o.E[0]).all() and o.E[0] > 0
+
+
+def test_shared_time_split_schedule_and_run(torch):
+    """schedule + capped runs give what one advance gives; a new schedule or
+    step before the pending events have run is refused."""
+    net = paper_network(40)
+    a = bwg.Ensemble(bwg.Network(net), 500, seed=2, shared_threshold=True)
+    b = bwg.Ensemble(bwg.Network(net), 500, seed=2, shared_threshold=True)
+    for x in (a, b):
+        x.init(("multinomial",))
+    a.advance(5.0)
+    b.schedule(5.0)
+    b.run(333)
+    with pytest.raises(bwg.BwgError):
+        b.schedule(6.0)
+    with pytest.raises(bwg.BwgError):
+        b.step(5)
+    while b.pending():
+        b.run(333)
+    np.testing.assert_array_equal(a.read_counts().cpu().numpy(), b.read_counts().cpu().numpy())
+    np.testing.assert_array_equal(a.read_events()[0].cpu().numpy(),
+                                  b.read_events()[0].cpu().numpy())
+
+
 def test_shared_threshold_rejections(torch):
     net = bwg.Network(paper_network(32))
     e = bwg.Ensemble(net, 100, shared_threshold=True)
     e.init(("multinomial",))
-    for call in (lambda: e.advance(1.0), lambda: e.schedule(1.0),
-                 lambda: bwg.Batch([e])):
-        with pytest.raises(bwg.BwgError):
-            call()
+    with pytest.raises(bwg.BwgError):
+        bwg.Batch([e])
     with pytest.raises(bwg.BwgError):
         bwg.Ensemble(net, 100, engine="plain", shared_threshold=True)
     lat = bwg.Network(frank_network(12, lx=4, ly=4, hop=0.1, site_planes=4))
