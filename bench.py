@@ -13,6 +13,8 @@ a bounded sample.
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -74,7 +76,7 @@ def main():
     ap.add_argument("--cpu-replicas", type=int, default=65536)
     ap.add_argument("--cpu-replicas-lattice", type=int, default=64)
     ap.add_argument("--workload", default="well-mixed",
-                    choices=["well-mixed", "lattice", "batch", "serve", "gain"],
+                    choices=["well-mixed", "lattice", "batch", "serve", "gain", "trajectory"],
                     help="lattice: 64x64 compartments, 2^16 replicas; batch: the 256 uneven "
                          "networks in one persistent launch; gain: the paper's Q(N) sweep")
     ap.add_argument("--gain-n", default="8,16,32,64,128,256,512,1024",
@@ -116,6 +118,8 @@ def main():
         return bench_serve(args)
     if args.workload == "gain":
         return bench_gain(args)
+    if args.workload == "trajectory":
+        return bench_trajectory(args)
 
     c = config("c1")
     net, M, t_end = c["net"], c["replicas"], c["t_end"]
@@ -492,6 +496,65 @@ def bench_gain(args):
                                   % (M, T, args.gain_n),
                       "value_at_n_tot": last["n_tot"]},
            "rows": rows}
+    print(json.dumps(out))
+
+
+def bench_trajectory(args):
+    """The paper's trajectory figure as a workload (Sec. 5, Sec. 6): its
+    network at N_tot = 32 with the shared threshold and shared time, 2^22
+    replicas from multinomial starts around the racemic state, recorded on a
+    grid of 100 times up to t = 2 (L, D, A of 64 replicas after each) with
+    every replica's first grid time at |N_L - N_D| >= 24; against the rate of
+    one advance to t = 2 (one budget instead of 100, so another count)."""
+    import torch
+    import paper_2412_16613_amd as bwg
+    from workloads import paper_network
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, M, t_end, n_grid, thr = 32, 1 << 22, 2.0, 100, 24
+    network = bwg.Network(paper_network(N))
+    grid = [t_end * (k + 1) / n_grid for k in range(n_grid)]
+    sel = list(range(0, M, M // 64))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3, out
+
+    def make():
+        e = bwg.Ensemble(network, M, seed=7, net_id=1, device=dev, shared_threshold=True)
+        e.init(("multinomial",))
+        return e
+
+    make().record(grid[:10], sel, threshold=thr)                     # warm-up
+    e = make()
+    s_rec, (traj, first) = timed(lambda: e.record(grid, sel, threshold=thr))
+    ev = e.stats()["events_total"]
+    f = make()
+    s_adv, _ = timed(lambda: f.advance(t_end))
+    ev_adv = f.stats()["events_total"]          # one budget instead of 100: another count
+    counts = e.read_counts().cpu().numpy()
+    first = first.cpu().numpy()
+    hit = first >= 0
+    out = {"metric": "replica-events/sec recording trajectories (1 GPU)",
+           "value": ev / s_rec, "unit": "replica-events/s", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "u32 bit-planes",
+           "data": "synthetic",
+           "config": {"workload": "paper's network N_tot=32 with ghosts, shared threshold and "
+                                  "time, 2^22 replicas, multinomial start, 100 grid times to "
+                                  "t=2, 64 recorded replicas, first passage at |L-D| >= 24"},
+           "seconds": s_rec, "one_advance_seconds": s_adv,
+           "one_advance_replica_events_per_s": ev_adv / s_adv,
+           "recording_cost_factor": (ev_adv / s_adv) / (ev / s_rec),
+           "homochiral_fraction": float(hit.mean()),
+           "L_fraction_of_homochiral": float((counts[hit, 0] > counts[hit, 1]).mean()),
+           "median_first_passage_time": float(grid[int(np.median(first[hit]))]) if hit.any()
+           else None}
     print(json.dumps(out))
 
 

@@ -269,6 +269,23 @@ int bwg_ensemble_read_counts(bwg_ens *ens, int32_t *dev_dst, void *stream);
 int bwg_ensemble_histogram(bwg_ens *ens, int32_t n_bins, uint64_t *dev_dst,
                            void *stream);
 
+/* Trajectories of chosen replicas and first passages to homochirality (the
+ * paper's trajectory figure and its use for rare events, Sec. 5 and Sec. 6):
+ * for k = 0 .. n_points-1, advance to t_grid[k] (host array, non-decreasing,
+ * from t_now on; EINVAL before any work otherwise), then
+ *   - copy the counts of replicas dev_sel[0 .. n_sel) (device, uint32) into
+ *     dev_out[(k * n_sel + j) * 3 + x] (device, int32, species order); an
+ *     index at or past the replica count gives -1;
+ *   - if dev_first is not NULL (device, uint32[n_replicas]): every replica
+ *     whose entry is still 0xFFFFFFFF and whose |N_L - N_D| >= threshold gets
+ *     dev_first[i] = k (the caller fills it with 0xFFFFFFFF first).
+ * The same as n_points calls of bwg_ensemble_advance with a read after each.
+ * Well-mixed ensembles of any engine, Frank species (EUNSUPPORTED for
+ * lattices).  Async. */
+int bwg_ensemble_record(bwg_ens *ens, const double *t_grid, uint32_t n_points,
+                        const uint32_t *dev_sel, uint32_t n_sel, int32_t *dev_out,
+                        int32_t threshold, uint32_t *dev_first, void *stream);
+
 /* Events run per replica, dev_events[i], and real (state-changing) events
  * so far, dev_real[]: per replica for the plain engine, per 32-replica word
  * (ceil(M/32) entries) for the bit-sliced engine and lattices.  uint64;

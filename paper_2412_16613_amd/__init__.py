@@ -231,6 +231,30 @@ class Ensemble:
                                                     self._stream()))
         return out
 
+    def record(self, t_grid, replicas=(), threshold=None, first=None):
+        """Advance through t_grid; return (counts of the chosen replicas after
+        each grid time, int32 [n_points, n_sel, 3]; first grid index at which
+        |N_L - N_D| >= threshold per replica, int64 [M] with -1 for never, or
+        None).  `first` continues an earlier record's first-passage tensor
+        (uint32-valued, as returned with -1 entries)."""
+        t = self.torch
+        grid = [float(x) for x in t_grid]
+        arr = (ctypes.c_double * max(len(grid), 1))(*grid)
+        sel = t.tensor(list(replicas), dtype=t.int32, device=self.device)
+        out = t.empty((len(grid), len(sel), 3), dtype=t.int32, device=self.device)
+        fp = None
+        if threshold is not None:
+            if first is None:
+                fp = t.full((self.M,), -1, dtype=t.int32, device=self.device)
+            else:
+                fp = first.to(device=self.device, dtype=t.int32).clone()
+        _abi.check(_lib().bwg_ensemble_record(
+            self.handle, arr, len(grid), ctypes.c_void_p(sel.data_ptr() if len(sel) else 0),
+            len(sel), ctypes.c_void_p(out.data_ptr() if len(sel) else 0),
+            int(threshold or 0), ctypes.c_void_p(fp.data_ptr() if fp is not None else 0),
+            self._stream()))
+        return out, (fp.to(t.int64) if fp is not None else None)
+
     def read_events(self):
         """(events per replica, real events per 32-lane group (bitwise) or
         per replica (plain)) as int64 tensors."""

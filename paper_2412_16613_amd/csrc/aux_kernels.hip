@@ -182,6 +182,43 @@ __global__ void histogram_kernel(const uint32_t *planes, const int32_t *counts, 
         if (hist[b]) atomicAdd((unsigned long long *)&dst[b], (unsigned long long)hist[b]);
 }
 
+// Counts of the selected replicas into dst[j * 3 + x]; an index at or past
+// M gives -1 for every species.
+__global__ void gather_counts_kernel(const uint32_t *planes, const int32_t *counts, int nb,
+                                     uint64_t wp, uint64_t M, const uint32_t *sel, uint32_t n_sel,
+                                     int32_t *dst)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_sel) return;
+    const uint64_t i = sel[j];
+    for (int x = 0; x < 3; ++x) {
+        int32_t v = -1;
+        if (i < M)
+            v = planes ? plane_count(planes, x, nb, wp, i >> 5, (int)(i & 31)) : counts[3 * i + x];
+        dst[3 * j + x] = v;
+    }
+}
+
+// first[i] = k for every replica that has no entry yet (0xFFFFFFFF) and whose
+// |N_L - N_D| has reached the threshold.
+__global__ void first_passage_kernel(const uint32_t *planes, const int32_t *counts, int nb,
+                                     uint64_t wp, uint64_t M, int32_t threshold, uint32_t k,
+                                     uint32_t *first)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M || first[i] != 0xFFFFFFFFu) return;
+    int32_t nl, nd;
+    if (planes) {
+        nl = plane_count(planes, 0, nb, wp, i >> 5, (int)(i & 31));
+        nd = plane_count(planes, 1, nb, wp, i >> 5, (int)(i & 31));
+    } else {
+        nl = counts[3 * i];
+        nd = counts[3 * i + 1];
+    }
+    const int32_t d = nl - nd;
+    if ((d < 0 ? -d : d) >= threshold) first[i] = k;
+}
+
 __global__ void copy_u64_kernel(const uint64_t *src, uint64_t *dst, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -278,6 +315,25 @@ hipError_t launch_histogram(const uint32_t *planes, const int32_t *counts, int n
     hipLaunchKernelGGL(histogram_kernel, grid_for(M, 256), dim3(256),
                        (size_t)n_bins * sizeof(uint32_t), s, planes, counts, nb, wp, M, n_tot,
                        n_bins, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_counts(const uint32_t *planes, const int32_t *counts, int nb,
+                                uint64_t wp, uint64_t M, const uint32_t *sel, uint32_t n_sel,
+                                int32_t *dst, hipStream_t s)
+{
+    if (n_sel == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_counts_kernel, grid_for(n_sel, 256), dim3(256), 0, s, planes,
+                       counts, nb, wp, M, sel, n_sel, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_first_passage(const uint32_t *planes, const int32_t *counts, int nb,
+                                uint64_t wp, uint64_t M, int32_t threshold, uint32_t k,
+                                uint32_t *first, hipStream_t s)
+{
+    hipLaunchKernelGGL(first_passage_kernel, grid_for(M, 256), dim3(256), 0, s, planes, counts,
+                       nb, wp, M, threshold, k, first);
     return hipGetLastError();
 }
 

@@ -213,6 +213,12 @@ hipError_t launch_read_counts_plain(const int32_t *counts, uint64_t M, int32_t *
 hipError_t launch_histogram(const uint32_t *planes, const int32_t *counts, int nb,
                             uint64_t wp, uint64_t M, int64_t n_tot, int n_bins,
                             uint64_t *dst, hipStream_t s);
+hipError_t launch_gather_counts(const uint32_t *planes, const int32_t *counts, int nb,
+                                uint64_t wp, uint64_t M, const uint32_t *sel, uint32_t n_sel,
+                                int32_t *dst, hipStream_t s);
+hipError_t launch_first_passage(const uint32_t *planes, const int32_t *counts, int nb,
+                                uint64_t wp, uint64_t M, int32_t threshold, uint32_t k,
+                                uint32_t *first, hipStream_t s);
 hipError_t launch_copy_u64(const uint64_t *src, uint64_t *dst, uint64_t n, hipStream_t s);
 hipError_t launch_sum_u64(const uint64_t *src, uint64_t n, uint64_t *dst2, int slot,
                           hipStream_t s);

@@ -317,22 +317,24 @@ extern "C" int bwg_poisson_table(double mu, int64_t *k_lo, uint64_t *table, uint
 }
 
 // Cached pinned copy of the table for mean mu.
-int bwg::get_table(bwg_net *n, double mu, const Table **out)
+int bwg::get_table(bwg_net *n, double mu, const Table **out, bool pinned)
 {
     uint64_t key;
     memcpy(&key, &mu, sizeof key);
     std::lock_guard<std::mutex> g(n->mu);
     auto it = n->tables.find(key);
     if (it == n->tables.end()) {
-        std::vector<uint64_t> T;
-        int64_t k_lo;
-        if (poisson_table_q(mu, &k_lo, T) != 0) return fail(BWG_EINVAL, "invalid mean %g", mu);
-        Table t{k_lo, T.size(), nullptr};
-        HIP_TRY(hipHostMalloc((void **)&t.host, T.size() * sizeof(uint64_t), hipHostMallocDefault));
-        memcpy(t.host, T.data(), T.size() * sizeof(uint64_t));
-        it = n->tables.emplace(key, t).first;
+        Table t{0, 0, {}, nullptr};
+        if (poisson_table_q(mu, &t.k_lo, t.vals) != 0) return fail(BWG_EINVAL, "invalid mean %g", mu);
+        t.len = t.vals.size();
+        it = n->tables.emplace(key, std::move(t)).first;
     }
-    *out = &it->second;
+    Table &t = it->second;
+    if (pinned && !t.host) {
+        HIP_TRY(hipHostMalloc((void **)&t.host, t.len * sizeof(uint64_t), hipHostMallocDefault));
+        memcpy(t.host, t.vals.data(), t.len * sizeof(uint64_t));
+    }
+    *out = &t;
     return BWG_OK;
 }
 
@@ -764,7 +766,7 @@ static uint64_t shared_budget(const bwg_ens *e, const Table *t)
     host_philox((uint32_t)e->adv, (DOM_BUDGET << 24) | ((uint32_t)(e->adv >> 32) & 0xFFFFu),
                 0xFFFFFFFFu, e->net_id, e->seed, o);
     const uint64_t u = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
-    const uint64_t *T = t->host;
+    const uint64_t *T = t->vals.data();
     uint64_t lo = 0, hi = t->len;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
@@ -790,7 +792,7 @@ int bwg::schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *km
         uint64_t K = 0;
         if (mu > 0) {
             const Table *t;
-            const int rc = get_table(e->net, mu, &t);
+            const int rc = get_table(e->net, mu, &t, false);
             if (rc) return rc;
             K = shared_budget(e, t);
         }
@@ -907,6 +909,38 @@ extern "C" int bwg_ensemble_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst,
     if (e->lat) return lat_histogram(e, n_bins, dst, s);
     HIP_TRY(launch_histogram(e->engine != BWG_ENGINE_PLAIN ? e->planes : nullptr, e->counts,
                              e->nb, e->wp, e->M, e->net->n_tot, n_bins, dst, s));
+    return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_record(bwg_ens *e, const double *t_grid, uint32_t n_points,
+                                   const uint32_t *dev_sel, uint32_t n_sel, int32_t *dev_out,
+                                   int32_t threshold, uint32_t *dev_first, void *stream)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
+    if (e->lat) return fail(BWG_EUNSUPPORTED, "record runs on well-mixed ensembles");
+    if (n_points && !t_grid) return fail(BWG_EINVAL, "null time grid");
+    if (n_points && n_sel && (!dev_sel || !dev_out))
+        return fail(BWG_EINVAL, "null selection or output");
+    if (dev_first && threshold < 0) return fail(BWG_EINVAL, "negative threshold");
+    if (n_points >= 0xFFFFFFFFu) return fail(BWG_EINVAL, "too many grid points");
+    double t = e->t_now;
+    for (uint32_t k = 0; k < n_points; ++k) {
+        if (!(t_grid[k] >= t))
+            return fail(BWG_EINVAL, "grid point %u (%g) before %g", k, t_grid[k], t);
+        t = t_grid[k];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t *planes = e->engine != BWG_ENGINE_PLAIN ? e->planes : nullptr;
+    for (uint32_t k = 0; k < n_points; ++k) {
+        const int rc = bwg_ensemble_advance(e, t_grid[k], stream);
+        if (rc) return rc;
+        HIP_TRY(launch_gather_counts(planes, e->counts, e->nb, e->wp, e->M, dev_sel, n_sel,
+                                     dev_out ? dev_out + (uint64_t)k * n_sel * 3 : nullptr, s));
+        if (dev_first)
+            HIP_TRY(launch_first_passage(planes, e->counts, e->nb, e->wp, e->M, threshold, k,
+                                         dev_first, s));
+    }
     return BWG_OK;
 }
 

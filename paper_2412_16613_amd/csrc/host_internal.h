@@ -29,7 +29,9 @@ int fail(int code, const char *fmt, ...);
 struct Table {  // Poisson table of one mean
     int64_t k_lo;
     uint64_t len;
-    uint64_t *host;  // pinned; lives as long as the network
+    std::vector<uint64_t> vals;  // the entries, for host-side draws
+    uint64_t *host;              // pinned copy for uploads (made on first need);
+                                 // lives as long as the network
 };
 
 struct bwg_net {
@@ -109,8 +111,9 @@ struct bwg_ens {
 
 
 namespace bwg {
-// Cached pinned Poisson table for mean mu (lives as long as the network).
-int get_table(bwg_net *n, double mu, const Table **out);
+// Cached Poisson table for mean mu (lives as long as the network); with
+// pinned, also its pinned copy for uploads to the device.
+int get_table(bwg_net *n, double mu, const Table **out, bool pinned = true);
 // Budgets of one advance to t_end (no event launches); *kmin/*kmax bound K.
 int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, uint64_t *kmax);
 // Bookkeeping after budgets with K in [kmin, kmax] were drawn.
