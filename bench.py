@@ -76,7 +76,8 @@ def main():
     ap.add_argument("--cpu-replicas", type=int, default=65536)
     ap.add_argument("--cpu-replicas-lattice", type=int, default=64)
     ap.add_argument("--workload", default="well-mixed",
-                    choices=["well-mixed", "lattice", "batch", "serve", "gain", "trajectory"],
+                    choices=["well-mixed", "lattice", "batch", "serve", "gain", "trajectory",
+                             "general"],
                     help="lattice: 64x64 compartments, 2^16 replicas; batch: the 256 uneven "
                          "networks in one persistent launch; gain: the paper's Q(N) sweep")
     ap.add_argument("--gain-n", default="8,16,32,64,128,256,512,1024",
@@ -120,6 +121,8 @@ def main():
         return bench_gain(args)
     if args.workload == "trajectory":
         return bench_trajectory(args)
+    if args.workload == "general":
+        return bench_general(args)
 
     c = config("c1")
     net, M, t_end = c["net"], c["replicas"], c["t_end"]
@@ -495,6 +498,54 @@ def bench_gain(args):
                                   "%d replicas, T=%d steps, N_tot in %s"
                                   % (M, T, args.gain_n),
                       "value_at_n_tot": last["n_tot"]},
+           "rows": rows}
+    print(json.dumps(out))
+
+
+def bench_general(args):
+    """The general bit-sliced kernel (weights recomputed from the planes at
+    every event) against the Frank kernel on the Frank workload N_tot = 1024,
+    2^20 replicas, and against the plain engine on seeded random 3-species
+    networks of order <= 2 (2^20 replicas, about 2000 events each)."""
+    import torch
+    import paper_2412_16613_amd as bwg
+    from workloads import config, random_network
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def rate(net, M, init, horizon, **kw):
+        e = bwg.Ensemble(bwg.Network(net), M, seed=1, net_id=2, device=dev, **kw)
+        e.init(init)
+        e.advance(horizon / 20)                                       # warm-up
+        torch.cuda.synchronize()
+        ev0 = e.stats()["events_total"]
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        e.advance(horizon)
+        b.record()
+        torch.cuda.synchronize()
+        return (e.stats()["events_total"] - ev0) / (a.elapsed_time(b) / 1e3)
+
+    c = config("c1")
+    rows = {"frank1024": {
+        "frank_kernel": rate(c["net"], c["replicas"], c["init"], c["t_end"] / 4),
+        "general_kernel": rate(c["net"], c["replicas"], c["init"], c["t_end"] / 4, generic=True),
+        "plain": rate(c["net"], c["replicas"], c["init"], c["t_end"] / 4, engine="plain")}}
+    for seed, n_tot, n_r in ((1, 50, 7), (2, 200, 12), (8, 400, 5)):
+        net = random_network(seed, n_tot, n_r)
+        t = 2000.0 / bwg.Network(net).quantized()["Lambda"]
+        rows["random_s%d_n%d_r%d" % (seed, n_tot, n_r)] = {
+            "general_kernel": rate(net, 1 << 20, ("multinomial",), t),
+            "plain": rate(net, 1 << 20, ("multinomial",), t, engine="plain")}
+    for r in rows.values():
+        r["general_over_plain"] = r["general_kernel"] / r["plain"]
+    out = {"metric": "replica-events/sec of the general bit-sliced kernel (1 GPU)",
+           "value": rows["frank1024"]["general_kernel"], "unit": "replica-events/s",
+           "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+           "dtype": "u32 bit-planes", "data": "synthetic",
+           "config": {"workload": "Frank N_tot=1024 and seeded random 3-species networks, "
+                                  "2^20 replicas"},
            "rows": rows}
     print(json.dumps(out))
 

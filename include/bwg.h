@@ -50,12 +50,16 @@ enum {
 #define BWG_EXACT_INTEGER 1u   /* rates are the integer weights (paper mode) */
 
 /* engines of bwg_opts */
-#define BWG_ENGINE_BITWISE 0   /* bit-sliced words, 32 replicas per lane      */
+#define BWG_ENGINE_BITWISE 0   /* bit-sliced words, 32 replicas per lane: the
+                                  Frank-family kernel (incremental products,
+                                  App. B) for the five Frank reactions with or
+                                  without ghosts, the general kernel for any
+                                  other 3-species network of order <= 2      */
 #define BWG_ENGINE_PLAIN 1     /* comparator: one replica per thread, int32   */
 #define BWG_ENGINE_LANES 2     /* the bit-plane state and draws of BITWISE, one
                                   replica per thread: identical results, a
                                   shorter chain per event, more work per
-                                  replica-event                               */
+                                  replica-event (Frank family only)          */
 
 /* initial-state modes of bwg_ensemble_init */
 #define BWG_INIT_FIXED 0        /* every replica starts from counts[0..S-1]   */
@@ -158,6 +162,14 @@ typedef struct {
  * 2 * table_capacity events (and at most events_per_launch, if set), each
  * after a fill of its thresholds into the ensemble's table region. */
 #define BWG_OPT_SHARED_THRESHOLD 2u
+/* Run a Frank-family network on the general bit-sliced kernel, the one
+ * every other 3-species network of order <= 2 takes on the bit-sliced engine:
+ * weights c_j h_j recomputed from the planes at every event (h = N_X,
+ * N_X N_Y or N_X (N_X - 1) / 2, Eq. (7)), first crossing in table order,
+ * the same draws, so the same results as the Frank kernel at a higher cost
+ * per event.  Bit-sliced engine on well-mixed networks only (EUNSUPPORTED
+ * otherwise), not with BWG_OPT_SHARED_THRESHOLD. */
+#define BWG_OPT_GENERIC_KERNEL 4u
 
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */

@@ -102,7 +102,7 @@ class Ensemble:
 
     def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
                  device="cuda", events_per_launch=0, table_capacity=0, block=0,
-                 time_kernels=False, shared_threshold=False):
+                 time_kernels=False, shared_threshold=False, generic=False):
         import torch
         self.torch = torch
         L = _lib()
@@ -115,7 +115,8 @@ class Ensemble:
         o.table_capacity = table_capacity
         o.events_per_launch = events_per_launch
         o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
-                   (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0))
+                   (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0) |
+                   (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0))
         self._opts = o
         nbytes = ctypes.c_uint64()
         _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),

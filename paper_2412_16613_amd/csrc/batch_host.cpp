@@ -103,6 +103,8 @@ static int check_members(bwg_ens *const *ens, int32_t n, uint64_t *items)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: batches run the bit-plane engines", k);
         if (e->zs)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: shared-threshold ensembles move by step", k);
+        if (!e->net->shape_ok)
+            return fail(BWG_EUNSUPPORTED, "ensemble %d: batches run Frank-family networks", k);
         if (e->lat)
             return fail(BWG_EUNSUPPORTED, "ensemble %d: lattices run their own launches", k);
         if (pick_bucket(e) < 0)

@@ -80,6 +80,29 @@ struct WmVariant {
 extern const WmVariant kWmVariants[];
 extern const int kWmVariantCount;
 
+// Any 3-species network of order <= 2 on the bit-sliced state (reactions in
+// table order).  Each reaction's weight is c_j h_j with h_j one of nine
+// kinds: N_X (kind X), the pair counts N_L N_D, N_L N_A, N_D N_A (kinds 3,
+// 4, 5) and N_X (N_X - 1) / 2 (kind 6 + X); d holds the state change.
+constexpr int kGenMaxR = 16;
+struct GenNet {
+    int32_t R;
+    uint32_t used;            // bit k: some reaction has kind k
+    uint32_t change;          // bit j: reaction j changes the state
+    int32_t n_slots;          // LDS slots, one per used kind
+    uint32_t c[kGenMaxR];
+    uint8_t kind[kGenMaxR];
+    uint8_t slot[9];          // LDS slot of each used kind
+    int8_t d[kGenMaxR][3];
+};
+using GenLaunch = hipError_t (*)(const WmArgs &, const GenNet &, hipStream_t);
+struct GenVariant {
+    int nb, bc;
+    GenLaunch fn;
+};
+extern const GenVariant kGenVariants[];
+extern const int kGenVariantCount;
+
 hipError_t launch_plain(const PlainArgs &a, hipStream_t s, int block);
 hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s);
 // Shared thresholds of events [e0, e0 + len) into tab (len uint32).

@@ -156,6 +156,42 @@ static void classify_plain(bwg_net &n)
     n.plain_ok = true;
 }
 
+// Reaction table of the general bit-sliced kernel: the weight kind of each
+// reaction (N_X; N_L N_D, N_L N_A, N_D N_A; N_X (N_X - 1) / 2), its integer
+// weight and state change.
+static void classify_generic(bwg_net &n)
+{
+    n.gen_ok = false;
+    if (n.S != 3 || n.R > bwg::kGenMaxR) return;
+    bwg::GenNet &g = n.gen;
+    g = bwg::GenNet{};
+    g.R = n.R;
+    for (int j = 0; j < n.R; ++j) {
+        const int32_t *r = &n.reac[j * 3], *p = &n.prod[j * 3];
+        int xs[2], k = 0;
+        for (int x = 0; x < 3; ++x)
+            for (int m = 0; m < r[x]; ++m) xs[k++] = x;
+        int kind;
+        if (k == 1)
+            kind = xs[0];
+        else if (xs[0] == xs[1])
+            kind = 6 + xs[0];
+        else
+            kind = xs[0] == 0 ? (xs[1] == 1 ? 3 : 4) : 5;
+        if (n.q.c[j] >= (1ll << 32)) return;
+        g.c[j] = (uint32_t)n.q.c[j];
+        g.kind[j] = (uint8_t)kind;
+        if (g.c[j]) g.used |= 1u << kind;
+        for (int x = 0; x < 3; ++x) {
+            g.d[j][x] = (int8_t)(p[x] - r[x]);
+            if (p[x] != r[x]) g.change |= 1u << j;
+        }
+    }
+    for (int k = 0; k < 9; ++k)
+        if ((g.used >> k) & 1u) g.slot[k] = (uint8_t)g.n_slots++;
+    n.gen_ok = true;
+}
+
 extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
 {
     if (!d || !out) return fail(BWG_EINVAL, "null argument");
@@ -289,7 +325,8 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     q.z_shared = z < (1ll << 32) ? z : 0;
     classify(*n);
     classify_plain(*n);
-    q.gpu_ok = n->shape_ok ? 1 : 0;
+    classify_generic(*n);
+    q.gpu_ok = (n->shape_ok || n->gen_ok) ? 1 : 0;
     *out = n;
     return BWG_OK;
 }
@@ -408,13 +445,38 @@ static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_ca
     return L;
 }
 
-static int check_engine(const bwg_net *n, int engine, const WmVariant **v)
+static const GenVariant *pick_gen_variant(const bwg_net *n)
+{
+    if (!n->gen_ok) return nullptr;
+    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
+    const GenVariant *best = nullptr;
+    for (int i = 0; i < kGenVariantCount; ++i) {
+        const GenVariant &v = kGenVariants[i];
+        if (v.nb < n->q.b || v.bc < need_bc) continue;
+        if (!best || v.nb + v.bc < best->nb + best->bc) best = &v;
+    }
+    return best;
+}
+
+// Kernel of an engine for a network: the Frank-family kernel where it
+// applies (unless generic is asked for), else the general bit-sliced one.
+static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
+                        const GenVariant **gv = nullptr, bool generic = false)
 {
     *v = nullptr;
+    if (gv) *gv = nullptr;
+    if (engine == BWG_ENGINE_BITWISE && (generic || !n->shape_ok)) {
+        const GenVariant *g = pick_gen_variant(n);
+        if (!g)
+            return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for this network (b=%d B=%d)",
+                        n->q.b, n->q.B);
+        if (gv) *gv = g;
+        return BWG_OK;
+    }
     if (engine == BWG_ENGINE_BITWISE || engine == BWG_ENGINE_LANES) {
         if (!n->shape_ok)
             return fail(BWG_EUNSUPPORTED,
-                        "network is not of the Frank family the bit-sliced kernel implements");
+                        "network is not of the Frank family the lanes engine implements");
         *v = pick_variant(n);
         if (!*v)
             return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for b=%d B=%d fa=%d fi=%d",
@@ -438,10 +500,15 @@ extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_
     if (o && (o->block < 0 || o->block > 256 || o->block % 64))
         return fail(BWG_EINVAL, "block %d: the event kernels take 64, 128, 192 or 256 threads",
                     o->block);
+    const bool generic = o && (o->flags & BWG_OPT_GENERIC_KERNEL);
+    if (generic && (n->lat || engine != BWG_ENGINE_BITWISE))
+        return fail(BWG_EUNSUPPORTED, "the general kernel is a well-mixed bit-sliced engine");
     if (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) {
         if (n->lat || engine == BWG_ENGINE_PLAIN)
             return fail(BWG_EUNSUPPORTED,
                         "shared thresholds run on the well-mixed bit-plane engines");
+        if (generic || !n->shape_ok)
+            return fail(BWG_EUNSUPPORTED, "shared thresholds run on Frank-family networks");
         if (!n->q.z_shared)
             return fail(BWG_ERANGE, "shared-threshold range beyond 32 bits");
     }
@@ -451,7 +518,7 @@ extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_
         return lat_state_bytes(n, M, cap, bytes);
     }
     const WmVariant *v;
-    int rc = check_engine(n, engine, &v);
+    int rc = check_engine(n, engine, &v, nullptr, generic);
     if (rc) return rc;
     *bytes = layout(n, M, engine, cap, v).total;
     return BWG_OK;
@@ -488,7 +555,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
         *out = e;
         return BWG_OK;
     }
-    check_engine(n, e->engine, &e->var);
+    check_engine(n, e->engine, &e->var, &e->gvar, o && (o->flags & BWG_OPT_GENERIC_KERNEL));
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
@@ -513,8 +580,8 @@ extern "C" void bwg_ensemble_destroy(bwg_ens *e) { delete e; }
 extern "C" int bwg_ensemble_set_lanes_words(bwg_ens *e, uint64_t n_words)
 {
     if (!e) return fail(BWG_EINVAL, "null ensemble");
-    if (e->lat || e->engine == BWG_ENGINE_PLAIN)
-        return fail(BWG_EINVAL, "only bit-plane well-mixed ensembles split their words");
+    if (e->lat || e->engine == BWG_ENGINE_PLAIN || !e->net->shape_ok)
+        return fail(BWG_EINVAL, "only Frank-family bit-plane ensembles split their words");
     e->lanes_words = n_words;
     return BWG_OK;
 }
@@ -525,6 +592,12 @@ extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)
     if (e->lat) return fail(BWG_EINVAL, "lattices have one engine");
     if (e->engine == BWG_ENGINE_PLAIN || (engine != BWG_ENGINE_BITWISE && engine != BWG_ENGINE_LANES))
         return fail(BWG_EINVAL, "only the bit-sliced and lanes engines share a state layout");
+    if (engine == BWG_ENGINE_LANES && e->gvar)
+        return fail(BWG_EINVAL, "the lanes engine runs Frank-family networks on their own kernel");
+    if (engine == BWG_ENGINE_BITWISE && !e->var && !e->gvar) {
+        e->var = pick_variant(e->net);
+        if (!e->var) return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for this network");
+    }
     e->engine = engine;
     return BWG_OK;
 }
@@ -667,6 +740,8 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         if (rc) return rc;
         if (e->engine == BWG_ENGINE_LANES)
             HIP_TRY(launch_wm_lanes(a, s));
+        else if (e->gvar)
+            HIP_TRY(e->gvar->fn(a, n->gen, s));
         else
             HIP_TRY(e->var->fn(a, s, e->block));
         rc = mark_end(e, s, ev);

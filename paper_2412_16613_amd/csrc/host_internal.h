@@ -45,6 +45,8 @@ struct bwg_net {
     bool shape_ok = false;
     bwg::PlainReaction prx[16]{};
     bool plain_ok = false;
+    bwg::GenNet gen{};      // reaction table of the general bit-sliced kernel
+    bool gen_ok = false;
     // lattice networks
     bool lat = false;
     bwg::LatShape lsh{};
@@ -72,6 +74,7 @@ struct bwg_ens {
     uint64_t wp = 0;
     int nb = 0;
     const bwg::WmVariant *var = nullptr;
+    const bwg::GenVariant *gvar = nullptr;  // general kernel (non-Frank or forced)
     uint32_t *planes = nullptr;
     int32_t *counts = nullptr;
     uint64_t *E = nullptr, *Et = nullptr, *real = nullptr, *table = nullptr, *scratch = nullptr;

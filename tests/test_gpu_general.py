@@ -1,0 +1,86 @@
+"""The general bit-sliced kernel (any 3-species network of order <= 2)
+against the oracle, and against the Frank kernel on Frank networks."""
+
+import numpy as np
+import pytest
+
+import paper_2412_16613_amd as bwg
+from oracle import ssa
+from workloads import frank_network, paper_network, random_network
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _group_sums(x, M):
+    out = np.zeros((M + 31) // 32, dtype=np.uint64)
+    np.add.at(out, np.arange(M) // 32, x.astype(np.uint64))
+    return out
+
+
+def _check(torch, net, M, init, sched, seed, net_id, generic=False, epl=0):
+    print("case", net["n_tot"], len(net["rates"]), M, init, sched, seed, generic, epl, flush=True)
+    e = bwg.Ensemble(bwg.Network(net), M, seed=seed, net_id=net_id, generic=generic,
+                     events_per_launch=epl)
+    e.init(init)
+    o = ssa.OracleEnsemble(net, M, seed=seed, net_id=net_id)
+    o.init(init)
+    for op, v in sched:
+        getattr(e, op)(v)
+        getattr(o, op)(v)
+    ev, real = e.read_events()
+    np.testing.assert_array_equal(e.read_counts().cpu().numpy(), o.counts)
+    np.testing.assert_array_equal(ev.cpu().numpy().astype(np.uint64), o.E)
+    np.testing.assert_array_equal(real.cpu().numpy().astype(np.uint64), _group_sums(o.real, M))
+    return e
+
+
+@pytest.mark.parametrize("seed,n_tot,R,M", [
+    (0, 12, 3, 100), (1, 50, 7, 1000), (2, 200, 12, 333), (3, 12, 16, 65),
+    (4, 30, 5, 2048 + 7), (5, 100, 9, 31), (6, 7, 4, 500), (7, 300, 6, 257), (8, 400, 5, 1024),
+])
+def test_random_networks_match_oracle(torch, seed, n_tot, R, M):
+    net = random_network(seed, n_tot, R)
+    q = bwg.Network(net).quantized()
+    mu_t = 400.0 / q["Lambda"]                # about 400 events per replica
+    _check(torch, net, M, ("multinomial",), [("advance", mu_t), ("step", 123)], seed=seed,
+           net_id=seed + 10)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_random_integer_networks_match_oracle(torch, seed):
+    net = random_network(seed, 40, 8, exact_integer=True)
+    _check(torch, net, 700, ("multinomial",), [("step", 1500)], seed=seed, net_id=3, epl=400)
+
+
+@pytest.mark.parametrize("net", [frank_network(32), frank_network(1024), paper_network(64)])
+def test_general_kernel_equals_frank_kernel(torch, net):
+    """Frank networks asked onto the general kernel give the Frank kernel's
+    results (and the oracle's)."""
+    M = 1500
+    sched = [("advance", 300.0 / bwg.Network(net).quantized()["Lambda"]), ("step", 50)]
+    init = ("multinomial",)
+    g = _check(torch, net, M, init, sched, seed=4, net_id=2, generic=True)
+    f = bwg.Ensemble(bwg.Network(net), M, seed=4, net_id=2)
+    f.init(init)
+    for op, v in sched:
+        getattr(f, op)(v)
+    np.testing.assert_array_equal(g.read_counts().cpu().numpy(), f.read_counts().cpu().numpy())
+
+
+def test_general_kernel_refusals(torch):
+    net = random_network(0, 12, 3)
+    e = bwg.Ensemble(bwg.Network(net), 64)
+    e.init(("multinomial",))
+    with pytest.raises(bwg.BwgError):
+        e.set_engine("lanes")
+    with pytest.raises(bwg.BwgError):
+        bwg.Batch([e])
+    with pytest.raises(bwg.BwgError):
+        bwg.Ensemble(bwg.Network(net), 64, shared_threshold=True)

@@ -108,23 +108,43 @@ def test_invalid_networks_are_rejected():
     assert e.value.code == _abi.BWG_ERANGE
 
 
-def test_non_frank_order_is_plain_only():
+def test_non_frank_networks_take_the_general_kernel():
+    """A network outside the Frank family (here its reactions reordered) runs
+    on the general bit-sliced kernel and the plain engine, not on the lanes
+    engine, shared thresholds or in batches."""
+    import ctypes
     net = frank_network(16)
     order = [2, 0, 1, 3, 4]
     net["reactants"] = [net["reactants"][i] for i in order]
     net["products"] = [net["products"][i] for i in order]
     net["rates"] = [net["rates"][i] for i in order]
     n = bwg.Network(net)
-    assert not n.quantized()["gpu_ok"]
-    import ctypes
-    nbytes = ctypes.c_uint64()
+    assert n.quantized()["gpu_ok"]
+    L = _abi.load()
+
+    def rc(**kw):
+        o = _abi.Opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        nbytes = ctypes.c_uint64()
+        r = L.bwg_ensemble_state_bytes(n.handle, 1024, ctypes.byref(o), ctypes.byref(nbytes))
+        return r, nbytes.value
+
+    assert rc(engine=_abi.BWG_ENGINE_BITWISE)[0] == _abi.BWG_OK
+    assert rc(engine=_abi.BWG_ENGINE_LANES)[0] == _abi.BWG_EUNSUPPORTED
+    assert rc(engine=_abi.BWG_ENGINE_BITWISE,
+              flags=_abi.BWG_OPT_SHARED_THRESHOLD)[0] == _abi.BWG_EUNSUPPORTED
+    r, nb = rc(engine=_abi.BWG_ENGINE_PLAIN)
+    assert r == 0 and nb > 1024 * 3 * 4
+    # a Frank-family network may ask for the general kernel
+    f = bwg.Network(frank_network(16))
     o = _abi.Opts()
-    o.engine = _abi.BWG_ENGINE_BITWISE
-    rc = _abi.load().bwg_ensemble_state_bytes(n.handle, 1024, ctypes.byref(o), ctypes.byref(nbytes))
-    assert rc == _abi.BWG_EUNSUPPORTED
-    o.engine = _abi.BWG_ENGINE_PLAIN
-    rc = _abi.load().bwg_ensemble_state_bytes(n.handle, 1024, ctypes.byref(o), ctypes.byref(nbytes))
-    assert rc == 0 and nbytes.value > 1024 * 3 * 4
+    o.flags = _abi.BWG_OPT_GENERIC_KERNEL
+    nbytes = ctypes.c_uint64()
+    assert L.bwg_ensemble_state_bytes(f.handle, 64, ctypes.byref(o), ctypes.byref(nbytes)) == 0
+    o.engine = _abi.BWG_ENGINE_LANES
+    assert (L.bwg_ensemble_state_bytes(f.handle, 64, ctypes.byref(o), ctypes.byref(nbytes))
+            == _abi.BWG_EUNSUPPORTED)
 
 
 def test_state_bytes_scale_with_replicas():

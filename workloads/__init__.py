@@ -16,3 +16,4 @@ from .frank import (  # noqa: F401
     batch_networks,
     serve_requests,
 )
+from .general import random_network  # noqa: F401
