@@ -189,130 +189,6 @@ __device__ __forceinline__ void philox_planes(uint32_t (&n)[BC], uint64_t e, uin
     }
 }
 
-// One event of a word given its threshold planes n (consumed): selection
-// (b)-(d), occupancy update (e) and product update (f) for the lanes in act.
-template <int NB, int BC, int FA, int CU, int WP, int WD>
-__device__ __forceinline__ void word_event(const WmArgs &a, uint32_t (&n)[BC], uint32_t act,
-                                           uint32_t cu, bool has_a, bool has_i,
-                                           uint32_t (&L)[NB], uint32_t (&D)[NB],
-                                           uint32_t (&A)[NB], uint32_t (&PAL)[WP],
-                                           uint32_t (&PAD)[WP], uint32_t (&PLD)[WP],
-                                           uint32_t (&U)[BC], uint64_t &nreal)
-{
-    // (b)-(d) cumulative weights and first crossing
-    uint32_t br = 0;
-#pragma unroll
-    for (int q = 0; q < BC; ++q) br = BWG_OP3(n[q], U[q], br, L_BORROW);
-    const uint32_t lt1 = br;  // n < U
-    br = 0;                   // n -= 2U (in place)
-#pragma unroll
-    for (int q = 1; q < BC; ++q) {
-        const uint32_t v = U[q - 1];
-        const uint32_t nb = BWG_OP3(n[q], v, br, L_BORROW);
-        n[q] = BWG_OP3(n[q], v, br, L_XOR3);
-        br = nb;
-    }
-    const uint32_t lt2 = br;  // n < 2U
-    uint32_t lt3 = lt2, lt4 = lt2, lt5;
-    if (has_a) {
-        lt3 = lt2 | sub_w<FA, BC, WP, true>(a.fa, n, PAL);
-        lt4 = lt3 | sub_w<FA, BC, WP, true>(a.fa, n, PAD);
-    }
-    lt5 = lt4;
-    if (has_i) lt5 = lt4 | sub_w<FA, BC, WP, false>(a.fi, n, PLD);
-
-    const uint32_t mL = (lt1 | (lt3 & ~lt2)) & act;
-    const uint32_t mD = ((lt2 & ~lt1) | (lt4 & ~lt3)) & act;
-    const uint32_t mI = (lt5 & ~lt4) & act;
-    const uint32_t mLD = mL | mD;
-    nreal += (uint32_t)__builtin_popcount(mLD | mI);
-
-    // (e) occupancies: keep the pre-event values for the products
-    uint32_t L2[NB], D2[NB], A2[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        L2[q] = L[q];
-        D2[q] = D[q];
-        A2[q] = A[q];
-    }
-    add_pm1<NB>(L2, mL, mI);
-    add_pm1<NB>(D2, mD, mI);
-    add_m1_p2<NB>(A2, mLD, mI);
-
-    // (f) products: P_AX += dA * X' + dX * A;  P_LD += dL * D' + dD * L
-    {
-        uint32_t t[WD];
-        const uint32_t mLI = mL | mI, mDI = mD | mI;
-        // P_AL
-        {
-            uint32_t c = mLD;
-#pragma unroll
-            for (int q = 0; q < WD; ++q) {
-                const uint32_t xq = q < NB ? L2[q] : 0u;
-                const uint32_t xm = (q >= 1 && q - 1 < NB) ? L2[q - 1] : 0u;
-                const uint32_t t1 = BWG_OP3(mI, xm, BWG_OP3(mLD, xq, 0u, L_ANDNOT), L_ANDOR);
-                const uint32_t t2 = q < NB ? BWG_OP3(A[q], mLI, mI, L_ANDXOR) : mI;
-                t[q] = BWG_OP3(t1, t2, c, L_XOR3);
-                c = BWG_OP3(t1, t2, c, L_MAJ);
-            }
-            add_sext<WP, WD>(PAL, t, mI);
-        }
-        // P_AD
-        {
-            uint32_t c = mLD;
-#pragma unroll
-            for (int q = 0; q < WD; ++q) {
-                const uint32_t xq = q < NB ? D2[q] : 0u;
-                const uint32_t xm = (q >= 1 && q - 1 < NB) ? D2[q - 1] : 0u;
-                const uint32_t t1 = BWG_OP3(mI, xm, BWG_OP3(mLD, xq, 0u, L_ANDNOT), L_ANDOR);
-                const uint32_t t2 = q < NB ? BWG_OP3(A[q], mDI, mI, L_ANDXOR) : mI;
-                t[q] = BWG_OP3(t1, t2, c, L_XOR3);
-                c = BWG_OP3(t1, t2, c, L_MAJ);
-            }
-            add_sext<WP, WD>(PAD, t, mI);
-        }
-        // P_LD
-        {
-            uint32_t c = mI;
-#pragma unroll
-            for (int q = 0; q < WD; ++q) {
-                const uint32_t t1 = q < NB ? BWG_OP3(D2[q], mLI, mI, L_ANDXOR) : mI;
-                const uint32_t t2 = q < NB ? BWG_OP3(L[q], mDI, mI, L_ANDXOR) : mI;
-                t[q] = BWG_OP3(t1, t2, c, L_XOR3);
-                c = BWG_OP3(t1, t2, c, L_MAJ);
-            }
-            add_sext<WP, WD>(PLD, t, mI);
-        }
-    }
-    // U += cu * dA with dA = -1 on mLD, +2 on mI: addend planes are the
-    // bits of -cu (two's complement, the +1 as carry-in) on mLD and of
-    // 2 cu on mI
-    if (cu) {
-        uint32_t c = mLD;
-#pragma unroll
-        for (int q = 0; q < BC; ++q) {
-            uint32_t v;
-            if constexpr (CU >= 0) {
-                constexpr uint32_t ncu = ~(uint32_t)CU, dcu = 2u * (uint32_t)CU;
-                const bool bn = (ncu >> q) & 1u, bd = (dcu >> q) & 1u;
-                v = bn ? (bd ? (mLD | mI) : mLD) : (bd ? mI : 0u);
-            } else {
-                const uint32_t neg = ((cu >> q) & 1u) ? 0u : mLD;
-                const uint32_t dbl = (q >= 1 && ((cu >> (q - 1)) & 1u)) ? mI : 0u;
-                v = neg | dbl;
-            }
-            const uint32_t s = BWG_OP3(U[q], v, c, L_XOR3);
-            if (q + 1 < BC) c = BWG_OP3(U[q], v, c, L_MAJ);
-            U[q] = s;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        L[q] = L2[q];
-        D[q] = D2[q];
-        A[q] = A2[q];
-    }
-}
 
 // Occupancies and per-replica event counts back to memory after a launch
 // that ran the word's events up to hi.
@@ -398,8 +274,7 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
             } else {
                 philox_planes<BC>(n, e, G, a.net_id, k0, k1, nq, lastm);
             }
-            word_event<NB, BC, FA, CU, WP, WD>(a, n, act, cu, has_a, has_i, L, D, A, PAL, PAD,
-                                               PLD, U, nreal);
+#include "wm_event_body.inc"
         }
         a.real[w] += nreal;
     }
@@ -513,8 +388,7 @@ __device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4
                         n[4 * q4 + 2] = v.z;
                         n[4 * q4 + 3] = v.w;
                     }
-                    word_event<NB, BC, FA, CU, WP, WD>(a, n, act, cu, has_a, has_i, L, D, A, PAL,
-                                                       PAD, PLD, U, nreal);
+#include "wm_event_body.inc"
                 }
             }
         }
