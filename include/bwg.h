@@ -170,6 +170,14 @@ typedef struct {
  * per event.  Bit-sliced engine on well-mixed networks only (EUNSUPPORTED
  * otherwise), not with BWG_OPT_SHARED_THRESHOLD. */
 #define BWG_OPT_GENERIC_KERNEL 4u
+/* Networks on the general path run, by default, a kernel compiled at run
+ * time (hipRTC) for their own reaction table on the first ensemble created:
+ * weight kinds in registers, one compile-time shifted subtraction per set bit
+ * of each c_j, trailing reactions that change nothing left out; same results
+ * as the precompiled general kernel.  Creation fails with EDEVICE (and the
+ * compiler's log in bwg_last_error) if that compile fails.  This flag keeps
+ * the precompiled general kernel instead. */
+#define BWG_OPT_NO_JIT 8u
 
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */

@@ -102,7 +102,7 @@ class Ensemble:
 
     def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
                  device="cuda", events_per_launch=0, table_capacity=0, block=0,
-                 time_kernels=False, shared_threshold=False, generic=False):
+                 time_kernels=False, shared_threshold=False, generic=False, jit=True):
         import torch
         self.torch = torch
         L = _lib()
@@ -116,7 +116,8 @@ class Ensemble:
         o.events_per_launch = events_per_launch
         o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
                    (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0) |
-                   (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0))
+                   (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0) |
+                   (0 if jit else _abi.BWG_OPT_NO_JIT))
         self._opts = o
         nbytes = ctypes.c_uint64()
         _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),

@@ -28,6 +28,7 @@ BWG_INIT_SITES = 3
 BWG_OPT_TIME_KERNELS = 1
 BWG_OPT_SHARED_THRESHOLD = 2
 BWG_OPT_GENERIC_KERNEL = 4
+BWG_OPT_NO_JIT = 8
 
 # Every symbol include/bwg.h declares.
 SYMBOLS = (

@@ -556,6 +556,13 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
         return BWG_OK;
     }
     check_engine(n, e->engine, &e->var, &e->gvar, o && (o->flags & BWG_OPT_GENERIC_KERNEL));
+    if (e->gvar && !(o && (o->flags & BWG_OPT_NO_JIT))) {
+        rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
+        if (rc) {
+            delete e;
+            return rc;
+        }
+    }
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
@@ -740,6 +747,8 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         if (rc) return rc;
         if (e->engine == BWG_ENGINE_LANES)
             HIP_TRY(launch_wm_lanes(a, s));
+        else if (e->jit)
+            HIP_TRY(jit_launch(e->jit, a, s));
         else if (e->gvar)
             HIP_TRY(e->gvar->fn(a, n->gen, s));
         else

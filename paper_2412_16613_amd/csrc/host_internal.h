@@ -24,6 +24,11 @@ int fail(int code, const char *fmt, ...);
             return ::bwg::fail(BWG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
     } while (0)
 
+// A bit-sliced kernel compiled at run time for one network (jit_host.cpp).
+struct JitKernel;
+void jit_release(JitKernel *k);
+hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s);
+
 }  // namespace bwg
 
 struct Table {  // Poisson table of one mean
@@ -56,10 +61,12 @@ struct bwg_net {
     bool lat_gpu = false;       // the event kernel implements this table
     std::mutex mu;
     std::map<uint64_t, Table> tables;  // keyed by the bits of mu
+    bwg::JitKernel *jit = nullptr;     // compiled on the first ensemble that needs it
     ~bwg_net()
     {
         for (auto &kv : tables)
             if (kv.second.host) (void)hipHostFree(kv.second.host);
+        bwg::jit_release(jit);
     }
 };
 
@@ -75,6 +82,7 @@ struct bwg_ens {
     int nb = 0;
     const bwg::WmVariant *var = nullptr;
     const bwg::GenVariant *gvar = nullptr;  // general kernel (non-Frank or forced)
+    const bwg::JitKernel *jit = nullptr;    // its per-network compiled form, if used
     uint32_t *planes = nullptr;
     int32_t *counts = nullptr;
     uint64_t *E = nullptr, *Et = nullptr, *real = nullptr, *table = nullptr, *scratch = nullptr;
@@ -117,6 +125,8 @@ namespace bwg {
 // Cached Poisson table for mean mu (lives as long as the network); with
 // pinned, also its pinned copy for uploads to the device.
 int get_table(bwg_net *n, double mu, const Table **out, bool pinned = true);
+// The network's run-time compiled kernel (compiled on the first call).
+int jit_get(bwg_net *n, const JitKernel **out);
 // Budgets of one advance to t_end (no event launches); *kmin/*kmax bound K.
 int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, uint64_t *kmax);
 // Bookkeeping after budgets with K in [kmin, kmax] were drawn.

@@ -1,0 +1,207 @@
+// Per-network bit-sliced kernels compiled at run time with hipRTC.
+//
+// The general kernel (generic.hip) takes the reaction table as data, so it
+// forms every weight kind in LDS and multiplies by each weight c_j bit by
+// bit behind a run-time shift switch.  For a given network all of that is
+// known before the first launch; this file writes the event loop of that
+// network as source (weight kinds in registers, one compile-time shifted
+// subtraction per set bit of c_j, the state change of each reaction as
+// fixed mask updates, trailing reactions that change nothing left out since
+// they cannot change which earlier reaction a lane selects) on top of the
+// same device headers, compiles it once per network and launches it through
+// the module API.  It draws the same thresholds and computes the same first
+// crossing as the general kernel, so results are identical.
+
+#include <hip/hiprtc.h>
+
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "host_internal.h"
+
+namespace bwg {
+
+extern const int kJitHeaderCount;
+extern const char *const kJitHeaderNames[];
+extern const char *const kJitHeaders[];
+
+struct JitKernel {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+};
+
+void jit_release(JitKernel *k)
+{
+    if (!k) return;
+    if (k->mod) (void)hipModuleUnload(k->mod);
+    delete k;
+}
+
+constexpr int kJitBlock = 128;  // threads per block of the compiled kernels
+
+// Event loop of network n with NB count planes and BC threshold planes.
+static std::string jit_source(const bwg_net &n, int NB, int BC)
+{
+    const GenNet &g = n.gen;
+    static const char *const kPair[3][2] = {{"N0", "N1"}, {"N0", "N2"}, {"N1", "N2"}};
+    // reactions that matter: up to the last one that changes the state
+    int R = g.R;
+    while (R > 0 && !((g.change >> (R - 1)) & 1u)) --R;
+    uint32_t used = 0;
+    for (int j = 0; j < R; ++j)
+        if (g.c[j]) used |= 1u << g.kind[j];
+    int last_j = -1, last_bit = -1;  // the final subtraction need not keep d
+    for (int j = 0; j < R; ++j)
+        if (g.c[j]) {
+            last_j = j;
+            last_bit = 31 - __builtin_clz(g.c[j]);
+        }
+    std::ostringstream o;
+    o << "#include \"gen_device.h\"\n"
+      << "namespace bwg {\n"
+      << "extern \"C\" __global__ __launch_bounds__(" << kJitBlock
+      << ") void bwg_jit_word(WmArgs a)\n{\n"
+      << "    constexpr int NB = " << NB << ", BC = " << BC << ", WH = 2 * NB;\n"
+      << "    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;\n"
+      << "    if (w >= a.n_words) return;\n"
+      << "    const uint32_t live = live_lanes(a, w);\n"
+      << "    const uint64_t *E = a.E + 32 * w;\n"
+      << "    const uint64_t *T = a.Etgt + 32 * w;\n"
+      << "    const WordWindow win = word_window(a, E, T, live);\n"
+      << "    uint32_t N0[NB], N1[NB], N2[NB];\n"
+      << "    load_word<NB>(a, w, N0, N1, N2);\n"
+      << "    if (win.lo < win.hi) {\n"
+      << "        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);\n"
+      << "        const int nq = (a.B + 3) / 4;\n"
+      << "        uint32_t lastm[4];\n"
+      << "#pragma unroll\n"
+      << "        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;\n"
+      << "        uint64_t nreal = 0;\n"
+      << "        for (uint64_t e = win.lo; e < win.hi; ++e) {\n"
+      << "            const uint32_t act =\n"
+      << "                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);\n"
+      << "            uint32_t d[BC];\n"
+      << "            philox_planes<BC>(d, e, (uint32_t)w, a.net_id, k0, k1, nq, lastm);\n";
+    // weight kinds
+    for (int k = 3; k < 9; ++k) {
+        if (!((used >> k) & 1u)) continue;
+        if (k < 6) {
+            o << "            uint32_t h" << k << "[WH];\n"
+              << "            mul_planes<NB, WH>(h" << k << ", " << kPair[k - 3][0] << ", "
+              << kPair[k - 3][1] << ");\n";
+        } else {
+            const int x = k - 6;
+            o << "            uint32_t h" << k << "[WH];\n"
+              << "            {\n"
+              << "                uint32_t xm[NB], p[WH];\n"
+              << "#pragma unroll\n"
+              << "                for (int q = 0; q < NB; ++q) xm[q] = N" << x << "[q];\n"
+              << "                add_pm1<NB>(xm, 0u, ~0u);\n"
+              << "                mul_planes<NB, WH>(p, N" << x << ", xm);\n"
+              << "#pragma unroll\n"
+              << "                for (int q = 0; q < WH; ++q) h" << k
+              << "[q] = q + 1 < WH ? p[q + 1] : 0u;\n"
+              << "            }\n";
+        }
+    }
+    o << "            uint32_t lt = 0, realm = 0;\n"
+      << "            uint32_t mk[3][4] = {};\n";
+    static const int kSlot[5] = {3, 1, -1, 0, 2};  // delta -2..2 -> mask index
+    for (int j = 0; j < R; ++j) {
+        if (!g.c[j]) continue;  // weight 0: never selected
+        const int k = g.kind[j];
+        const std::string op = k < 3 ? ("N" + std::to_string(k)) : ("h" + std::to_string(k));
+        const char *wp = k < 3 ? "NB" : "WH";
+        o << "            {  // reaction " << j << "\n"
+          << "                uint32_t br = 0;\n";
+        for (int b = 0; b < 32; ++b) {
+            if (!((g.c[j] >> b) & 1u)) continue;
+            const bool keep = !(j == last_j && b == last_bit);
+            o << "                br |= sub_shifted<" << b << ", BC, " << wp << ", "
+              << (keep ? "true" : "false") << ">(d, " << op << ");\n";
+        }
+        o << "                const uint32_t ltj = lt | br;\n"
+          << "                const uint32_t xi = ltj & ~lt & act;\n"
+          << "                lt = ltj;\n";
+        if ((g.change >> j) & 1u) o << "                realm |= xi;\n";
+        for (int x = 0; x < 3; ++x) {
+            const int dv = g.d[j][x];
+            if (dv) o << "                mk[" << x << "][" << kSlot[dv + 2] << "] |= xi;\n";
+        }
+        o << "            }\n";
+    }
+    o << "            nreal += (uint32_t)__builtin_popcount(realm);\n";
+    for (int x = 0; x < 3; ++x) {
+        bool any = false;
+        for (int j = 0; j < R; ++j) any |= g.c[j] && g.d[j][x];
+        if (any)
+            o << "            add_delta<NB>(N" << x << ", mk[" << x << "][0], mk[" << x
+              << "][1], mk[" << x << "][2], mk[" << x << "][3]);\n";
+    }
+    o << "        }\n"
+      << "        a.real[w] += nreal;\n"
+      << "    }\n"
+      << "    store_word<NB>(a, w, live, win.hi, N0, N1, N2);\n"
+      << "}\n"
+      << "}  // namespace bwg\n";
+    return o.str();
+}
+
+// The compiled kernel of network n, built on the first call (under the
+// network's lock).
+int jit_get(bwg_net *n, const JitKernel **out)
+{
+    std::lock_guard<std::mutex> lock(n->mu);
+    if (n->jit) {
+        *out = n->jit;
+        return BWG_OK;
+    }
+    if (!n->gen_ok) return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
+    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
+    const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
+    if (BC > 32 || NB > 14) return fail(BWG_EUNSUPPORTED, "network beyond 14 count / 32 threshold planes");
+    const std::string src = jit_source(*n, NB, BC);
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "bwg_jit_word.hip", kJitHeaderCount, kJitHeaders,
+                            kJitHeaderNames) != HIPRTC_SUCCESS)
+        return fail(BWG_EDEVICE, "hiprtcCreateProgram failed");
+    // no packed-fp32 instructions in device code, as for the precompiled kernels
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang",
+                          "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, 7, opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(BWG_EDEVICE, "run-time compile of the network's kernel failed: %.400s",
+                    log.c_str());
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    auto k = new JitKernel();
+    hipError_t e = hipModuleLoadData(&k->mod, code.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "bwg_jit_word");
+    if (e != hipSuccess) {
+        jit_release(k);
+        return fail(BWG_EDEVICE, "loading the network's kernel: %s", hipGetErrorString(e));
+    }
+    n->jit = k;
+    *out = k;
+    return BWG_OK;
+}
+
+hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s)
+{
+    WmArgs arg = a;
+    void *params[] = {&arg};
+    const unsigned grid = (unsigned)((a.n_words + kJitBlock - 1) / kJitBlock);
+    return hipModuleLaunchKernel(k->fn, grid, 1, 1, kJitBlock, 1, 1, 0, s, params, nullptr);
+}
+
+}  // namespace bwg

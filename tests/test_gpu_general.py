@@ -1,5 +1,6 @@
-"""The general bit-sliced kernel (any 3-species network of order <= 2)
-against the oracle, and against the Frank kernel on Frank networks."""
+"""The general bit-sliced kernels (any 3-species network of order <= 2): the
+per-network kernel compiled at run time and the precompiled one, against
+the oracle, and against the Frank kernel on Frank networks."""
 
 import numpy as np
 import pytest
@@ -24,10 +25,11 @@ def _group_sums(x, M):
     return out
 
 
-def _check(torch, net, M, init, sched, seed, net_id, generic=False, epl=0):
-    print("case", net["n_tot"], len(net["rates"]), M, init, sched, seed, generic, epl, flush=True)
+def _check(torch, net, M, init, sched, seed, net_id, generic=False, epl=0, jit=True):
+    print("case", net["n_tot"], len(net["rates"]), M, init, sched, seed, generic, epl, jit,
+          flush=True)
     e = bwg.Ensemble(bwg.Network(net), M, seed=seed, net_id=net_id, generic=generic,
-                     events_per_launch=epl)
+                     events_per_launch=epl, jit=jit)
     e.init(init)
     o = ssa.OracleEnsemble(net, M, seed=seed, net_id=net_id)
     o.init(init)
@@ -45,12 +47,13 @@ def _check(torch, net, M, init, sched, seed, net_id, generic=False, epl=0):
     (0, 12, 3, 100), (1, 50, 7, 1000), (2, 200, 12, 333), (3, 12, 16, 65),
     (4, 30, 5, 2048 + 7), (5, 100, 9, 31), (6, 7, 4, 500), (7, 300, 6, 257), (8, 400, 5, 1024),
 ])
-def test_random_networks_match_oracle(torch, seed, n_tot, R, M):
+@pytest.mark.parametrize("jit", [True, False])
+def test_random_networks_match_oracle(torch, seed, n_tot, R, M, jit):
     net = random_network(seed, n_tot, R)
     q = bwg.Network(net).quantized()
     mu_t = 400.0 / q["Lambda"]                # about 400 events per replica
     _check(torch, net, M, ("multinomial",), [("advance", mu_t), ("step", 123)], seed=seed,
-           net_id=seed + 10)
+           net_id=seed + 10, jit=jit)
 
 
 @pytest.mark.parametrize("seed", [11, 12, 13])
@@ -59,14 +62,27 @@ def test_random_integer_networks_match_oracle(torch, seed):
     _check(torch, net, 700, ("multinomial",), [("step", 1500)], seed=seed, net_id=3, epl=400)
 
 
+def test_one_compile_per_network(torch):
+    """Ensembles of one network share its compiled kernel; equal results."""
+    net = random_network(21, 60, 6)
+    n = bwg.Network(net)
+    a = bwg.Ensemble(n, 999, seed=2)
+    b = bwg.Ensemble(n, 999, seed=2)
+    for e in (a, b):
+        e.init(("multinomial",)).step(700)
+    np.testing.assert_array_equal(a.read_counts().cpu().numpy(), b.read_counts().cpu().numpy())
+
+
+@pytest.mark.parametrize("jit", [True, False])
 @pytest.mark.parametrize("net", [frank_network(32), frank_network(1024), paper_network(64)])
-def test_general_kernel_equals_frank_kernel(torch, net):
-    """Frank networks asked onto the general kernel give the Frank kernel's
-    results (and the oracle's)."""
+def test_general_kernel_equals_frank_kernel(torch, net, jit):
+    """Frank networks asked onto the general kernels give the Frank kernel's
+    results (and the oracle's); the paper's network has trailing ghosts the
+    run-time compiled kernel leaves out."""
     M = 1500
     sched = [("advance", 300.0 / bwg.Network(net).quantized()["Lambda"]), ("step", 50)]
     init = ("multinomial",)
-    g = _check(torch, net, M, init, sched, seed=4, net_id=2, generic=True)
+    g = _check(torch, net, M, init, sched, seed=4, net_id=2, generic=True, jit=jit)
     f = bwg.Ensemble(bwg.Network(net), M, seed=4, net_id=2)
     f.init(init)
     for op, v in sched:
