@@ -23,4 +23,128 @@ __device__ __forceinline__ void add_delta(uint32_t (&x)[NB], uint32_t p1, uint32
     }
 }
 
+// Word loops of the per-network kernels: the event itself is a functor
+// ev(d, act, N, nreal) that takes the threshold planes d (consumed), the
+// active lanes and the counts N[species][plane], and adds its real lanes to
+// nreal.  gen_word: one thread per word, as wm_word.
+template <int NB, int BC, typename Event>
+__device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, const Event &ev)
+{
+    if (w >= a.n_words) return;
+    const uint32_t live = live_lanes(a, w);
+    const uint64_t *E = a.E + 32 * w;
+    const uint64_t *T = a.Etgt + 32 * w;
+    const WordWindow win = word_window(a, E, T, live);
+    uint32_t N[3][NB];
+    load_word<NB>(a, w, N[0], N[1], N[2]);
+    if (win.lo < win.hi) {
+        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+        const int nq = (a.B + 3) / 4;
+        uint32_t lastm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
+        uint64_t nreal = 0;
+        for (uint64_t e = win.lo; e < win.hi; ++e) {
+            const uint32_t act =
+                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+            uint32_t d[BC];
+            philox_planes<BC>(d, e, (uint32_t)w, a.net_id, k0, k1, nq, lastm);
+            ev(d, act, N, nreal);
+        }
+        a.real[w] += nreal;
+    }
+    store_word<NB>(a, w, live, win.hi, N[0], N[1], N[2]);
+}
+
+// gen_word_pc: the producer/consumer form of wm_word_pc (four waves per 128
+// words, Philox planes handed over through rings of 2 x PH events in LDS, a
+// barrier per PH events, the workgroup's largest window as step count).
+template <int NB, int BC, int PH, typename Event>
+__device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4][64],
+                                            uint64_t *wave_span, const Event &ev)
+{
+    const int lane = threadIdx.x & 63;
+    const int grp = (threadIdx.x >> 6) & 1;
+    const bool producer = threadIdx.x < 128;
+    ring += grp * 2 * PH;
+    const uint64_t w = (uint64_t)blockIdx.x * 128 + grp * 64 + lane;
+    const bool valid = w < a.n_words;
+    const uint32_t live = valid ? live_lanes(a, w) : 0u;
+    const uint64_t *E = a.E + 32 * (valid ? w : 0);
+    const uint64_t *T = a.Etgt + 32 * (valid ? w : 0);
+    const WordWindow win = word_window(a, E, T, live);
+    const uint64_t lo = win.lo, hi = win.hi;
+    {
+        const uint64_t m = wave_max_u64(hi - lo);
+        if (lane == 0) wave_span[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    uint64_t span = wave_span[0];
+    for (int i = 1; i < 4; ++i) span = wave_span[i] > span ? wave_span[i] : span;
+    const uint64_t nsteps = (span + PH - 1) / PH;
+    const int nq = (a.B + 3) / 4;
+
+    if (producer) {
+        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+        uint32_t lastm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
+        for (uint64_t s = 0; s <= nsteps; ++s) {
+            if (s < nsteps) {
+                const int half = (int)(s & 1) * PH;
+                for (int j = 0; j < PH; ++j) {
+                    const uint64_t e = lo + s * PH + j;
+                    if (e < hi) {
+                        uint32_t n[BC];
+                        philox_planes<BC>(n, e, (uint32_t)w, a.net_id, k0, k1, nq, lastm);
+#pragma unroll
+                        for (int q4 = 0; q4 < BC / 4; ++q4)
+                            if (q4 < nq)
+                                ring[half + j][q4][lane] =
+                                    make_uint4(n[4 * q4], n[4 * q4 + 1], n[4 * q4 + 2], n[4 * q4 + 3]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    uint32_t N[3][NB];
+    if (valid) {
+        load_word<NB>(a, w, N[0], N[1], N[2]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) N[0][q] = N[1][q] = N[2][q] = 0u;
+    }
+    uint64_t nreal = 0;
+    for (uint64_t s = 0; s <= nsteps; ++s) {
+        if (s >= 1) {
+            const int half = (int)((s - 1) & 1) * PH;
+            for (int j = 0; j < PH; ++j) {
+                const uint64_t e = lo + (s - 1) * PH + j;
+                if (e < hi) {
+                    const uint32_t act =
+                        (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+                    uint32_t d[BC];
+#pragma unroll
+                    for (int q4 = 0; q4 < BC / 4; ++q4) {
+                        const uint4 v = q4 < nq ? ring[half + j][q4][lane] : make_uint4(0, 0, 0, 0);
+                        d[4 * q4 + 0] = v.x;
+                        d[4 * q4 + 1] = v.y;
+                        d[4 * q4 + 2] = v.z;
+                        d[4 * q4 + 3] = v.w;
+                    }
+                    ev(d, act, N, nreal);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        if (lo < hi) a.real[w] += nreal;
+        store_word<NB>(a, w, live, hi, N[0], N[1], N[2]);
+    }
+}
+
 }  // namespace bwg

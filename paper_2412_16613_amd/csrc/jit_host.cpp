@@ -8,8 +8,9 @@
 // subtraction per set bit of c_j, the state change of each reaction as
 // fixed mask updates, trailing reactions that change nothing left out since
 // they cannot change which earlier reaction a lane selects) on top of the
-// same device headers, compiles it once per network and launches it through
-// the module API.  It draws the same thresholds and computes the same first
+// same device headers (in the one-wave-per-word and the producer/consumer
+// forms), compiles it once per network and launches it through the module
+// API.  It draws the same thresholds and computes the same first
 // crossing as the general kernel, so results are identical.
 
 #include <hip/hiprtc.h>
@@ -28,7 +29,8 @@ extern const char *const kJitHeaders[];
 
 struct JitKernel {
     hipModule_t mod = nullptr;
-    hipFunction_t fn = nullptr;
+    hipFunction_t fn = nullptr;  // one thread per word
+    hipFunction_t pc = nullptr;  // producer/consumer form
 };
 
 void jit_release(JitKernel *k)
@@ -38,13 +40,16 @@ void jit_release(JitKernel *k)
     delete k;
 }
 
-constexpr int kJitBlock = 128;  // threads per block of the compiled kernels
+constexpr int kJitBlock = 128;  // threads per block of the one-wave-per-word kernel
+constexpr int kJitPcHalf = 4;   // events per ring half of the producer/consumer kernel
 
-// Event loop of network n with NB count planes and BC threshold planes.
+// Source of network n's kernels with NB count planes and BC threshold planes:
+// an event functor (weight kinds, selection, state change) and the two word
+// loops of gen_device.h around it.
 static std::string jit_source(const bwg_net &n, int NB, int BC)
 {
     const GenNet &g = n.gen;
-    static const char *const kPair[3][2] = {{"N0", "N1"}, {"N0", "N2"}, {"N1", "N2"}};
+    static const char *const kPair[3][2] = {{"N[0]", "N[1]"}, {"N[0]", "N[2]"}, {"N[1]", "N[2]"}};
     // reactions that matter: up to the last one that changes the state
     int R = g.R;
     while (R > 0 && !((g.change >> (R - 1)) & 1u)) --R;
@@ -60,89 +65,81 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
     std::ostringstream o;
     o << "#include \"gen_device.h\"\n"
       << "namespace bwg {\n"
-      << "extern \"C\" __global__ __launch_bounds__(" << kJitBlock
-      << ") void bwg_jit_word(WmArgs a)\n{\n"
-      << "    constexpr int NB = " << NB << ", BC = " << BC << ", WH = 2 * NB;\n"
-      << "    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;\n"
-      << "    if (w >= a.n_words) return;\n"
-      << "    const uint32_t live = live_lanes(a, w);\n"
-      << "    const uint64_t *E = a.E + 32 * w;\n"
-      << "    const uint64_t *T = a.Etgt + 32 * w;\n"
-      << "    const WordWindow win = word_window(a, E, T, live);\n"
-      << "    uint32_t N0[NB], N1[NB], N2[NB];\n"
-      << "    load_word<NB>(a, w, N0, N1, N2);\n"
-      << "    if (win.lo < win.hi) {\n"
-      << "        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);\n"
-      << "        const int nq = (a.B + 3) / 4;\n"
-      << "        uint32_t lastm[4];\n"
-      << "#pragma unroll\n"
-      << "        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;\n"
-      << "        uint64_t nreal = 0;\n"
-      << "        for (uint64_t e = win.lo; e < win.hi; ++e) {\n"
-      << "            const uint32_t act =\n"
-      << "                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);\n"
-      << "            uint32_t d[BC];\n"
-      << "            philox_planes<BC>(d, e, (uint32_t)w, a.net_id, k0, k1, nq, lastm);\n";
+      << "constexpr int NB = " << NB << ", BC = " << BC << ", WH = 2 * NB;\n"
+      << "struct NetEvent {\n"
+      << "    __device__ __forceinline__ void operator()(uint32_t (&d)[BC], uint32_t act,\n"
+      << "                                               uint32_t (&N)[3][NB], uint64_t &nreal) const\n"
+      << "    {\n";
     // weight kinds
     for (int k = 3; k < 9; ++k) {
         if (!((used >> k) & 1u)) continue;
         if (k < 6) {
-            o << "            uint32_t h" << k << "[WH];\n"
-              << "            mul_planes<NB, WH>(h" << k << ", " << kPair[k - 3][0] << ", "
+            o << "        uint32_t h" << k << "[WH];\n"
+              << "        mul_planes<NB, WH>(h" << k << ", " << kPair[k - 3][0] << ", "
               << kPair[k - 3][1] << ");\n";
         } else {
             const int x = k - 6;
-            o << "            uint32_t h" << k << "[WH];\n"
-              << "            {\n"
-              << "                uint32_t xm[NB], p[WH];\n"
+            o << "        uint32_t h" << k << "[WH];\n"
+              << "        {\n"
+              << "            uint32_t xm[NB], p[WH];\n"
               << "#pragma unroll\n"
-              << "                for (int q = 0; q < NB; ++q) xm[q] = N" << x << "[q];\n"
-              << "                add_pm1<NB>(xm, 0u, ~0u);\n"
-              << "                mul_planes<NB, WH>(p, N" << x << ", xm);\n"
+              << "            for (int q = 0; q < NB; ++q) xm[q] = N[" << x << "][q];\n"
+              << "            add_pm1<NB>(xm, 0u, ~0u);\n"
+              << "            mul_planes<NB, WH>(p, N[" << x << "], xm);\n"
               << "#pragma unroll\n"
-              << "                for (int q = 0; q < WH; ++q) h" << k
+              << "            for (int q = 0; q < WH; ++q) h" << k
               << "[q] = q + 1 < WH ? p[q + 1] : 0u;\n"
-              << "            }\n";
+              << "        }\n";
         }
     }
-    o << "            uint32_t lt = 0, realm = 0;\n"
-      << "            uint32_t mk[3][4] = {};\n";
+    o << "        uint32_t lt = 0, realm = 0;\n"
+      << "        uint32_t mk[3][4] = {};\n";
     static const int kSlot[5] = {3, 1, -1, 0, 2};  // delta -2..2 -> mask index
     for (int j = 0; j < R; ++j) {
         if (!g.c[j]) continue;  // weight 0: never selected
         const int k = g.kind[j];
-        const std::string op = k < 3 ? ("N" + std::to_string(k)) : ("h" + std::to_string(k));
+        const std::string op =
+            k < 3 ? ("N[" + std::to_string(k) + "]") : ("h" + std::to_string(k));
         const char *wp = k < 3 ? "NB" : "WH";
-        o << "            {  // reaction " << j << "\n"
-          << "                uint32_t br = 0;\n";
+        o << "        {  // reaction " << j << "\n"
+          << "            uint32_t br = 0;\n";
         for (int b = 0; b < 32; ++b) {
             if (!((g.c[j] >> b) & 1u)) continue;
             const bool keep = !(j == last_j && b == last_bit);
-            o << "                br |= sub_shifted<" << b << ", BC, " << wp << ", "
+            o << "            br |= sub_shifted<" << b << ", BC, " << wp << ", "
               << (keep ? "true" : "false") << ">(d, " << op << ");\n";
         }
-        o << "                const uint32_t ltj = lt | br;\n"
-          << "                const uint32_t xi = ltj & ~lt & act;\n"
-          << "                lt = ltj;\n";
-        if ((g.change >> j) & 1u) o << "                realm |= xi;\n";
+        o << "            const uint32_t ltj = lt | br;\n"
+          << "            const uint32_t xi = ltj & ~lt & act;\n"
+          << "            lt = ltj;\n";
+        if ((g.change >> j) & 1u) o << "            realm |= xi;\n";
         for (int x = 0; x < 3; ++x) {
             const int dv = g.d[j][x];
-            if (dv) o << "                mk[" << x << "][" << kSlot[dv + 2] << "] |= xi;\n";
+            if (dv) o << "            mk[" << x << "][" << kSlot[dv + 2] << "] |= xi;\n";
         }
-        o << "            }\n";
+        o << "        }\n";
     }
-    o << "            nreal += (uint32_t)__builtin_popcount(realm);\n";
+    o << "        nreal += (uint32_t)__builtin_popcount(realm);\n";
     for (int x = 0; x < 3; ++x) {
         bool any = false;
         for (int j = 0; j < R; ++j) any |= g.c[j] && g.d[j][x];
         if (any)
-            o << "            add_delta<NB>(N" << x << ", mk[" << x << "][0], mk[" << x
-              << "][1], mk[" << x << "][2], mk[" << x << "][3]);\n";
+            o << "        add_delta<NB>(N[" << x << "], mk[" << x << "][0], mk[" << x << "][1], mk["
+              << x << "][2], mk[" << x << "][3]);\n";
     }
-    o << "        }\n"
-      << "        a.real[w] += nreal;\n"
-      << "    }\n"
-      << "    store_word<NB>(a, w, live, win.hi, N0, N1, N2);\n"
+    o << "    }\n"
+      << "};\n"
+      << "extern \"C\" __global__ __launch_bounds__(" << kJitBlock
+      << ") void bwg_jit_word(WmArgs a)\n"
+      << "{\n"
+      << "    gen_word<NB, BC>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, NetEvent{});\n"
+      << "}\n"
+      << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
+      << "{\n"
+      << "    constexpr int PH = " << kJitPcHalf << ";\n"
+      << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
+      << "    __shared__ uint64_t wave_span[4];\n"
+      << "    gen_word_pc<NB, BC, PH>(a, ring, wave_span, NetEvent{});\n"
       << "}\n"
       << "}  // namespace bwg\n";
     return o.str();
@@ -187,6 +184,7 @@ int jit_get(bwg_net *n, const JitKernel **out)
     auto k = new JitKernel();
     hipError_t e = hipModuleLoadData(&k->mod, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "bwg_jit_word");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->pc, k->mod, "bwg_jit_pc");
     if (e != hipSuccess) {
         jit_release(k);
         return fail(BWG_EDEVICE, "loading the network's kernel: %s", hipGetErrorString(e));
@@ -200,6 +198,12 @@ hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s)
 {
     WmArgs arg = a;
     void *params[] = {&arg};
+    // as for the Frank kernels: the producer/consumer form while the words
+    // fill at most one wave per SIMD pair
+    if (a.n_words <= 32768) {
+        const unsigned grid = (unsigned)((a.n_words + 127) / 128);
+        return hipModuleLaunchKernel(k->pc, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr);
+    }
     const unsigned grid = (unsigned)((a.n_words + kJitBlock - 1) / kJitBlock);
     return hipModuleLaunchKernel(k->fn, grid, 1, 1, kJitBlock, 1, 1, 0, s, params, nullptr);
 }

@@ -100,3 +100,20 @@ def test_general_kernel_refusals(torch):
         bwg.Batch([e])
     with pytest.raises(bwg.BwgError):
         bwg.Ensemble(bwg.Network(net), 64, shared_threshold=True)
+
+
+@pytest.mark.parametrize("jit", [True, False])
+def test_large_ensemble_sampled(torch, jit):
+    """Past 32768 words the compiled kernel runs one wave per word (below it
+    the producer/consumer form): 2^20 + 77 replicas of a random network,
+    three blocks of replicas against the oracle, including the ragged end."""
+    net = random_network(31, 80, 6)
+    M = (1 << 20) + 77
+    e = bwg.Ensemble(bwg.Network(net), M, seed=6, net_id=4, jit=jit)
+    e.init(("multinomial",)).step(300)
+    counts = e.read_counts().cpu().numpy()
+    for first, count in ((0, 64), (M // 2 - 5, 40), (M - 45, 45)):
+        o = ssa.OracleEnsemble(net, M, seed=6, net_id=4, first=first, count=count)
+        o.init(("multinomial",))
+        o.step(300)
+        np.testing.assert_array_equal(counts[first:first + count], o.counts)
