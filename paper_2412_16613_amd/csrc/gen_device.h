@@ -23,12 +23,49 @@ __device__ __forceinline__ void add_delta(uint32_t (&x)[NB], uint32_t p1, uint32
     }
 }
 
+// acc += delta * y with delta = +1 on p1, -1 on m1, +2 on p2, -2 on m2
+// (disjoint masks), y a non-negative NB-plane count, acc WP planes modulo
+// 2^WP: the magnitude |delta| y is y or y shifted one plane up, negated as
+// (magnitude ^ neg) + neg on the negative lanes, sign-extended.
+template <int NB, int WP>
+__device__ __forceinline__ void add_scaled(uint32_t (&acc)[WP], const uint32_t (&y)[NB],
+                                           uint32_t p1, uint32_t m1, uint32_t p2, uint32_t m2)
+{
+    const uint32_t one = p1 | m1, two = p2 | m2, neg = m1 | m2;
+    uint32_t c = neg;
+#pragma unroll
+    for (int q = 0; q < WP; ++q) {
+        const uint32_t lo = q < NB ? (y[q] & one) : 0u;
+        const uint32_t hi = (q >= 1 && q - 1 < NB) ? y[q - 1] : 0u;
+        const uint32_t v = BWG_OP3(hi, two, lo, L_ANDOR) ^ neg;
+        const uint32_t s = BWG_OP3(acc[q], v, c, L_XOR3);
+        if (q + 1 < WP) c = BWG_OP3(acc[q], v, c, L_MAJ);
+        acc[q] = s;
+    }
+}
+
+// acc += 1 on a1, 3 on a3 (disjoint masks).
+template <int WP>
+__device__ __forceinline__ void add_one_three(uint32_t (&acc)[WP], uint32_t a1, uint32_t a3)
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < WP; ++q) {
+        const uint32_t v = q == 0 ? (a1 | a3) : (q == 1 ? a3 : 0u);
+        const uint32_t s = BWG_OP3(acc[q], v, c, L_XOR3);
+        if (q + 1 < WP) c = BWG_OP3(acc[q], v, c, L_MAJ);
+        acc[q] = s;
+    }
+}
+
 // Word loops of the per-network kernels: the event itself is a functor
 // ev(d, act, N, nreal) that takes the threshold planes d (consumed), the
 // active lanes and the counts N[species][plane], and adds its real lanes to
-// nreal.  gen_word: one thread per word, as wm_word.
+// nreal; ev.init(N) runs once per launch before the first event (the functor
+// may keep quantities it updates from event to event).  gen_word: one thread
+// per word, as wm_word.
 template <int NB, int BC, typename Event>
-__device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, const Event &ev)
+__device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, Event ev)
 {
     if (w >= a.n_words) return;
     const uint32_t live = live_lanes(a, w);
@@ -44,6 +81,7 @@ __device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, const Even
 #pragma unroll
         for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
         uint64_t nreal = 0;
+        ev.init(N);
         for (uint64_t e = win.lo; e < win.hi; ++e) {
             const uint32_t act =
                 (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
@@ -61,7 +99,7 @@ __device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, const Even
 // barrier per PH events, the workgroup's largest window as step count).
 template <int NB, int BC, int PH, typename Event>
 __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4][64],
-                                            uint64_t *wave_span, const Event &ev)
+                                            uint64_t *wave_span, Event ev)
 {
     const int lane = threadIdx.x & 63;
     const int grp = (threadIdx.x >> 6) & 1;
@@ -117,6 +155,7 @@ __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 
 #pragma unroll
         for (int q = 0; q < NB; ++q) N[0][q] = N[1][q] = N[2][q] = 0u;
     }
+    ev.init(N);
     uint64_t nreal = 0;
     for (uint64_t s = 0; s <= nsteps; ++s) {
         if (s >= 1) {

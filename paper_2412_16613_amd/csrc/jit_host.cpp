@@ -44,8 +44,8 @@ constexpr int kJitBlock = 128;  // threads per block of the one-wave-per-word ke
 constexpr int kJitPcHalf = 4;   // events per ring half of the producer/consumer kernel
 
 // Source of network n's kernels with NB count planes and BC threshold planes:
-// an event functor (weight kinds, selection, state change) and the two word
-// loops of gen_device.h around it.
+// an event functor (weight kinds kept from event to event, selection, state
+// change) and the two word loops of gen_device.h around it.
 static std::string jit_source(const bwg_net &n, int NB, int BC)
 {
     const GenNet &g = n.gen;
@@ -66,21 +66,21 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
     o << "#include \"gen_device.h\"\n"
       << "namespace bwg {\n"
       << "constexpr int NB = " << NB << ", BC = " << BC << ", WH = 2 * NB;\n"
-      << "struct NetEvent {\n"
-      << "    __device__ __forceinline__ void operator()(uint32_t (&d)[BC], uint32_t act,\n"
-      << "                                               uint32_t (&N)[3][NB], uint64_t &nreal) const\n"
+      << "struct NetEvent {\n";
+    // pair counts and X (X - 1) / 2 the reactions use: formed once per launch,
+    // then updated from each event's changes (App. B, for changes in -2..2)
+    for (int k = 3; k < 9; ++k)
+        if ((used >> k) & 1u) o << "    uint32_t h" << k << "[WH];\n";
+    o << "    __device__ __forceinline__ void init(const uint32_t (&N)[3][NB])\n"
       << "    {\n";
-    // weight kinds
     for (int k = 3; k < 9; ++k) {
         if (!((used >> k) & 1u)) continue;
         if (k < 6) {
-            o << "        uint32_t h" << k << "[WH];\n"
-              << "        mul_planes<NB, WH>(h" << k << ", " << kPair[k - 3][0] << ", "
+            o << "        mul_planes<NB, WH>(h" << k << ", " << kPair[k - 3][0] << ", "
               << kPair[k - 3][1] << ");\n";
         } else {
             const int x = k - 6;
-            o << "        uint32_t h" << k << "[WH];\n"
-              << "        {\n"
+            o << "        {\n"
               << "            uint32_t xm[NB], p[WH];\n"
               << "#pragma unroll\n"
               << "            for (int q = 0; q < NB; ++q) xm[q] = N[" << x << "][q];\n"
@@ -92,6 +92,10 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
               << "        }\n";
         }
     }
+    o << "    }\n"
+      << "    __device__ __forceinline__ void operator()(uint32_t (&d)[BC], uint32_t act,\n"
+      << "                                               uint32_t (&N)[3][NB], uint64_t &nreal)\n"
+      << "    {\n";
     o << "        uint32_t lt = 0, realm = 0;\n"
       << "        uint32_t mk[3][4] = {};\n";
     static const int kSlot[5] = {3, 1, -1, 0, 2};  // delta -2..2 -> mask index
@@ -120,12 +124,27 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
         o << "        }\n";
     }
     o << "        nreal += (uint32_t)__builtin_popcount(realm);\n";
+    // species in order: a pair count takes the change of x times the other
+    // species' current count (before that one's own change if it comes
+    // later, after it if earlier: X'Y' - XY = dX Y + dY X'), X (X - 1) / 2
+    // takes dX X + dX (dX - 1) / 2; then the count itself changes
+    static const int kPairOf[3][3] = {{-1, 3, 4}, {3, -1, 5}, {4, 5, -1}};
     for (int x = 0; x < 3; ++x) {
         bool any = false;
         for (int j = 0; j < R; ++j) any |= g.c[j] && g.d[j][x];
-        if (any)
-            o << "        add_delta<NB>(N[" << x << "], mk[" << x << "][0], mk[" << x << "][1], mk["
-              << x << "][2], mk[" << x << "][3]);\n";
+        if (!any) continue;
+        const std::string X = std::to_string(x);
+        const std::string m = "mk[" + X + "][0], mk[" + X + "][1], mk[" + X + "][2], mk[" + X + "][3]";
+        for (int y = 0; y < 3; ++y) {
+            const int k = kPairOf[x][y];
+            if (k >= 0 && ((used >> k) & 1u))
+                o << "        add_scaled<NB, WH>(h" << k << ", N[" << y << "], " << m << ");\n";
+        }
+        if ((used >> (6 + x)) & 1u)
+            o << "        add_scaled<NB, WH>(h" << 6 + x << ", N[" << x << "], " << m << ");\n"
+              << "        add_one_three<WH>(h" << 6 + x << ", mk[" << x << "][1] | mk[" << x
+              << "][2], mk[" << x << "][3]);\n";
+        o << "        add_delta<NB>(N[" << x << "], " << m << ");\n";
     }
     o << "    }\n"
       << "};\n"
