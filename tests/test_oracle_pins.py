@@ -496,3 +496,26 @@ def test_shared_budget_is_one_poisson_number_per_advance():
     exp = stats.poisson.pmf(np.arange(kmax + 1), rate * 0.2) * len(ks)
     exp[-1] += stats.poisson.sf(kmax, rate * 0.2) * len(ks)
     assert chi2_pvalue(obs, exp) > 1e-3
+
+
+@pytest.mark.parametrize("seed,n_tot,R,integer", [(3, 6, 5, False), (5, 7, 8, False),
+                                                  (11, 6, 6, True)])
+def test_random_network_fixed_k_law(seed, n_tot, R, integer):
+    """The oracle on seeded random 3-species networks of order <= 2 (dimers,
+    pairs, no-change reactions) against the exact law after K uniformised
+    events, computed from the generator's integer weights."""
+    from workloads import random_network
+    net = random_network(seed, n_tot, R, exact_integer=integer)
+    q = quantize(net)
+    start = (n_tot // 3, n_tot // 3, n_tot - 2 * (n_tot // 3))
+    K = 9
+    st, probs = master.fixed_k_probs(net, q, start, K)
+    M = 6000
+    o = ssa.OracleEnsemble(net, M, seed=seed + 100, q=q)
+    o.init(("fixed", start))
+    o.step(K)
+    idx = {s: i for i, s in enumerate(st)}
+    obs = np.zeros(len(st))
+    for c in o.counts:
+        obs[idx[tuple(int(v) for v in c)]] += 1
+    assert chi2_pvalue(obs, probs * M) > 1e-3
