@@ -117,3 +117,46 @@ def test_large_ensemble_sampled(torch, jit):
         o.init(("multinomial",))
         o.step(300)
         np.testing.assert_array_equal(counts[first:first + count], o.counts)
+
+
+def _table(reactions, rates, n_tot, integer=True):
+    from workloads.frank import _net
+    return _net(reactions, rates, n_tot, exact_integer=integer)
+
+
+@pytest.mark.parametrize("jit", [True, False])
+def test_edge_tables(torch, jit):
+    """Zero weights between real reactions, a network where nothing changes
+    the state, and a dimer conversion with a large weight."""
+    zero_mid = _table([((0, 0, 1), (1, 0, 0)), ((1, 0, 0), (0, 1, 0)), ((0, 1, 0), (0, 0, 1)),
+                       ((2, 0, 0), (0, 0, 2))], [3, 0, 2, 5], 20)
+    still = _table([((1, 0, 0), (1, 0, 0)), ((0, 1, 1), (0, 1, 1))], [4, 1], 15)
+    dimer = _table([((0, 0, 2), (1, 1, 0)), ((1, 1, 0), (0, 0, 2)), ((2, 0, 0), (1, 0, 1))],
+                   [1000, 3, 7], 30)
+    for net, init in ((zero_mid, ("fixed", (5, 5, 10))), (still, ("fixed", (5, 5, 5))),
+                      (dimer, ("multinomial",))):
+        e = _check(torch, net, 333, init, [("step", 800), ("step", 5)], seed=3, net_id=7, jit=jit)
+    ev, real = e.read_events()
+    assert int(real.sum()) > 0
+
+
+def test_still_network_changes_nothing(torch):
+    net = _table([((1, 0, 0), (1, 0, 0)), ((0, 1, 1), (0, 1, 1))], [4, 1], 15)
+    e = bwg.Ensemble(bwg.Network(net), 100)
+    e.init(("fixed", (5, 5, 5))).step(1000)
+    assert (e.read_counts().cpu().numpy() == [5, 5, 5]).all()
+    assert int(e.read_events()[1].sum()) == 0
+
+
+def test_record_on_a_general_network(torch):
+    net = random_network(41, 40, 6)
+    M = 500
+    grid = [0.2 * (k + 1) / bwg.Network(net).quantized()["Lambda"] * 100 for k in range(10)]
+    e = bwg.Ensemble(bwg.Network(net), M, seed=2)
+    e.init(("multinomial",))
+    traj, first = e.record(grid, [0, 17, 499], threshold=10)
+    o = ssa.OracleEnsemble(net, M, seed=2)
+    o.init(("multinomial",))
+    for k, t in enumerate(grid):
+        o.advance(t)
+        np.testing.assert_array_equal(traj[k].cpu().numpy(), o.counts[[0, 17, 499]])
