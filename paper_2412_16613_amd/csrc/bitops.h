@@ -55,7 +55,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 
 // ---- bit-sliced arithmetic ------------------------------------------------
 // Planes are uint32 arrays, least significant plane first.  All operations
-// are modulo 2^width of the destination.
+// are modulo 2^width of the destination.  The in-place ripple updates form
+// each plane's carry before overwriting the plane, so the new value can take
+// the old one's register (in an event loop, no copies at the loop latch).
 
 // Masked increment/decrement/double by per-lane masks: x += d with
 // d = +1 on `plus`, -1 on `minus`, 0 elsewhere (plus & minus = 0).
@@ -67,9 +69,9 @@ __device__ __forceinline__ void add_pm1(uint32_t (&x)[W], uint32_t plus, uint32_
     x[0] ^= (plus | minus);
 #pragma unroll
     for (int q = 1; q < W; ++q) {
-        const uint32_t s = BWG_OP3(x[q], minus, c, L_XOR3);
-        if (q + 1 < W) c = BWG_OP3(x[q], minus, c, L_MAJ);
-        x[q] = s;
+        const uint32_t cn = q + 1 < W ? BWG_OP3(x[q], minus, c, L_MAJ) : 0u;
+        x[q] = BWG_OP3(x[q], minus, c, L_XOR3);
+        c = cn;
     }
 }
 
@@ -82,15 +84,15 @@ __device__ __forceinline__ void add_m1_p2(uint32_t (&x)[W], uint32_t minus1, uin
     x[0] ^= minus1;
     if (W > 1) {
         const uint32_t a1 = minus1 | plus2;
-        const uint32_t s = BWG_OP3(x[1], a1, c, L_XOR3);
-        c = BWG_OP3(x[1], a1, c, L_MAJ);
-        x[1] = s;
+        const uint32_t cn = BWG_OP3(x[1], a1, c, L_MAJ);
+        x[1] = BWG_OP3(x[1], a1, c, L_XOR3);
+        c = cn;
     }
 #pragma unroll
     for (int q = 2; q < W; ++q) {
-        const uint32_t s = BWG_OP3(x[q], minus1, c, L_XOR3);
-        if (q + 1 < W) c = BWG_OP3(x[q], minus1, c, L_MAJ);
-        x[q] = s;
+        const uint32_t cn = q + 1 < W ? BWG_OP3(x[q], minus1, c, L_MAJ) : 0u;
+        x[q] = BWG_OP3(x[q], minus1, c, L_XOR3);
+        c = cn;
     }
 }
 
@@ -104,9 +106,9 @@ __device__ __forceinline__ void add_sext(uint32_t (&acc)[WA], const uint32_t (&d
 #pragma unroll
     for (int q = 0; q < WA; ++q) {
         const uint32_t v = q < WD ? d[q] : sgn;
-        const uint32_t s = BWG_OP3(acc[q], v, c, L_XOR3);
-        if (q + 1 < WA) c = BWG_OP3(acc[q], v, c, L_MAJ);
-        acc[q] = s;
+        const uint32_t cn = q + 1 < WA ? BWG_OP3(acc[q], v, c, L_MAJ) : 0u;
+        acc[q] = BWG_OP3(acc[q], v, c, L_XOR3);
+        c = cn;
     }
 }
 

@@ -127,6 +127,10 @@ __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 
         uint32_t lastm[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
+        // quads past the network's threshold planes stay zero in every slot
+        // (visible to the consumer after the first barrier)
+        for (int h = 0; h < 2 * PH; ++h)
+            for (int q4 = nq; q4 < BC / 4; ++q4) ring[h][q4][lane] = make_uint4(0, 0, 0, 0);
         for (uint64_t s = 0; s <= nsteps; ++s) {
             if (s < nsteps) {
                 const int half = (int)(s & 1) * PH;
@@ -168,7 +172,7 @@ __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 
                     uint32_t d[BC];
 #pragma unroll
                     for (int q4 = 0; q4 < BC / 4; ++q4) {
-                        const uint4 v = q4 < nq ? ring[half + j][q4][lane] : make_uint4(0, 0, 0, 0);
+                        const uint4 v = ring[half + j][q4][lane];
                         d[4 * q4 + 0] = v.x;
                         d[4 * q4 + 1] = v.y;
                         d[4 * q4 + 2] = v.z;
