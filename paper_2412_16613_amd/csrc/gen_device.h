@@ -81,10 +81,12 @@ __device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, Event ev)
 #pragma unroll
         for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
         uint64_t nreal = 0;
+        uint64_t nxt = 0;  // next event at which the active lanes change
+        uint32_t actc = 0;
         ev.init(N);
         for (uint64_t e = win.lo; e < win.hi; ++e) {
-            const uint32_t act =
-                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+            if (e >= nxt) actc = lane_mask_next(E, T, win.pend, e, win.blo, nxt);
+            const uint32_t act = actc;
             uint32_t d[BC];
             philox_planes<BC>(d, e, (uint32_t)w, a.net_id, k0, k1, nq, lastm);
             ev(d, act, N, nreal);
@@ -161,14 +163,16 @@ __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 
     }
     ev.init(N);
     uint64_t nreal = 0;
+    uint64_t nxt = 0;  // next event at which the active lanes change
+    uint32_t actc = 0;
     for (uint64_t s = 0; s <= nsteps; ++s) {
         if (s >= 1) {
             const int half = (int)((s - 1) & 1) * PH;
             for (int j = 0; j < PH; ++j) {
                 const uint64_t e = lo + (s - 1) * PH + j;
                 if (e < hi) {
-                    const uint32_t act =
-                        (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+                    if (e >= nxt) actc = lane_mask_next(E, T, win.pend, e, win.blo, nxt);
+                    const uint32_t act = actc;
                     uint32_t d[BC];
 #pragma unroll
                     for (int q4 = 0; q4 < BC / 4; ++q4) {

@@ -39,9 +39,11 @@ __global__ __launch_bounds__(64) void gen_event_kernel(WmArgs a, GenNet g)
 #pragma unroll
         for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
         uint64_t nreal = 0;
+        uint64_t nxt = 0;  // next event at which the active lanes change
+        uint32_t actc = 0;
         for (uint64_t e = win.lo; e < win.hi; ++e) {
-            const uint32_t act =
-                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+            if (e >= nxt) actc = lane_mask_next(E, T, win.pend, e, win.blo, nxt);
+            const uint32_t act = actc;
             // (b) weight kinds into LDS
 #pragma unroll
             for (int k = 0; k < 9; ++k) {

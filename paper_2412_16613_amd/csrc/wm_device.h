@@ -74,16 +74,67 @@ __device__ __forceinline__ uint32_t sub_w(int sh, uint32_t (&d)[BC], const uint3
         return sub_dispatch<BC, WP, KEEP>(sh, d, p);
 }
 
-// Active lanes of a word at event e: E_l <= e < Etgt_l.
-__device__ __forceinline__ uint32_t lane_mask(const uint64_t *E, const uint64_t *T,
-                                              uint32_t live, uint64_t e)
+// Active lanes of a word at event e (E_l <= e < Etgt_l among pend) and, in
+// nxt, the first event after e at which that set changes (~0: never), so
+// that an event loop recomputes the set only there.  A word's 32 entries of
+// E and Etgt are contiguous and 256-byte aligned (the arrays hold 32 entries
+// for every word), so they are read with 16-byte loads, eight in flight;
+// entries of lanes outside pend are read but ignored.  From blo on every
+// pending lane has started and only the targets are needed.
+__device__ __forceinline__ uint32_t lane_mask_next(const uint64_t *E, const uint64_t *T,
+                                                   uint32_t pend, uint64_t e, uint64_t blo,
+                                                   uint64_t &nxt)
 {
     uint32_t m = 0;
-    for (int l = 0; l < 32; ++l) {
-        if (!((live >> l) & 1u)) continue;
-        const uint64_t a = E[l], b = T[l];
-        m |= (a <= e && e < b) ? (1u << l) : 0u;
+    uint64_t nx = ~0ull;
+    const uint4 *T4 = reinterpret_cast<const uint4 *>(T);
+    if (e >= blo) {
+#pragma unroll 1
+        for (int g = 0; g < 2; ++g) {
+            uint4 tv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) tv[j] = T4[8 * g + j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int l = 16 * g + 2 * j + h;
+                    const uint64_t y = h ? ((uint64_t)tv[j].w << 32 | tv[j].z)
+                                         : ((uint64_t)tv[j].y << 32 | tv[j].x);
+                    const bool on = ((pend >> l) & 1u) && e < y;
+                    m |= on ? (1u << l) : 0u;
+                    nx = (on && y < nx) ? y : nx;
+                }
+            }
+        }
+    } else {
+        const uint4 *E4 = reinterpret_cast<const uint4 *>(E);
+#pragma unroll 1
+        for (int g = 0; g < 4; ++g) {
+            uint4 ev[4], tv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ev[j] = E4[4 * g + j];
+                tv[j] = T4[4 * g + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int l = 8 * g + 2 * j + h;
+                    const uint64_t x = h ? ((uint64_t)ev[j].w << 32 | ev[j].z)
+                                         : ((uint64_t)ev[j].y << 32 | ev[j].x);
+                    const uint64_t y = h ? ((uint64_t)tv[j].w << 32 | tv[j].z)
+                                         : ((uint64_t)tv[j].y << 32 | tv[j].x);
+                    const bool p = (pend >> l) & 1u;
+                    m |= (p && x <= e && e < y) ? (1u << l) : 0u;
+                    const uint64_t c = x > e ? x : (y > e ? y : ~0ull);
+                    nx = (p && c < nx) ? c : nx;
+                }
+            }
+        }
     }
+    nxt = nx;
     return m;
 }
 
@@ -257,10 +308,12 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
         for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
         uint32_t nv_next = SH ? shared_at(a, lo) : 0u;
         uint64_t nreal = 0;
+        uint64_t nxt = 0;  // next event at which the active lanes change
+        uint32_t actc = 0;
 
         for (uint64_t e = lo; e < hi; ++e) {
-            const uint32_t act =
-                (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+            if (e >= nxt) actc = lane_mask_next(E, T, win.pend, e, win.blo, nxt);
+            const uint32_t act = actc;
             // (a) threshold planes
             uint32_t n[BC];
             if constexpr (SH) {
@@ -375,14 +428,16 @@ __device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4
     init_weights<NB, BC, WP>(L, D, A, cu, PAL, PAD, PLD, U);
     const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
     uint64_t nreal = 0;
+    uint64_t nxt = 0;  // next event at which the active lanes change
+    uint32_t actc = 0;
     for (uint64_t s = 0; s <= nsteps; ++s) {
         if (s >= 1) {
             const int half = (int)((s - 1) & 1) * PH;
             for (int j = 0; j < PH; ++j) {
                 const uint64_t e = lo + (s - 1) * PH + j;
                 if (e < hi) {
-                    const uint32_t act =
-                        (e >= win.blo && e < win.bhi) ? win.pend : lane_mask(E, T, win.pend, e);
+                    if (e >= nxt) actc = lane_mask_next(E, T, win.pend, e, win.blo, nxt);
+                    const uint32_t act = actc;
                     uint32_t n[BC];
 #pragma unroll
                     for (int q4 = 0; q4 < BC / 4; ++q4) {
