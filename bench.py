@@ -44,9 +44,9 @@ VALU_PEAK = 256 * 128 * 2.4e9   # 32-bit lane-slots/s: 256 CUs x 128 lanes/clk x
 # kernel -> (sha1 prefix of its sources, sources, bytes per launch, summary file).
 CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
 MEASURED_TRAFFIC = {
-    "wm_pc_kernel": ("eec7ece87b83", ("bitops.h", "wm_device.h", "wm_event_body.inc",
+    "wm_pc_kernel": ("7b196892f1ba", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
-                     int((2 * 10686.875 + 12672) * 1024), "profiles/wm_pc_kernel_frank1024_2p20.md"),
+                     int((2 * 10848.25 + 12672) * 1024), "profiles/wm_pc_kernel_frank1024_2p20.md"),
     "lat_event_kernel": ("1233d02af292", ("bitops.h", "lattice.hip"),
                          (2 * 3994154 + 8337447) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),

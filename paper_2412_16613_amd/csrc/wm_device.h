@@ -433,6 +433,13 @@ __device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4
     for (uint64_t s = 0; s <= nsteps; ++s) {
         if (s >= 1) {
             const int half = (int)((s - 1) & 1) * PH;
+            // unrolled where the weights are compile-time: the PH events of
+            // a step share registers without copies and the ring offsets are
+            // constants (measured faster); the run-time weight variants,
+            // whose shifted subtractions dispatch per shift, run slower
+            // unrolled
+            constexpr int UNR = (FA >= 0 && CU >= 0) ? PH : 1;
+#pragma unroll UNR
             for (int j = 0; j < PH; ++j) {
                 const uint64_t e = lo + (s - 1) * PH + j;
                 if (e < hi) {
