@@ -24,7 +24,8 @@ sys.path.insert(0, ROOT)
 
 # VALU issue slots per word-event (32 replica-events) the bit-sliced method
 # needs for a network with b count planes, B threshold planes and product
-# shift f; see DESIGN.md ("Algorithmic work").
+# shift f: Philox calls, selection chains, occupancy and product updates,
+# the unimolecular weight and the real-event count (word_event_slots).
 PHILOX_SLOTS = 100          # 20 32x32->64 multiplies at 4 slots + 20 xor3
 
 
@@ -97,8 +98,8 @@ def main():
                     help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the path shards by replica across GPUs "
-              "(see DESIGN.md) but no multi-GPU run is part of this build", file=sys.stderr)
+        print("bench.py runs on one GPU only: replicas are independent and would shard by "
+              "word across GPUs, but only the single-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
