@@ -56,6 +56,17 @@ def test_random_networks_match_oracle(torch, seed, n_tot, R, M, jit):
            net_id=seed + 10, jit=jit)
 
 
+# Many short advances: the replicas of a word start and end each launch at
+# different events (the active lanes are rebuilt only where they change).
+@pytest.mark.parametrize("jit", [True, False])
+def test_staggered_starts_and_ends(torch, jit):
+    net = random_network(9, 60, 6)
+    q = bwg.Network(net).quantized()
+    dt = 40.0 / q["Lambda"]                   # about 40 events per replica
+    _check(torch, net, 64 * 32 * 2 + 45, ("multinomial",),
+           [("advance", dt * (k + 1)) for k in range(15)], seed=9, net_id=19, jit=jit)
+
+
 @pytest.mark.parametrize("seed", [11, 12, 13])
 def test_random_integer_networks_match_oracle(torch, seed):
     net = random_network(seed, 40, 8, exact_integer=True)

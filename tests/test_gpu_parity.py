@@ -209,6 +209,22 @@ def test_word_kernel_forms_match_oracle(torch, block, net, M, init, sched, epl):
     check_parity(torch, net, M, init, sched, seed=12, net_id=4, epl=epl, block=block)
 
 
+# The active lanes of a word change only where one of its replicas starts or
+# ends its budget; the kernels rebuild the set at exactly those events.  After
+# each short advance the replicas of a word stand at different event counts,
+# so every later launch has lanes starting and ending at different events of
+# the same word (both forms of the word kernel, ragged last word, two
+# workgroups of the producer/consumer form).
+@pytest.mark.parametrize("block", [0, 128])
+def test_staggered_starts_and_ends(torch, block):
+    net = frank_network(200, k0=0.03)
+    q = bwg.Network(net).quantized()
+    dt = 60.0 / q["Lambda"]                   # about 60 events per replica
+    sched = [("advance", dt * (k + 1)) for k in range(20)]
+    check_parity(torch, net, 64 * 32 * 2 + 45, ("multinomial",), sched, seed=21, net_id=6,
+                 block=block)
+
+
 # ---- comparator engine -----------------------------------------------------------
 
 def test_plain_engine_exact(torch):
