@@ -175,8 +175,14 @@ typedef struct {
  * weight kinds in registers, one compile-time shifted subtraction per set bit
  * of each c_j, trailing reactions that change nothing left out; same results
  * as the precompiled general kernel.  Creation fails with EDEVICE (and the
- * compiler's log in bwg_last_error) if that compile fails.  This flag keeps
- * the precompiled general kernel instead. */
+ * compiler's log in bwg_last_error) if that compile fails.  Likewise a
+ * Frank-family network whose product shift and unimolecular weight match no
+ * precompiled variant runs the Frank kernels compiled for its plane counts
+ * and weights; that compile happens at the ensemble's first bit-sliced
+ * launch (default block size, per-replica thresholds; batches never run it),
+ * which fails with EDEVICE if the compile fails, and gives the results of the
+ * precompiled run-time weight kernels.  This flag keeps the precompiled
+ * kernels instead. */
 #define BWG_OPT_NO_JIT 8u
 
 typedef struct {
@@ -335,6 +341,14 @@ int bwg_ensemble_kernel_time(bwg_ens *ens, double *ms, uint64_t *launches);
  * state layout and random draws, so results do not change); EINVAL for other
  * engines, lattices or a plain ensemble.  Takes effect at the next launch. */
 int bwg_ensemble_set_engine(bwg_ens *ens, int32_t engine);
+
+/* Builds now the kernel that the ensemble's next bit-sliced launch would
+ * compile at run time (a Frank-family network on a run-time weight variant,
+ * see BWG_OPT_NO_JIT), so that the compile does not fall into a later launch
+ * (a timed region, a serving loop); shared by every ensemble of the network.
+ * A no-op for every other ensemble.  EDEVICE if the compile fails, EINVAL
+ * for a null ensemble.  Host only. */
+int bwg_ensemble_prepare(bwg_ens *ens);
 
 /* In batches, run the last n_words words of a bit-sliced ensemble (rounded so
  * that the bit-sliced part is whole 64-word items) as lanes items of the same

@@ -269,6 +269,12 @@ class Ensemble:
                                                    self._stream()))
         return ev, real
 
+    def prepare(self):
+        """Build now any kernel the next bit-sliced launch would compile at
+        run time (Frank-family networks on run-time weights)."""
+        _abi.check(_lib().bwg_ensemble_prepare(self.handle))
+        return self
+
     def set_engine(self, engine):
         """Switch between the "bitwise" and "lanes" engines (same state and
         results; the lanes engine runs one replica per thread)."""

@@ -42,7 +42,7 @@ SYMBOLS = (
     "bwg_batch_capacity_bytes", "bwg_batch_set_members", "bwg_batch_run",
     "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
     "bwg_ensemble_kernel_time", "bwg_ensemble_set_engine", "bwg_ensemble_set_lanes_words",
-    "bwg_ensemble_record",
+    "bwg_ensemble_record", "bwg_ensemble_prepare",
 )
 
 
@@ -142,6 +142,7 @@ def load():
         "bwg_ensemble_read_blocked": (i32, [vp, vp, vp]),
         "bwg_ensemble_kernel_time": (i32, [vp, P(ctypes.c_double), P(u64)]),
         "bwg_ensemble_set_engine": (i32, [vp, i32]),
+        "bwg_ensemble_prepare": (i32, [vp]),
         "bwg_ensemble_set_lanes_words": (i32, [vp, u64]),
         "bwg_ensemble_record": (i32, [vp, P(ctypes.c_double), u32, vp, u32, vp, i32, vp, vp]),
     }

@@ -556,13 +556,20 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
         return BWG_OK;
     }
     check_engine(n, e->engine, &e->var, &e->gvar, o && (o->flags & BWG_OPT_GENERIC_KERNEL));
-    if (e->gvar && !(o && (o->flags & BWG_OPT_NO_JIT))) {
+    const bool jit_ok = !(o && (o->flags & BWG_OPT_NO_JIT));
+    if (e->gvar && jit_ok) {
         rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
         if (rc) {
             delete e;
             return rc;
         }
     }
+    // a Frank-family network on a run-time weight variant gets its own
+    // compiled kernel, built at its first launch of the bit-sliced engine
+    // (batch members never launch alone and never build it); the
+    // precompiled variant stays for the lanes engine, explicit block sizes
+    // and shared thresholds
+    e->want_jit_frank = e->var && jit_ok && !e->zs && (e->var->fa < 0 || e->var->cu < 0);
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
@@ -591,6 +598,13 @@ extern "C" int bwg_ensemble_set_lanes_words(bwg_ens *e, uint64_t n_words)
         return fail(BWG_EINVAL, "only Frank-family bit-plane ensembles split their words");
     e->lanes_words = n_words;
     return BWG_OK;
+}
+
+extern "C" int bwg_ensemble_prepare(bwg_ens *e)
+{
+    if (!e) return fail(BWG_EINVAL, "null ensemble");
+    if (e->lat || !e->want_jit_frank || e->jit_frank) return BWG_OK;
+    return jit_frank_get(e->net, &e->jit_frank);
 }
 
 extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)
@@ -742,11 +756,19 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         a.zbase = e->zbase;
         a.zlen = e->zs ? e->zlen : 0;
         if (a.zs && !a.zlen) return fail(BWG_EINVAL, "shared thresholds not staged");
+        const bool frank_jit = e->engine == BWG_ENGINE_BITWISE && e->want_jit_frank &&
+                               e->block <= 0 && !a.zs;
+        if (frank_jit && !e->jit_frank) {
+            const int jrc = jit_frank_get(e->net, &e->jit_frank);
+            if (jrc) return jrc;
+        }
         hipEvent_t ev = nullptr;
         int rc = mark_begin(e, s, &ev);
         if (rc) return rc;
         if (e->engine == BWG_ENGINE_LANES)
             HIP_TRY(launch_wm_lanes(a, s));
+        else if (frank_jit)
+            HIP_TRY(jit_launch(e->jit_frank, a, s));
         else if (e->jit)
             HIP_TRY(jit_launch(e->jit, a, s));
         else if (e->gvar)

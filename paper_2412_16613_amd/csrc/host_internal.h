@@ -62,11 +62,13 @@ struct bwg_net {
     std::mutex mu;
     std::map<uint64_t, Table> tables;  // keyed by the bits of mu
     bwg::JitKernel *jit = nullptr;     // compiled on the first ensemble that needs it
+    bwg::JitKernel *jit_frank = nullptr;  // compiled Frank-family kernel (run-time weights)
     ~bwg_net()
     {
         for (auto &kv : tables)
             if (kv.second.host) (void)hipHostFree(kv.second.host);
         bwg::jit_release(jit);
+        bwg::jit_release(jit_frank);
     }
 };
 
@@ -83,6 +85,8 @@ struct bwg_ens {
     const bwg::WmVariant *var = nullptr;
     const bwg::GenVariant *gvar = nullptr;  // general kernel (non-Frank or forced)
     const bwg::JitKernel *jit = nullptr;    // its per-network compiled form, if used
+    const bwg::JitKernel *jit_frank = nullptr;  // compiled Frank kernel for a run-time variant
+    bool want_jit_frank = false;                // build it at the first bit-sliced launch
     uint32_t *planes = nullptr;
     int32_t *counts = nullptr;
     uint64_t *E = nullptr, *Et = nullptr, *real = nullptr, *table = nullptr, *scratch = nullptr;
@@ -127,6 +131,8 @@ namespace bwg {
 int get_table(bwg_net *n, double mu, const Table **out, bool pinned = true);
 // The network's run-time compiled kernel (compiled on the first call).
 int jit_get(bwg_net *n, const JitKernel **out);
+// The network's compiled Frank-family kernel (compiled on the first call).
+int jit_frank_get(bwg_net *n, const JitKernel **out);
 // Budgets of one advance to t_end (no event launches); *kmin/*kmax bound K.
 int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, uint64_t *kmax);
 // Bookkeeping after budgets with K in [kmin, kmax] were drawn.

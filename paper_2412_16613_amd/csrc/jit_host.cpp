@@ -12,6 +12,12 @@
 // forms), compiles it once per network and launches it through the module
 // API.  It draws the same thresholds and computes the same first
 // crossing as the general kernel, so results are identical.
+//
+// Frank-family networks whose product shift and unimolecular weight match
+// no precompiled variant get the hand-written Frank kernels of wm_device.h
+// compiled the same way, with those weights and the network's plane counts
+// as template constants: the results are those of the precompiled run-time
+// weight kernels, at the speed of the named workloads' kernels.
 
 #include <hip/hiprtc.h>
 
@@ -31,6 +37,7 @@ struct JitKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;  // one thread per word
     hipFunction_t pc = nullptr;  // producer/consumer form
+    bool frank = false;          // the Frank-family kernel of wm_device.h
 };
 
 void jit_release(JitKernel *k)
@@ -164,20 +171,9 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
     return o.str();
 }
 
-// The compiled kernel of network n, built on the first call (under the
-// network's lock).
-int jit_get(bwg_net *n, const JitKernel **out)
+// Compiles src with hipRTC for gfx950 and loads its two kernels.
+static int jit_compile(const std::string &src, bool frank, JitKernel **out)
 {
-    std::lock_guard<std::mutex> lock(n->mu);
-    if (n->jit) {
-        *out = n->jit;
-        return BWG_OK;
-    }
-    if (!n->gen_ok) return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
-    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
-    const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
-    if (BC > 32 || NB > 14) return fail(BWG_EUNSUPPORTED, "network beyond 14 count / 32 threshold planes");
-    const std::string src = jit_source(*n, NB, BC);
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "bwg_jit_word.hip", kJitHeaderCount, kJitHeaders,
                             kJitHeaderNames) != HIPRTC_SUCCESS)
@@ -201,6 +197,7 @@ int jit_get(bwg_net *n, const JitKernel **out)
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     auto k = new JitKernel();
+    k->frank = frank;
     hipError_t e = hipModuleLoadData(&k->mod, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "bwg_jit_word");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->pc, k->mod, "bwg_jit_pc");
@@ -208,7 +205,81 @@ int jit_get(bwg_net *n, const JitKernel **out)
         jit_release(k);
         return fail(BWG_EDEVICE, "loading the network's kernel: %s", hipGetErrorString(e));
     }
+    *out = k;
+    return BWG_OK;
+}
+
+// The compiled kernel of network n, built on the first call (under the
+// network's lock).
+int jit_get(bwg_net *n, const JitKernel **out)
+{
+    std::lock_guard<std::mutex> lock(n->mu);
+    if (n->jit) {
+        *out = n->jit;
+        return BWG_OK;
+    }
+    if (!n->gen_ok) return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
+    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
+    const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
+    if (BC > 32 || NB > 14) return fail(BWG_EUNSUPPORTED, "network beyond 14 count / 32 threshold planes");
+    JitKernel *k = nullptr;
+    const int rc = jit_compile(jit_source(*n, NB, BC), false, &k);
+    if (rc) return rc;
     n->jit = k;
+    *out = k;
+    return BWG_OK;
+}
+
+// Source of the Frank-family kernels of wm_device.h for network n with its
+// count and threshold planes, product shift and unimolecular weight as
+// compile-time constants (the precompiled kernels take them at run time
+// unless the network is one of the named workloads).  The second shift, if
+// it differs from the first, stays a run-time value as in the precompiled
+// kernels.
+static std::string jit_frank_source(const bwg_net &n, int NB, int BC, int FA, int CU)
+{
+    std::ostringstream o;
+    o << "#include \"wm_device.h\"\n"
+      << "namespace bwg {\n"
+      << "constexpr int NB = " << NB << ", BC = " << BC << ", FA = " << FA << ", CU = " << CU
+      << ";\n"
+      << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_word(WmArgs a)\n"
+      << "{\n"
+      << "    wm_word<NB, BC, FA, CU, false>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
+      << "}\n"
+      << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
+      << "{\n"
+      << "    constexpr int PH = BC == 20 ? 6 : 4;\n"
+      << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
+      << "    __shared__ uint64_t wave_span[4];\n"
+      << "    wm_word_pc<NB, BC, FA, CU, PH>(a, ring, wave_span);\n"
+      << "}\n"
+      << "}  // namespace bwg\n";
+    (void)n;
+    return o.str();
+}
+
+// The compiled Frank-family kernel of network n (first call compiles it,
+// under the network's lock); BWG_EUNSUPPORTED where the network's planes
+// or weights do not fit the kernel's template parameters.
+int jit_frank_get(bwg_net *n, const JitKernel **out)
+{
+    std::lock_guard<std::mutex> lock(n->mu);
+    if (n->jit_frank) {
+        *out = n->jit_frank;
+        return BWG_OK;
+    }
+    if (!n->shape_ok) return fail(BWG_EUNSUPPORTED, "network is not of the Frank family");
+    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
+    const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
+    const int fa = n->shape.fa, fi = n->shape.fi;
+    const int FA = fa >= 0 ? fa : (fi >= 0 ? fi : 0);
+    if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || fi >= BC || n->shape.cu > 0x7FFFFFFFu)
+        return fail(BWG_EUNSUPPORTED, "network beyond the compiled Frank kernel's range");
+    JitKernel *k = nullptr;
+    const int rc = jit_compile(jit_frank_source(*n, NB, BC, FA, (int)n->shape.cu), true, &k);
+    if (rc) return rc;
+    n->jit_frank = k;
     *out = k;
     return BWG_OK;
 }
@@ -223,8 +294,11 @@ hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s)
         const unsigned grid = (unsigned)((a.n_words + 127) / 128);
         return hipModuleLaunchKernel(k->pc, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr);
     }
-    const unsigned grid = (unsigned)((a.n_words + kJitBlock - 1) / kJitBlock);
-    return hipModuleLaunchKernel(k->fn, grid, 1, 1, kJitBlock, 1, 1, 0, s, params, nullptr);
+    // Frank kernels: 256-thread blocks from 65 536 words on, as for the
+    // precompiled ones (128-thread blocks are placed unevenly there)
+    const unsigned block = (k->frank && a.n_words >= 65536) ? 256u : (unsigned)kJitBlock;
+    const unsigned grid = (unsigned)((a.n_words + block - 1) / block);
+    return hipModuleLaunchKernel(k->fn, grid, 1, 1, block, 1, 1, 0, s, params, nullptr);
 }
 
 }  // namespace bwg

@@ -29,10 +29,10 @@ def _say(*a):
 
 
 def gpu_run(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0,
-            shared=False, block=0):
+            shared=False, block=0, jit=True):
     n = bwg.Network(net)
     ens = bwg.Ensemble(n, M, seed=seed, net_id=net_id, engine=engine, events_per_launch=epl,
-                       shared_threshold=shared, block=block)
+                       shared_threshold=shared, block=block, jit=jit)
     ens.init(init)
     for op, v in schedule:
         if op == "advance":
@@ -67,10 +67,10 @@ def group_sums(x, M):
 
 
 def check_parity(torch, net, M, init, schedule, seed=0, net_id=0, engine="bitwise", epl=0,
-                 shared=False, block=0):
-    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl, shared, block)
+                 shared=False, block=0, jit=True):
+    _say("case", engine, net["n_tot"], M, init, schedule, seed, net_id, epl, shared, block, jit)
     counts, ev, real, ens = gpu_run(torch, net, M, init, schedule, seed, net_id, engine, epl,
-                                    shared, block)
+                                    shared, block, jit)
     draw = (ssa.DRAW_PLAIN if engine == "plain" else
             ssa.DRAW_SHARED if shared else ssa.DRAW_EVENT)
     o = oracle_run(net, M, init, schedule, seed, net_id, draw)
@@ -142,12 +142,29 @@ def test_paper_network_multinomial_start(torch):
     check_parity(torch, c["net"], 4096, ("multinomial",), [("step", 3000)], seed=1)
 
 
+# Frank networks whose weights match no precompiled variant: by default the
+# kernels compiled for the network (hipRTC), with jit=False the precompiled
+# run-time weight kernels; both against the oracle.
+@pytest.mark.parametrize("jit", [True, False])
 @pytest.mark.parametrize("n_tot,k0", [(12, 0.01), (40, 0.05), (100, 0.01), (300, 0.002),
                                       (1000, 0.02), (16, 0.1)])
-def test_run_time_shift_kernels(torch, n_tot, k0):
+def test_run_time_shift_kernels(torch, n_tot, k0, jit):
     net = frank_network(n_tot, k0=k0)
     check_parity(torch, net, 700, ("fixed", (0, 0, n_tot)), [("advance", 3.0)], seed=4,
-                 net_id=n_tot)
+                 net_id=n_tot, jit=jit)
+
+
+# The compiled kernel in its one-wave-per-word form (more than 32768 words,
+# 256-thread blocks from 65536 on) against the precompiled run-time weight
+# kernel, which the oracle pins above: every count and event counter equal.
+@pytest.mark.parametrize("M", [(1 << 20) + (1 << 16) + 5, (1 << 21) + 33])
+def test_compiled_frank_kernel_equals_precompiled(torch, M):
+    net = frank_network(1024, k0=0.02)
+    sched = [("advance", 0.4), ("step", 77)]
+    a = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, jit=True)
+    b = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, jit=False)
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
 
 
 def test_pure_conversion_without_bimolecular_reactions(torch):
