@@ -147,7 +147,7 @@ def test_paper_network_multinomial_start(torch):
 # run-time weight kernels; both against the oracle.
 @pytest.mark.parametrize("jit", [True, False])
 @pytest.mark.parametrize("n_tot,k0", [(12, 0.01), (40, 0.05), (100, 0.01), (300, 0.002),
-                                      (1000, 0.02), (16, 0.1)])
+                                      (1000, 0.02), (16, 0.1), (3, 0.1), (7, 0.1)])
 def test_run_time_shift_kernels(torch, n_tot, k0, jit):
     net = frank_network(n_tot, k0=k0)
     check_parity(torch, net, 700, ("fixed", (0, 0, n_tot)), [("advance", 3.0)], seed=4,
