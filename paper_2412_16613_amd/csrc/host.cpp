@@ -569,7 +569,8 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     // (batch members never launch alone and never build it); the
     // precompiled variant stays for the lanes engine, explicit block sizes
     // and shared thresholds
-    e->want_jit_frank = e->var && jit_ok && !e->zs && (e->var->fa < 0 || e->var->cu < 0);
+    e->want_jit_frank = e->var && jit_ok && !e->zs && (e->var->fa < 0 || e->var->cu < 0) &&
+                        jit_frank_fits(n);
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;

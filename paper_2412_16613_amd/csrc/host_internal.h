@@ -131,8 +131,10 @@ namespace bwg {
 int get_table(bwg_net *n, double mu, const Table **out, bool pinned = true);
 // The network's run-time compiled kernel (compiled on the first call).
 int jit_get(bwg_net *n, const JitKernel **out);
-// The network's compiled Frank-family kernel (compiled on the first call).
+// The network's compiled Frank-family kernel (compiled on the first call),
+// and whether the network fits that kernel's template parameters.
 int jit_frank_get(bwg_net *n, const JitKernel **out);
+bool jit_frank_fits(const bwg_net *n);
 // Budgets of one advance to t_end (no event launches); *kmin/*kmax bound K.
 int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, uint64_t *kmax);
 // Bookkeeping after budgets with K in [kmin, kmax] were drawn.

@@ -236,7 +236,7 @@ int jit_get(bwg_net *n, const JitKernel **out)
 // unless the network is one of the named workloads).  The second shift, if
 // it differs from the first, stays a run-time value as in the precompiled
 // kernels.
-static std::string jit_frank_source(const bwg_net &n, int NB, int BC, int FA, int CU)
+static std::string jit_frank_source(int NB, int BC, int FA, int CU)
 {
     std::ostringstream o;
     o << "#include \"wm_device.h\"\n"
@@ -255,8 +255,32 @@ static std::string jit_frank_source(const bwg_net &n, int NB, int BC, int FA, in
       << "    wm_word_pc<NB, BC, FA, CU, PH>(a, ring, wave_span);\n"
       << "}\n"
       << "}  // namespace bwg\n";
-    (void)n;
     return o.str();
+}
+
+// Template parameters of network n's compiled Frank kernel: count planes,
+// threshold planes (whole Philox quads), product shift, unimolecular weight.
+struct FrankParams {
+    int NB, BC, FA, CU;
+};
+
+static bool frank_params(const bwg_net &n, FrankParams *p)
+{
+    if (!n.shape_ok) return false;
+    const int need_bc = n.q.B + (n.q.max_total == (1ll << n.q.B) ? 1 : 0);
+    const int NB = n.q.b, BC = (need_bc + 3) / 4 * 4;
+    const int fa = n.shape.fa, fi = n.shape.fi;
+    const int FA = fa >= 0 ? fa : (fi >= 0 ? fi : 0);
+    if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || fi >= BC || n.shape.cu > 0x7FFFFFFFu)
+        return false;
+    *p = FrankParams{NB, BC, FA, (int)n.shape.cu};
+    return true;
+}
+
+bool jit_frank_fits(const bwg_net *n)
+{
+    FrankParams p;
+    return frank_params(*n, &p);
 }
 
 // The compiled Frank-family kernel of network n (first call compiles it,
@@ -269,15 +293,11 @@ int jit_frank_get(bwg_net *n, const JitKernel **out)
         *out = n->jit_frank;
         return BWG_OK;
     }
-    if (!n->shape_ok) return fail(BWG_EUNSUPPORTED, "network is not of the Frank family");
-    const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
-    const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
-    const int fa = n->shape.fa, fi = n->shape.fi;
-    const int FA = fa >= 0 ? fa : (fi >= 0 ? fi : 0);
-    if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || fi >= BC || n->shape.cu > 0x7FFFFFFFu)
+    FrankParams p;
+    if (!frank_params(*n, &p))
         return fail(BWG_EUNSUPPORTED, "network beyond the compiled Frank kernel's range");
     JitKernel *k = nullptr;
-    const int rc = jit_compile(jit_frank_source(*n, NB, BC, FA, (int)n->shape.cu), true, &k);
+    const int rc = jit_compile(jit_frank_source(p.NB, p.BC, p.FA, p.CU), true, &k);
     if (rc) return rc;
     n->jit_frank = k;
     *out = k;
