@@ -162,6 +162,12 @@ def test_state_bytes_scale_with_replicas():
     assert _abi.load().bwg_ensemble_state_bytes(n.handle, 0, None, ctypes.byref(b)) == _abi.BWG_EINVAL
 
 
+def test_prepare_refuses_a_null_ensemble():
+    """The entry point that builds a network's run-time compiled Frank kernel
+    ahead of its first launch validates its argument on the host."""
+    assert _abi.load().bwg_ensemble_prepare(None) == _abi.BWG_EINVAL
+
+
 def test_options_are_checked_before_any_device_work():
     """Block sizes beyond the kernels' launch bounds and shared thresholds
     where no kernel implements them are refused by the size query."""
