@@ -179,7 +179,8 @@ typedef struct {
  * Frank-family network whose product shift and unimolecular weight match no
  * precompiled variant runs the Frank kernels compiled for its plane counts
  * and weights; that compile happens at the ensemble's first bit-sliced
- * launch (default block size, per-replica thresholds; batches never run it),
+ * launch (default block size, per-replica or shared thresholds; batches
+ * never run it),
  * which fails with EDEVICE if the compile fails, and gives the results of the
  * precompiled run-time weight kernels.  This flag keeps the precompiled
  * kernels instead. */

@@ -567,9 +567,9 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     // a Frank-family network on a run-time weight variant gets its own
     // compiled kernel, built at its first launch of the bit-sliced engine
     // (batch members never launch alone and never build it); the
-    // precompiled variant stays for the lanes engine, explicit block sizes
-    // and shared thresholds
-    e->want_jit_frank = e->var && jit_ok && !e->zs && (e->var->fa < 0 || e->var->cu < 0) &&
+    // precompiled variant stays for the lanes engine and explicit block
+    // sizes
+    e->want_jit_frank = e->var && jit_ok && (e->var->fa < 0 || e->var->cu < 0) &&
                         jit_frank_fits(n);
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
@@ -758,7 +758,7 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         a.zlen = e->zs ? e->zlen : 0;
         if (a.zs && !a.zlen) return fail(BWG_EINVAL, "shared thresholds not staged");
         const bool frank_jit = e->engine == BWG_ENGINE_BITWISE && e->want_jit_frank &&
-                               e->block <= 0 && !a.zs;
+                               e->block <= 0;
         if (frank_jit && !e->jit_frank) {
             const int jrc = jit_frank_get(e->net, &e->jit_frank);
             if (jrc) return jrc;

@@ -16,8 +16,9 @@
 // Frank-family networks whose product shift and unimolecular weight match
 // no precompiled variant get the hand-written Frank kernels of wm_device.h
 // compiled the same way, with those weights and the network's plane counts
-// as template constants: the results are those of the precompiled run-time
-// weight kernels, at the speed of the named workloads' kernels.
+// as template constants (per-replica and shared thresholds): the results are
+// those of the precompiled run-time weight kernels, at the speed of the named
+// workloads' kernels.
 
 #include <hip/hiprtc.h>
 
@@ -37,6 +38,7 @@ struct JitKernel {
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;  // one thread per word
     hipFunction_t pc = nullptr;  // producer/consumer form
+    hipFunction_t sh = nullptr;  // Frank kernels: one shared threshold per event
     bool frank = false;          // the Frank-family kernel of wm_device.h
 };
 
@@ -201,6 +203,7 @@ static int jit_compile(const std::string &src, bool frank, JitKernel **out)
     hipError_t e = hipModuleLoadData(&k->mod, code.data());
     if (e == hipSuccess) e = hipModuleGetFunction(&k->fn, k->mod, "bwg_jit_word");
     if (e == hipSuccess) e = hipModuleGetFunction(&k->pc, k->mod, "bwg_jit_pc");
+    if (e == hipSuccess && frank) e = hipModuleGetFunction(&k->sh, k->mod, "bwg_jit_sh");
     if (e != hipSuccess) {
         jit_release(k);
         return fail(BWG_EDEVICE, "loading the network's kernel: %s", hipGetErrorString(e));
@@ -246,6 +249,10 @@ static std::string jit_frank_source(int NB, int BC, int FA, int CU)
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_word(WmArgs a)\n"
       << "{\n"
       << "    wm_word<NB, BC, FA, CU, false>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
+      << "}\n"
+      << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_sh(WmArgs a)\n"
+      << "{\n"
+      << "    wm_word<NB, BC, FA, CU, true>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
       << "{\n"
@@ -308,6 +315,14 @@ hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s)
 {
     WmArgs arg = a;
     void *params[] = {&arg};
+    if (a.zs) {
+        // shared thresholds (Frank kernels only): one wave per word, the
+        // block sizes of the precompiled shared-threshold kernels
+        if (!k->sh) return hipErrorInvalidValue;
+        const unsigned block = a.n_words >= 65536 ? 256u : 128u;
+        const unsigned grid = (unsigned)((a.n_words + block - 1) / block);
+        return hipModuleLaunchKernel(k->sh, grid, 1, 1, block, 1, 1, 0, s, params, nullptr);
+    }
     // as for the Frank kernels: the producer/consumer form while the words
     // fill at most one wave per SIMD pair
     if (a.n_words <= 32768) {

@@ -157,12 +157,16 @@ def test_run_time_shift_kernels(torch, n_tot, k0, jit):
 # The compiled kernel in its one-wave-per-word form (more than 32768 words,
 # 256-thread blocks from 65536 on) against the precompiled run-time weight
 # kernel, which the oracle pins above: every count and event counter equal.
-@pytest.mark.parametrize("M", [(1 << 20) + (1 << 16) + 5, (1 << 21) + 33])
-def test_compiled_frank_kernel_equals_precompiled(torch, M):
+# With shared thresholds the compiled kernel is the shared-threshold
+# instantiation (one wave per word at any size).
+@pytest.mark.parametrize("M,shared", [((1 << 20) + (1 << 16) + 5, False), ((1 << 21) + 33, False),
+                                      (4096 + 7, True), ((1 << 20) + 33, True)])
+def test_compiled_frank_kernel_equals_precompiled(torch, M, shared):
     net = frank_network(1024, k0=0.02)
-    sched = [("advance", 0.4), ("step", 77)]
-    a = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, jit=True)
-    b = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, jit=False)
+    sched = [("step", 300), ("step", 77)] if shared else [("advance", 0.4), ("step", 77)]
+    a = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, shared=shared, jit=True)
+    b = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, shared=shared,
+                jit=False)
     for x, y in zip(a[:3], b[:3]):
         np.testing.assert_array_equal(x, y)
 
