@@ -173,7 +173,9 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
     return o.str();
 }
 
-// Compiles src with hipRTC for gfx950 and loads its two kernels.
+// Compiles src with hipRTC for gfx950 and loads its kernels (one wave per
+// word and producer/consumer; for the Frank kernels also the
+// shared-threshold instantiation).
 static int jit_compile(const std::string &src, bool frank, JitKernel **out)
 {
     hiprtcProgram prog;
@@ -233,7 +235,7 @@ int jit_get(bwg_net *n, const JitKernel **out)
     return BWG_OK;
 }
 
-// Source of the Frank-family kernels of wm_device.h for network n with its
+// Source of the Frank-family kernels of wm_device.h for a network with its
 // count and threshold planes, product shift and unimolecular weight as
 // compile-time constants (the precompiled kernels take them at run time
 // unless the network is one of the named workloads).  The second shift, if
