@@ -49,7 +49,11 @@ void jit_release(JitKernel *k)
     delete k;
 }
 
-constexpr int kJitBlock = 128;  // threads per block of the one-wave-per-word kernel
+// threads per block of the one-wave-per-word kernels: 128 below 65 536
+// words, 256 from there (measured 1.3-1.5x on general networks at 2^21 and
+// 2^22 replicas; 128-thread blocks are placed unevenly there), as for the
+// precompiled Frank kernels
+constexpr int kJitBlockSmall = 128, kJitBlockLarge = 256;
 constexpr int kJitPcHalf = 4;   // events per ring half of the producer/consumer kernel
 
 // Source of network n's kernels with NB count planes and BC threshold planes:
@@ -157,7 +161,7 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
     }
     o << "    }\n"
       << "};\n"
-      << "extern \"C\" __global__ __launch_bounds__(" << kJitBlock
+      << "extern \"C\" __global__ __launch_bounds__(" << kJitBlockLarge
       << ") void bwg_jit_word(WmArgs a)\n"
       << "{\n"
       << "    gen_word<NB, BC>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, NetEvent{});\n"
@@ -331,9 +335,8 @@ hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s)
         const unsigned grid = (unsigned)((a.n_words + 127) / 128);
         return hipModuleLaunchKernel(k->pc, grid, 1, 1, 256, 1, 1, 0, s, params, nullptr);
     }
-    // Frank kernels: 256-thread blocks from 65 536 words on, as for the
-    // precompiled ones (128-thread blocks are placed unevenly there)
-    const unsigned block = (k->frank && a.n_words >= 65536) ? 256u : (unsigned)kJitBlock;
+    const unsigned block =
+        (unsigned)(a.n_words >= 65536 ? kJitBlockLarge : kJitBlockSmall);
     const unsigned grid = (unsigned)((a.n_words + block - 1) / block);
     return hipModuleLaunchKernel(k->fn, grid, 1, 1, block, 1, 1, 0, s, params, nullptr);
 }

@@ -130,6 +130,21 @@ def test_large_ensemble_sampled(torch, jit):
         np.testing.assert_array_equal(counts[first:first + count], o.counts)
 
 
+# The compiled kernel's one-wave-per-word form with 256-thread blocks (from
+# 65536 words) against the precompiled general kernel, which the oracle pins.
+def test_compiled_kernel_large_blocks_equal_precompiled(torch):
+    net = random_network(8, 400, 5)
+    M = (1 << 21) + 5
+    res = []
+    for jit in (True, False):
+        e = bwg.Ensemble(bwg.Network(net), M, seed=3, net_id=9, jit=jit)
+        e.init(("multinomial",)).step(150)
+        ev, real = e.read_events()
+        res.append((e.read_counts().cpu().numpy(), ev.cpu().numpy(), real.cpu().numpy()))
+    for x, y in zip(*res):
+        np.testing.assert_array_equal(x, y)
+
+
 def _table(reactions, rates, n_tot, integer=True):
     from workloads.frank import _net
     return _net(reactions, rates, n_tot, exact_integer=integer)
