@@ -280,6 +280,65 @@ def test_time_mode_matches_master_equation(oracle_lib):
     assert chi2_pvalue(_empirical(E.counts, st), probs * 16384) > 1e-4
 
 
+# ---- the comparator's draws (PLAIN domain: one replica per thread) ----------
+# The plain engine samples the same uniformised chain with its own draws: the
+# low B bits of output (e mod 4) of the call keyed by e // 4.  Its law is
+# pinned here directly, not by comparison with another implementation.
+
+def test_plain_draw_fixed_k_matches_exact_master_equation(oracle_lib):
+    # two steps whose lengths are not multiples of 4, so events of one
+    # Philox call straddle the steps
+    net = frank_network(8, k0=0.05)
+    q = quantize(net)
+    E = ssa.OracleEnsemble(net, 16384, seed=3, draw=ssa.DRAW_PLAIN)
+    E.init(("fixed", (0, 0, 8)))
+    E.step(151)
+    E.step(150)
+    st, probs = master.fixed_k_probs(net, q, (0, 0, 8), 301)
+    assert chi2_pvalue(_empirical(E.counts, st), probs * 16384) > 1e-4
+
+
+def test_plain_draw_time_mode_matches_master_equation(oracle_lib):
+    net = frank_network(10, k0=0.05)
+    q = quantize(net)
+    E = ssa.OracleEnsemble(net, 16384, seed=4, draw=ssa.DRAW_PLAIN)
+    E.init(("fixed", (0, 0, 10)))
+    E.advance(4.0)
+    E.advance(9.0)
+    st, probs = master.time_probs(net, q, {(0, 0, 10): 1.0}, 9.0)
+    assert chi2_pvalue(_empirical(E.counts, st), probs * 16384) > 1e-4
+
+
+def test_plain_draw_paper_network_master_equation(oracle_lib):
+    # unit weights, ghosts: B = 6 at N = 10, so every bit of n matters
+    n = 10
+    net = paper_network(n)
+    q = quantize(net)
+    E = ssa.OracleEnsemble(net, 16384, seed=15, draw=ssa.DRAW_PLAIN)
+    E.init(("fixed", (3, 3, 4)))
+    E.step(37)
+    st, probs = master.fixed_k_probs(net, q, (3, 3, 4), 37)
+    assert chi2_pvalue(_empirical(E.counts, st), probs * 16384) > 1e-4
+
+
+@pytest.mark.parametrize("B", [5, 12, 23, 32])
+def test_plain_threshold_is_uniform_and_independent(B):
+    # uniform on [0, 2^B) in its top bits (a dropped top plane fails), and
+    # independent between consecutive events of one call, across calls and
+    # across replicas (reusing one output word, one call or one replica's
+    # stream fails)
+    R, K = 64, 64
+    v = np.array([[ssa._ph.plain_threshold(9, 2, i, e, B) for e in range(K)]
+                  for i in range(R)], dtype=np.int64)
+    assert v.max() < (1 << B)
+    top = v >> (B - 3)
+    assert chi2_pvalue(np.bincount(top.ravel(), minlength=8), np.full(8, R * K / 8)) > 1e-4
+    for a, b in ((top[:, :-1], top[:, 1:]), (top[:, :-4], top[:, 4:]),
+                 (top[:-1, :], top[1:, :])):
+        joint = np.bincount((8 * a + b).ravel(), minlength=64)
+        assert chi2_pvalue(joint, np.full(64, a.size / 64)) > 1e-4
+
+
 def test_paper_network_master_equation_from_multinomial(oracle_lib):
     # Paper-exact network, multinomial racemic start, fixed number of events.
     n = 10
