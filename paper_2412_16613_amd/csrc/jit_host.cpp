@@ -240,41 +240,42 @@ int jit_get(bwg_net *n, const JitKernel **out)
 }
 
 // Source of the Frank-family kernels of wm_device.h for a network with its
-// count and threshold planes, product shift and unimolecular weight as
+// count and threshold planes, product shifts and unimolecular weight as
 // compile-time constants (the precompiled kernels take them at run time
-// unless the network is one of the named workloads).  The second shift, if
-// it differs from the first, stays a run-time value as in the precompiled
-// kernels.
-static std::string jit_frank_source(int NB, int BC, int FA, int CU)
+// unless the network is one of the named workloads): FA shifts the A + L and
+// A + D weights, FI the L + D weight.
+static std::string jit_frank_source(int NB, int BC, int FA, int FI, int CU)
 {
     std::ostringstream o;
     o << "#include \"wm_device.h\"\n"
       << "namespace bwg {\n"
-      << "constexpr int NB = " << NB << ", BC = " << BC << ", FA = " << FA << ", CU = " << CU
-      << ";\n"
+      << "constexpr int NB = " << NB << ", BC = " << BC << ", FA = " << FA << ", FI = " << FI
+      << ", CU = " << CU << ";\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_word(WmArgs a)\n"
       << "{\n"
-      << "    wm_word<NB, BC, FA, CU, false>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
+      << "    wm_word<NB, BC, FA, CU, false, FI>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_sh(WmArgs a)\n"
       << "{\n"
-      << "    wm_word<NB, BC, FA, CU, true>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
+      << "    wm_word<NB, BC, FA, CU, true, FI>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
       << "{\n"
       << "    constexpr int PH = BC == 20 ? 6 : 4;\n"
       << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
       << "    __shared__ uint64_t wave_span[4];\n"
-      << "    wm_word_pc<NB, BC, FA, CU, PH>(a, ring, wave_span);\n"
+      << "    wm_word_pc<NB, BC, FA, CU, PH, FI>(a, ring, wave_span);\n"
       << "}\n"
       << "}  // namespace bwg\n";
     return o.str();
 }
 
 // Template parameters of network n's compiled Frank kernel: count planes,
-// threshold planes (whole Philox quads), product shift, unimolecular weight.
+// threshold planes (whole Philox quads), the two product shifts (A + L and
+// A + D; L + D), unimolecular weight.  A shift whose reactions are absent
+// takes the other one's value (its subtraction is never run).
 struct FrankParams {
-    int NB, BC, FA, CU;
+    int NB, BC, FA, FI, CU;
 };
 
 static bool frank_params(const bwg_net &n, FrankParams *p)
@@ -284,9 +285,10 @@ static bool frank_params(const bwg_net &n, FrankParams *p)
     const int NB = n.q.b, BC = (need_bc + 3) / 4 * 4;
     const int fa = n.shape.fa, fi = n.shape.fi;
     const int FA = fa >= 0 ? fa : (fi >= 0 ? fi : 0);
-    if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || fi >= BC || n.shape.cu > 0x7FFFFFFFu)
+    const int FI = fi >= 0 ? fi : FA;
+    if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || FI >= BC || n.shape.cu > 0x7FFFFFFFu)
         return false;
-    *p = FrankParams{NB, BC, FA, (int)n.shape.cu};
+    *p = FrankParams{NB, BC, FA, FI, (int)n.shape.cu};
     return true;
 }
 
@@ -310,7 +312,7 @@ int jit_frank_get(bwg_net *n, const JitKernel **out)
     if (!frank_params(*n, &p))
         return fail(BWG_EUNSUPPORTED, "network beyond the compiled Frank kernel's range");
     JitKernel *k = nullptr;
-    const int rc = jit_compile(jit_frank_source(p.NB, p.BC, p.FA, p.CU), true, &k);
+    const int rc = jit_compile(jit_frank_source(p.NB, p.BC, p.FA, p.FI, p.CU), true, &k);
     if (rc) return rc;
     n->jit_frank = k;
     *out = k;

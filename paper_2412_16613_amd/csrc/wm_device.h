@@ -275,9 +275,10 @@ __device__ __forceinline__ uint32_t live_lanes(const WmArgs &a, uint64_t w)
 
 // One word (32 replicas) of an ensemble: run its pending events.
 // NB count planes, BC = 4 * (quads of threshold planes), FA product shift
-// (-1: run time), CU unimolecular weight (-1: run time); SH: one shared
-// threshold per event (a.zs != 0) instead of per-replica draws.
-template <int NB, int BC, int FA, int CU, bool SH = false>
+// of the A + L and A + D weights and FI that of the L + D weight (-1: run
+// time), CU unimolecular weight (-1: run time); SH: one shared threshold per
+// event (a.zs != 0) instead of per-replica draws.
+template <int NB, int BC, int FA, int CU, bool SH = false, int FI = FA>
 __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
 {
     static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
@@ -356,7 +357,7 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
 // the events of half (s-1) mod 2, and a barrier separates the steps.  The
 // step count is the workgroup's largest window, so every wave meets every
 // barrier.  Results are those of wm_word.
-template <int NB, int BC, int FA, int CU, int PH>
+template <int NB, int BC, int FA, int CU, int PH, int FI = FA>
 __device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4][64],
                                            uint64_t *wave_span)
 {

@@ -154,15 +154,37 @@ def test_run_time_shift_kernels(torch, n_tot, k0, jit):
                  net_id=n_tot, jit=jit)
 
 
+# Frank networks whose L + D rate differs from the A + L / A + D rate: the two
+# product shifts differ (k2 = k1 / 4: the L + D weight is 2^(f-2) P_LD;
+# k2 = 2 k1: the A + L, A + D weights are 2^(f-1) P), so the L + D
+# subtraction must use its own shift in the compiled kernels (per-replica,
+# producer/consumer and shared-threshold forms) and in the precompiled
+# run-time kernels alike.
+@pytest.mark.parametrize("shared,block", [(False, 0), (False, 128), (True, 0)])
+@pytest.mark.parametrize("jit", [True, False])
+@pytest.mark.parametrize("n_tot,k0,r2", [(64, 0.01, 0.25), (64, 0.01, 2.0), (300, 0.002, 0.25),
+                                         (1000, 0.02, 2.0), (40, 0.05, 1.0)])
+def test_unequal_product_shifts(torch, n_tot, k0, r2, jit, shared, block):
+    net = frank_network(n_tot, k0=k0, k2=r2 / n_tot)
+    q = bwg.Network(net).quantized()
+    c = q["c"]
+    assert (c[4] == 2 * c[2]) if r2 == 2.0 else (c[2] == 4 * c[4]) if r2 == 0.25 else c[2] == c[4]
+    check_parity(torch, net, 700, ("multinomial",), [("advance", 2.0), ("step", 50)], seed=14,
+                 net_id=n_tot + 1, jit=jit, shared=shared, block=block)
+
+
 # The compiled kernel in its one-wave-per-word form (more than 32768 words,
 # 256-thread blocks from 65536 on) against the precompiled run-time weight
 # kernel, which the oracle pins above: every count and event counter equal.
 # With shared thresholds the compiled kernel is the shared-threshold
 # instantiation (one wave per word at any size).
-@pytest.mark.parametrize("M,shared", [((1 << 20) + (1 << 16) + 5, False), ((1 << 21) + 33, False),
-                                      (4096 + 7, True), ((1 << 20) + 33, True)])
-def test_compiled_frank_kernel_equals_precompiled(torch, M, shared):
-    net = frank_network(1024, k0=0.02)
+@pytest.mark.parametrize("M,shared,r2", [((1 << 20) + (1 << 16) + 5, False, 1.0),
+                                         ((1 << 21) + 33, False, 1.0),
+                                         ((1 << 20) + (1 << 16) + 5, False, 0.25),
+                                         (4096 + 7, True, 1.0), ((1 << 20) + 33, True, 1.0),
+                                         ((1 << 20) + 33, True, 2.0)])
+def test_compiled_frank_kernel_equals_precompiled(torch, M, shared, r2):
+    net = frank_network(1024, k0=0.02, k2=r2 / 1024)
     sched = [("step", 300), ("step", 77)] if shared else [("advance", 0.4), ("step", 77)]
     a = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, shared=shared, jit=True)
     b = gpu_run(torch, net, M, ("multinomial",), sched, seed=8, net_id=5, shared=shared,
