@@ -174,7 +174,9 @@ def main():
         st = ens.stats()
         assert int(hist.sum().item()) == M
         return dict(ms=ms, wall=wall, adv_ms=adv_ms, events=st["events_total"],
-                    real=st["real_total"], kt_ms=kt_ms, kt_n=kt_n)
+                    real=st["real_total"], kt_ms=kt_ms, kt_n=kt_n,
+                    counts=counts.cpu().numpy(), hist=hist.cpu().numpy(),
+                    ev=ens.read_events()[0].cpu().numpy())
 
     r = run("bitwise", args.steps, args.warmup)
     ms_step = r["ms"] / args.steps
@@ -220,9 +222,23 @@ def main():
         out["plain_ssa"] = {"value": pv, "unit": "replica-events/s",
                             "ms_per_step": p["ms"] / max(1, args.steps // 2),
                             "bitwise_over_plain": value / pv}
+    # every replica: histogram of the last step's counts by the integer rule
+    from oracle import ssa
+    hist_ok = bool(np.array_equal(r["hist"].astype(np.uint64),
+                                  ssa.ee_histogram(r["counts"], net["n_tot"], 256)))
+    out["parity"] = hist_ok
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(net, c, args.cpu_replicas)
+        cb, orc = cpu_baseline(net, c, args.cpu_replicas)
+        n = orc.n
+        same = (np.array_equal(r["counts"][:n], orc.counts) and
+                np.array_equal(r["ev"][:n].astype(np.uint64), orc.E))
+        cb["parity"] = {"replicas": n, "bit_exact": bool(same)}
+        out["cpu_baseline"] = cb
+        out["parity"] = hist_ok and same
     print(json.dumps(out))
+    if not out["parity"]:
+        print("parity failure: GPU counts differ from the oracle", file=sys.stderr)
+        sys.exit(1)
 
 
 def lattice_slots(q, li):
@@ -317,24 +333,43 @@ def bench_lattice(args):
                      "slots_per_word_event": slots,
                      "slots_reaction": react, "slots_hop": hop},
     }
+    out["parity"] = True
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_lattice(c, args.cpu_replicas_lattice)
+        cb, orc = cpu_baseline_lattice(c, args.cpu_replicas_lattice)
+        # the last step's state of the sampled replicas, site by site
+        got = np.stack([ens.read_sites(orc.first + k * orc.stride, 1).cpu().numpy()[0]
+                        for k in range(orc.n)])
+        ev = ens.read_events()[0].cpu().numpy().astype(np.uint64)
+        same = (np.array_equal(got, orc.sites) and
+                np.array_equal(ev[orc.first::orc.stride][:orc.n], orc.E))
+        cb["parity"] = {"replicas": orc.n, "stride": orc.stride, "bit_exact": bool(same)}
+        out["cpu_baseline"] = cb
+        out["parity"] = bool(same)
     print(json.dumps(out))
+    if not out["parity"]:
+        print("parity failure: GPU sites differ from the oracle", file=sys.stderr)
+        sys.exit(1)
 
 
 def cpu_baseline_lattice(c, n_rep):
+    """The lattice oracle on n_rep replicas spread evenly over the ensemble
+    (every component group and both launch bands of the 64 x 64 workload);
+    returns the report and the oracle (for the parity check)."""
     from oracle.lattice import OracleLattice
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    stride = max(1, c["replicas"] // n_rep)
     o = OracleLattice(c["net"], c["replicas"], seed=c["seed"], net_id=c["net_id"], first=0,
-                      count=n_rep, threads=threads)
+                      count=n_rep, stride=stride, threads=threads)
     o.init(c["init"])
     t = time.perf_counter()
     o.advance(c["t_end"])
     dt = time.perf_counter() - t
     ev = int(o.E.sum())
-    return {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d replicas, full t_end (%d events, %.1f s)"
-                      % (n_rep, c["replicas"], ev, dt)}
+    out = {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
+           "sample": "%d of %d replicas (every %d-th), full t_end (%d events, %.1f s)"
+                     % (n_rep, c["replicas"], stride, ev, dt)}
+    out.update(cpu_model())
+    return out, o
 
 
 def bench_batch(args):
@@ -383,10 +418,16 @@ def bench_batch(args):
         ev = sum(e.stats()["events_total"] for e in ens)
         res[tag] = {"s": dt, "replica_events_per_s": ev / dt, "networks": len(members),
                     "lanes_members": len(tn["lanes"])}
-        return ev
+        return ev, ens
 
-    events = run_batched(cfg, "batched")
-    ev_sub = run_batched(sub, "batched_subset")
+    events, batched_ens = run_batched(cfg, "batched")
+    # the first two words (64 replicas) of every network of the batch against
+    # the oracle, which is timed on them as the CPU baseline
+    first = [(e.read_counts()[:64].cpu().numpy(),
+              e.read_events()[0][:64].cpu().numpy().astype(np.uint64)) for e in batched_ens]
+    del batched_ens
+    cb, parity = cpu_baseline_batch(cfg, first)
+    ev_sub, _ = run_batched(sub, "batched_subset")
     for engine in ("bitwise", "plain"):
         ens = make(engine, sub)
         for e in ens:
@@ -411,8 +452,41 @@ def bench_batch(args):
                res["one_per_launch_plain"]["replica_events_per_s"],
            "speedup_vs_bitwise_one_per_launch":
                res["batched_subset"]["replica_events_per_s"] /
-               res["one_per_launch_bitwise"]["replica_events_per_s"]}
+               res["one_per_launch_bitwise"]["replica_events_per_s"],
+           "parity": parity, "cpu_baseline": cb}
     print(json.dumps(out))
+    if not parity:
+        print("parity failure: batched GPU counts differ from the oracle", file=sys.stderr)
+        sys.exit(1)
+
+
+def cpu_baseline_batch(cfg, gpu_first):
+    """The oracle on the first 64 replicas of every network of the batch,
+    compared bit for bit with the GPU's (counts, events) in gpu_first."""
+    from oracle import ssa
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    ssa.lib()
+    ev = 0
+    dt = 0.0
+    bad = []
+    for k, (c, (gc, ge)) in enumerate(zip(cfg, gpu_first)):
+        n = min(64, c["replicas"])
+        E = ssa.OracleEnsemble(c["net"], c["replicas"], seed=c["seed"], net_id=c["net_id"],
+                               first=0, count=n, threads=threads)
+        E.init(c["init"])
+        t = time.perf_counter()
+        E.advance(c["t_end"])
+        dt += time.perf_counter() - t
+        ev += int(E.E.sum())
+        if not (np.array_equal(gc[:n], E.counts) and np.array_equal(ge[:n], E.E)):
+            bad.append(k)
+    out = {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
+           "sample": "first 64 replicas of each of the %d networks, full t_end (%d events, "
+                     "%.1f s)" % (len(cfg), ev, dt),
+           "parity": {"networks": len(cfg), "replicas_each": 64, "bit_exact": not bad,
+                      "mismatched_networks": bad[:16]}}
+    out.update(cpu_model())
+    return out, not bad
 
 
 def bench_serve(args):
@@ -631,8 +705,23 @@ def bench_trajectory(args):
     print(json.dumps(out))
 
 
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo) and logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": name, "host_logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(net, c, n_rep):
-    """The CPU oracle on the first n_rep replicas of the same workload."""
+    """The CPU oracle on the first n_rep replicas of the same workload;
+    returns the report and the oracle ensemble (for the parity check)."""
     from oracle import ssa
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     ssa.lib()
@@ -643,9 +732,11 @@ def cpu_baseline(net, c, n_rep):
     E.advance(c["t_end"])
     dt = time.perf_counter() - t
     ev = int(E.E.sum())
-    return {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d replicas, full t_end (%d events, %.1f s)"
-                      % (n_rep, c["replicas"], ev, dt)}
+    out = {"value": ev / dt, "unit": "replica-events/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d of %d replicas, full t_end (%d events, %.1f s)"
+                     % (n_rep, c["replicas"], ev, dt)}
+    out.update(cpu_model())
+    return out, E
 
 
 if __name__ == "__main__":

@@ -138,6 +138,34 @@ def test_uneven_batch_workload_sample(torch):
     _assert_same(_state(torch, batched), _state(torch, alone))
 
 
+def test_full_uneven_batch_first_words_match_oracle(torch):
+    """The whole uneven batch (256 networks, full replica counts and
+    horizons) in one persistent launch: the first two words (64 replicas)
+    of every network against the oracle, counts and events per replica."""
+    cfg = batch_networks()
+    _say("case full uneven batch", len(cfg))
+    ens = []
+    for c in cfg:
+        e = bwg.Ensemble(bwg.Network(c["net"]), c["replicas"], seed=c["seed"],
+                         net_id=c["net_id"])
+        e.init(c["init"])
+        ens.append(e)
+    bwg.Batch(ens).advance([c["t_end"] for c in cfg])
+    first = [(e.read_counts()[:64].cpu().numpy(), e.read_events()[0][:64].cpu().numpy())
+             for e in ens]
+    torch.cuda.synchronize()
+    bad = []
+    for k, (c, (gc, ge)) in enumerate(zip(cfg, first)):
+        n = min(64, c["replicas"])
+        o = ssa.OracleEnsemble(c["net"], c["replicas"], seed=c["seed"], net_id=c["net_id"],
+                               first=0, count=n)
+        o.init(c["init"])
+        o.advance(c["t_end"])
+        if not (np.array_equal(gc[:n], o.counts) and np.array_equal(ge[:n].astype(np.uint64), o.E)):
+            bad.append(k)
+    assert not bad, "networks whose first words differ from the oracle: %s" % bad[:16]
+
+
 def test_batch_with_lanes_members_equals_alone(torch):
     """Members on the lanes engine (2-word items, one replica per thread)
     beside bit-sliced members give the same results as each alone."""

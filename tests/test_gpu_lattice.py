@@ -177,15 +177,19 @@ def test_full_lattice_short_horizon_sampled():
 
 
 def test_full_lattice_bench_configuration_sampled():
-    """The bench workload: init + advance to t_end = 20 on 2^16 replicas;
-    four replicas from different groups and words are checked."""
+    """The bench workload: init + advance to t_end = 20 on 2^16 replicas.
+    64 replicas one every 1024 (two from each of the 32 component groups,
+    both launch bands of 16 groups, different words and lanes) and the last
+    two replicas are checked site by site, with their event counts."""
     c = config("c2")
     M = c["replicas"]
-    ens, orc = pair(c["net"], M, seed=c["seed"], net_id=c["net_id"], init=c["init"],
-                    first=M - 1, count=1)
-    ens.advance(c["t_end"])
-    for i in (0, 2047, 33333, M - 1):
-        o = OracleLattice(c["net"], M, seed=c["seed"], net_id=c["net_id"], first=i, count=1)
+    ens = bwg.Ensemble(bwg.Network(c["net"]), M, seed=c["seed"], net_id=c["net_id"])
+    ens.init(c["init"]).advance(c["t_end"])
+    ev = ens.read_events()[0].cpu().numpy().astype(np.uint64)
+    for first, count, stride in ((5, 64, 1024), (M - 2, 2, 1)):
+        o = OracleLattice(c["net"], M, seed=c["seed"], net_id=c["net_id"], first=first,
+                          count=count, stride=stride, threads=16)
         o.init(c["init"])
         o.advance(c["t_end"])
-        check(ens, o, "64x64, t=20, replica %d" % i)
+        check(ens, o, "64x64, t=20, replicas %d + k * %d" % (first, stride))
+        np.testing.assert_array_equal(ev[first::stride][:count], o.E)

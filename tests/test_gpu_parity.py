@@ -301,11 +301,14 @@ def test_full_size_well_mixed_workload_sampled(torch):
     table = poisson_table(q["Lambda"] * c["t_end"])
     K = ssa.budgets(0, 0, 0, 0, M, table)
     np.testing.assert_array_equal(ev, K)
-    for first in (0, 1 << 19, M - 32, 777 * 32 + 5):
-        E = ssa.OracleEnsemble(net, M, first=first, count=16)
+    # the first 2^14 replicas (512 words: four producer/consumer workgroups)
+    # and blocks spread over the rest, counts and events per replica
+    for first, count in ((0, 1 << 14), (1 << 19, 64), (M - 64, 64), (777 * 32 + 5, 16)):
+        E = ssa.OracleEnsemble(net, M, first=first, count=count)
         E.init(c["init"])
         E.advance(c["t_end"])
-        np.testing.assert_array_equal(counts[first:first + 16], E.counts)
+        np.testing.assert_array_equal(counts[first:first + count], E.counts)
+        np.testing.assert_array_equal(ev[first:first + count], E.E)
 
 
 # ---- lanes engine: one replica per thread on the bit-plane state ------------
