@@ -361,6 +361,33 @@ int bwg_ensemble_set_lanes_words(bwg_ens *ens, uint64_t n_words);
 /* Synchronises the stream and reports totals. */
 int bwg_ensemble_stats(bwg_ens *ens, void *stream, bwg_stats *out);
 
+/* ---- allocation-free run ------------------------------------------------ */
+
+/* Bytes of the library's static device array that holds the state of a
+ * bwg_ensemble_step_static run (one array per GPU, held until the process
+ * ends). */
+#define BWG_STATIC_STATE_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid allocation): the same as
+ * creating a bit-sliced ensemble of n_replicas of a well-mixed network
+ * (seed, net_id), bwg_ensemble_init(BWG_INIT_FIXED, counts), bwg_ensemble_step
+ * (n_events) and bwg_ensemble_read_counts(dev_counts), with the ensemble's
+ * device state in the library's static array instead of a caller buffer and
+ * the precompiled kernels only (BWG_OPT_NO_JIT): the results are those of
+ * that sequence.  counts[S] is a host array summing to n_tot; dev_counts is a
+ * caller-owned device array of n_replicas * S int32 (species order of the
+ * network).  No device or pinned memory is allocated and nothing is
+ * compiled.  ERANGE if the state of n_replicas exceeds BWG_STATIC_STATE_BYTES
+ * (e.g. about 3 * 10^6 replicas at 11 count planes); EUNSUPPORTED for
+ * lattices.  Every call on one GPU uses that GPU's one array, so calls that
+ * overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller; a call leaves its state in the array, and the
+ * next call rewrites every word it reads before reading it.  Async. */
+int bwg_ensemble_step_static(const bwg_net *net, uint64_t n_replicas, uint64_t seed,
+                             uint32_t net_id, const int32_t *counts, uint64_t n_events,
+                             int32_t *dev_counts, void *stream);
+
 void bwg_ensemble_destroy(bwg_ens *ens);
 
 /* ---- batches: many ensembles in one persistent launch ------------------- */

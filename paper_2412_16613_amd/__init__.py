@@ -97,6 +97,23 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
 
 
+def step_static(network, n_replicas, counts, n_events, seed=0, net_id=0, out=None,
+                device="cuda"):
+    """bwg_ensemble_step_static: n_replicas from the fixed start counts, run
+    n_events each with the ensemble state in the library's static device
+    array (no allocation inside the call); returns the counts, int32
+    [n_replicas, S], in out if given (a contiguous device tensor)."""
+    import torch
+    dev = torch.device(device)
+    S = len(network.net["species"])
+    if out is None:
+        out = torch.empty((int(n_replicas), S), dtype=torch.int32, device=dev)
+    _abi.check(_lib().bwg_ensemble_step_static(
+        network.handle, int(n_replicas), int(seed), int(net_id), _i32arr(counts), int(n_events),
+        ctypes.c_void_p(out.data_ptr()), _stream_ptr(torch.cuda.current_stream(dev))))
+    return out
+
+
 class Ensemble:
     """Replicas of one network in a caller-owned device buffer."""
 

@@ -42,8 +42,9 @@ SYMBOLS = (
     "bwg_batch_capacity_bytes", "bwg_batch_set_members", "bwg_batch_run",
     "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
     "bwg_ensemble_kernel_time", "bwg_ensemble_set_engine", "bwg_ensemble_set_lanes_words",
-    "bwg_ensemble_record", "bwg_ensemble_prepare",
+    "bwg_ensemble_record", "bwg_ensemble_prepare", "bwg_ensemble_step_static",
 )
+BWG_STATIC_STATE_BYTES = 64 << 20
 
 
 class NetDesc(ctypes.Structure):
@@ -145,6 +146,7 @@ def load():
         "bwg_ensemble_prepare": (i32, [vp]),
         "bwg_ensemble_set_lanes_words": (i32, [vp, u64]),
         "bwg_ensemble_record": (i32, [vp, P(ctypes.c_double), u32, vp, u32, vp, i32, vp, vp]),
+        "bwg_ensemble_step_static": (i32, [vp, u64, u64, u32, P(i32), u64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -538,6 +538,19 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
         return fail(BWG_ENOMEM, "buffer of %llu bytes, need %llu", (unsigned long long)buf_bytes,
                     (unsigned long long)need);
     auto e = new bwg_ens();
+    rc = ens_bind(e, n, M, seed, net_id, dev_buf, buf_bytes, o);
+    if (rc) {
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return BWG_OK;
+}
+
+// Fill ensemble e (fresh) for a validated buffer of at least the state bytes.
+int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint32_t net_id,
+                  void *dev_buf, uint64_t buf_bytes, const bwg_opts *o)
+{
     e->net = const_cast<bwg_net *>(n);
     e->M = M;
     e->seed = seed;
@@ -550,19 +563,12 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->zs = (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) ? (uint32_t)n->q.z_shared : 0;
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
-    if (n->lat) {
-        lat_bind(e);
-        *out = e;
-        return BWG_OK;
-    }
+    if (n->lat) return lat_bind(e);
     check_engine(n, e->engine, &e->var, &e->gvar, o && (o->flags & BWG_OPT_GENERIC_KERNEL));
     const bool jit_ok = !(o && (o->flags & BWG_OPT_NO_JIT));
     if (e->gvar && jit_ok) {
-        rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
-        if (rc) {
-            delete e;
-            return rc;
-        }
+        const int rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
+        if (rc) return rc;
     }
     // a Frank-family network on a run-time weight variant gets its own
     // compiled kernel, built at its first launch of the bit-sliced engine
@@ -586,7 +592,6 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
     e->table = (uint64_t *)(e->buf + L.table);
     e->scratch = (uint64_t *)(e->buf + L.scratch);
     e->adv_dev = e->scratch + 8;
-    *out = e;
     return BWG_OK;
 }
 

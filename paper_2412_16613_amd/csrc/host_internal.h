@@ -126,6 +126,11 @@ struct bwg_ens {
 
 
 namespace bwg {
+// Bind a fresh ensemble e to dev_buf (validated: aligned, at least the state
+// bytes of M replicas under o); what bwg_ensemble_create does after its
+// checks, without allocating e.
+int ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint32_t net_id,
+             void *dev_buf, uint64_t buf_bytes, const bwg_opts *o);
 // Cached Poisson table for mean mu (lives as long as the network); with
 // pinned, also its pinned copy for uploads to the device.
 int get_table(bwg_net *n, double mu, const Table **out, bool pinned = true);
