@@ -232,14 +232,22 @@ int bwg_poisson_table(double mu, int64_t *k_lo, uint64_t *table, uint64_t cap,
 
 /* ---- ensembles ---------------------------------------------------------- */
 
-/* Device bytes an ensemble of n_replicas needs (opts may be NULL). */
+/* Device bytes an ensemble of n_replicas needs (opts may be NULL): the bit
+ * planes of every species count (Sec. 4, Eqs. (15)-(19): plane q holds bit q
+ * of the counts of 32 replicas, 32 * ceil(n_replicas / 32) lanes, words
+ * padded to multiples of 64), the per-replica event counters and the Poisson
+ * table region.  EINVAL for n_replicas = 0 or >= 2^32 or a bad block size;
+ * EUNSUPPORTED when no kernel of the chosen engine runs the network. */
 int bwg_ensemble_state_bytes(const bwg_net *net, uint64_t n_replicas,
                              const bwg_opts *opts, uint64_t *bytes);
 
-/* Bind an ensemble to a caller buffer.  seed and net_id key every random
- * draw (Philox4x32-10 counters); replicas of equal (seed, net_id, index)
- * see identical draws in any ensemble, batch or word width.  No device work
- * is enqueued.  ENOMEM if buf_bytes is below bwg_ensemble_state_bytes. */
+/* Bind an ensemble of M copies of the network (the paper's M replicas of one
+ * network sharing N_tot, Sec. 4) to a caller buffer (device, 256-byte
+ * aligned, owned by the caller, which must outlive the ensemble).  seed and
+ * net_id key every random draw (Philox4x32-10 counters); replicas of equal
+ * (seed, net_id, index) see identical draws in any ensemble, batch or word
+ * width.  No device work is enqueued.  ENOMEM if buf_bytes is below
+ * bwg_ensemble_state_bytes; EINVAL for a null or misaligned buffer. */
 int bwg_ensemble_create(const bwg_net *net, uint64_t n_replicas, uint64_t seed,
                         uint32_t net_id, void *dev_buf, uint64_t buf_bytes,
                         const bwg_opts *opts, bwg_ens **out);
@@ -285,10 +293,15 @@ int bwg_ensemble_pending(const bwg_ens *ens, uint64_t *bound);
 int bwg_ensemble_step(bwg_ens *ens, uint64_t n_events, void *stream);
 
 /* Counts of every replica: dev_dst[i*S + x], int32, species order of the
- * network; on a lattice the species totals over all sites.  Async. */
+ * network; on a lattice the species totals over all sites.  This reads the
+ * integers N = sum_q b_q 2^q back out of the bit planes (Eqs. (15)-(19)), the
+ * occupancies whose trajectories the paper plots (Sec. 5).  dev_dst is a
+ * caller-owned device array of n_replicas * S int32.  Async. */
 int bwg_ensemble_read_counts(bwg_ens *ens, int32_t *dev_dst, void *stream);
 
-/* Histogram of the enantiomeric excess (N_L - N_D)/N_tot over replicas:
+/* Histogram over replicas of the enantiomeric excess (N_L - N_D)/N_tot,
+ * the chiral order parameter of the Frank model (Sec. 2; its spread over
+ * copies is what the paper's trajectory figure shows, Sec. 5):
  * bin = min(n_bins-1, floor((N_L - N_D + N_tot) n_bins / (2 N_tot))),
  * dev_dst[n_bins] uint64 (overwritten).  Frank species only.  On a lattice
  * N_L, N_D are totals over sites and N_tot is the replica's molecule count
