@@ -22,36 +22,92 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue slots per word-event (32 replica-events) the bit-sliced method
-# needs for a network with b count planes, B threshold planes and product
-# shift f: Philox calls, selection chains, occupancy and product updates,
-# the unimolecular weight and the real-event count (word_event_slots).
-PHILOX_SLOTS = 100          # 20 32x32->64 multiplies at 4 slots + 20 xor3
+# VALU issue slots per word-event (32 replica-events) that the bit-sliced method needs, in
+# the form the well-mixed kernel computes it (word_event_slots).  One slot is one 32-bit VALU
+# instruction per lane; v_mad_u64_u32 issues at the same rate as v_bitop3_b32 (--valu-ref).
+PHILOX_SLOTS = 40           # 20 32x32->64 multiply-adds + 20 three-input xors per call
 
 
-def word_event_slots(b, B, f, cu_bits):
+def _bitlen(v):
+    return int(v).bit_length()
+
+
+def _signed_width(lo, hi):
+    return max(2, _bitlen(max(hi, -lo - 1)) + 1)
+
+
+def word_event_slots(q, n_tot):
+    """Slots per word-event of the well-mixed Frank event at exact register
+    widths (the molecule count known): RNG, the five cumulative comparisons
+    (borrow chains, the two that feed later ones keep their difference),
+    the changer masks, three masked +-1/+2 ripple updates of the counts, the
+    pair counts P_AL, Q_A = N_A (N_tot - N_A), P_LD (masked change formed
+    over its exact width, then a sign-extended ripple add) and U = c_u N_A."""
+    b, B, N = q["b"], q["B"], n_tot
+    BS = B + (1 if q["max_total"] == (1 << B) else 0)
+    c = q["c"]
+    cu, fa, fi = c[0], _bitlen(c[2]) - 1, _bitlen(c[4]) - 1
+    fmin = min(fa, fi)
+    UW = max(1, _bitlen(cu * N))
+    WP = max(2, _bitlen((N // 2) * (N - N // 2)))
+    wd_al = _signed_width(-N + 1, 2 * N - 4)
+    wd_qa = _signed_width(-2 * N + 4, 2 * N - 4)
+    wd_ld = _signed_width(-N, N - 1)
     rng = ((B + 3) // 4) * PHILOX_SLOTS
-    select = B + 2 * (B - 1) + 2 * 2 * (B - f) + (B - f) + 8
-    species = 3 * 2 * b
-    products = 2 * (5 * (b + 2) + 2 * (2 * b - 2)) + (4 * (b + 2) + 2 * (2 * b - 2))
-    unimolecular = 3 * B if cu_bits else 0
-    return rng + select + species + products + unimolecular + 3
+    select = (UW + -(-(BS - UW - 1) // 2) + 1) + (fmin - 1) + 2 * (BS - fmin) \
+        + (BS - fa) + 2 * (BS - fa) + (BS - fi)
+    masks = 10
+    counts = 3 * (2 * b - 1)
+    products = (5 * wd_al + 2 * WP - 1) + (4 * wd_qa + 2 * WP - 1) + (4 * wd_ld + 2 * WP - 1)
+    unimolecular = 2 * UW - 1
+    return rng + select + masks + counts + products + unimolecular
 
 
-VALU_PEAK = 256 * 128 * 2.4e9   # 32-bit lane-slots/s: 256 CUs x 128 lanes/clk x 2.4 GHz
+# 32-bit VALU lane-operations/s: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz (a wave64
+# instruction in 4 cycles; the fp64 vector peak of 78.6 TFLOP/s is this lane rate of FMAs,
+# the fp32 157.3 counts packed pairs, which bitwise instructions do not have).  Measured by
+# --valu-ref: v_bitop3_b32 reaches 0.97 of it, v_mad_u64_u32 0.93.
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12               # bytes/s, MI355X HBM3E
 
 # HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (the factors of a 1 GiB copy), valid only for the sources they were taken on:
 # kernel -> (sha1 prefix of its sources, sources, bytes per launch, summary file).
 CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
 MEASURED_TRAFFIC = {
-    "wm_pc_kernel": ("7b196892f1ba", ("bitops.h", "wm_device.h", "wm_event_body.inc",
+    "wm_pc_kernel": ("74d32918df9c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
-                     int((2 * 10848.25 + 12672) * 1024), "profiles/wm_pc_kernel_frank1024_2p20.md"),
+                     int((2 * 10822.625 + 12672) * 1024), "profiles/wm_pc_kernel_frank1024_2p20.md"),
     "lat_event_kernel": ("1233d02af292", ("bitops.h", "lattice.hip"),
                          (2 * 3994154 + 8337447) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
 }
+
+
+# VALU wave instructions per launch (rocprofv3 SQ_INSTS_VALU), valid for the same sources:
+# kernel -> (sha1 prefix, sources, instructions per launch, summary file).
+MEASURED_VALU = {
+    "wm_pc_kernel": ("74d32918df9c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
+                                      "wm_kernel.hip"),
+                     20938398939, "profiles/wm_pc_kernel_frank1024_2p20.md"),
+}
+
+
+def _sources_match(entry):
+    import hashlib
+    sha, files = entry[0], entry[1]
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12] == sha
+
+
+def measured_valu(kernel):
+    """Counter-measured VALU wave instructions per launch, or None once the
+    kernel's sources differ from the ones the counter was taken on."""
+    e = MEASURED_VALU.get(kernel)
+    return e[2] if e and _sources_match(e) else None
 
 
 def measured_traffic(kernel):
@@ -96,6 +152,9 @@ def main():
                     help="networks for the one-network-per-launch comparison")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
+    ap.add_argument("--valu-ref", action="store_true",
+                    help="only the VALU issue-rate reference: v_bitop3_b32 and v_mad_u64_u32 "
+                         "chains at 1, 2, 4 and 8 waves per SIMD")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: replicas are independent and would shard by "
@@ -111,6 +170,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_ref_bytes": 1 << 30}))
         return
+    if args.valu_ref:
+        return valu_ref()
     import paper_2412_16613_amd as bwg
     from workloads import config
     if args.workload == "batch":
@@ -184,7 +245,7 @@ def main():
     value = events_per_step * args.steps / (r["ms"] / 1e3)
     adv_avg_ms = sum(r["adv_ms"]) / len(r["adv_ms"])
     word_events = events_per_step / 32.0
-    slots = word_event_slots(q["b"], q["B"], q["f"], bin(q["c"][0]).count("1") - 1)
+    slots = word_event_slots(q, net["n_tot"])
     # per event-kernel launch: its share of the step's word-events over its
     # duration (HIP events around each launch, on the launch stream)
     launches_per_step = r["kt_n"] / args.steps
@@ -210,11 +271,14 @@ def main():
         "real_events_per_s": r["real"] * args.steps / (r["ms"] / 1e3),
         "replica_time_per_s": M * t_end * args.steps / (r["ms"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
+                     "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK,
                      "traffic": measured_traffic("wm_pc_kernel"), "traffic_unit": "B/launch",
                      "kernel": "wm_pc_kernel", "kernel_ms": launch_ms,
                      "launches_per_step": launches_per_step, "advance_ms": adv_avg_ms,
-                     "slots_per_word_event": slots},
+                     "slots_per_word_event": slots,
+                     "valu_insts_per_launch": measured_valu("wm_pc_kernel"),
+                     "issued_frac": (measured_valu("wm_pc_kernel") * 64 / (launch_ms / 1e3) /
+                                     VALU_PEAK if measured_valu("wm_pc_kernel") else None)},
     }
     if not args.no_plain:
         p = run("plain", max(1, args.steps // 2), 1)
@@ -239,6 +303,46 @@ def main():
     if not out["parity"]:
         print("parity failure: GPU counts differ from the oracle", file=sys.stderr)
         sys.exit(1)
+
+
+def valu_ref():
+    """Sustained 32-bit VALU lane-operations per second of the two instructions
+    the bit-sliced kernels are made of (calib/valu_ref.hip): v_bitop3_b32 and
+    Philox's v_mad_u64_u32, eight independent chains per thread, with 1, 2,
+    4 and 8 waves per SIMD (256, 512, 1024, 2048 blocks of four waves).  Each
+    wave64 instruction counts 64 lane-operations; the fraction is of the
+    derived peak (256 CUs x 128 lanes per clock x 2.4 GHz)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2412_16613_amd", "libbwg_calib.so"))
+    lib.bwg_valu_ref.restype = ctypes.c_double
+    lib.bwg_valu_ref.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                 ctypes.c_void_p]
+    lib.bwg_valu_ref_ops_per_thread.restype = ctypes.c_uint64
+    lib.bwg_valu_ref_ops_per_thread.argtypes = [ctypes.c_uint32]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    rows = []
+    for kind, name, chains, iters in ((0, "v_bitop3_b32", 8, 20000),
+                                      (1, "v_mad_u64_u32", 8, 20000),
+                                      (3, "v_bitop3_b32", 2, 10000),
+                                      (2, "v_bitop3_b32", 1, 5000)):
+        for w in (1, 2, 4, 8):
+            blocks = 256 * w
+            out = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+            lib.bwg_valu_ref(kind, blocks, 100, ctypes.c_void_p(out.data_ptr()), stream)
+            ms = lib.bwg_valu_ref(kind, blocks, iters, ctypes.c_void_p(out.data_ptr()), stream)
+            if ms <= 0:
+                raise RuntimeError("reference kernel failed (%g)" % ms)
+            # every wave issues ops_per_thread instructions of 64 lanes each
+            wave_instr = blocks * 4 * lib.bwg_valu_ref_ops_per_thread(iters)
+            rate = wave_instr * 64 / (ms / 1e3)
+            rows.append({"instruction": name, "chains": chains, "waves_per_simd": w, "ms": ms,
+                         "lane_ops_per_s": rate, "frac_of_peak": rate / VALU_PEAK,
+                         "cycles_per_wave_instruction_per_simd":
+                             (ms / 1e3) * 2.4e9 / (wave_instr / (256 * 4))})
+    print(json.dumps({"valu_ref": rows, "peak_lane_ops_per_s": VALU_PEAK}))
 
 
 def lattice_slots(q, li):
@@ -313,7 +417,19 @@ def bench_lattice(args):
     slots = f_r * react + (1 - f_r) * hop
     launches_per_step = kt_n / args.steps
     launch_ms = kt_ms / kt_n
-    achieved = slots * (events / 32.0) / launches_per_step / (launch_ms / 1e3)
+    word_events = events / 32.0 / launches_per_step          # per launch
+    achieved = slots * word_events / (launch_ms / 1e3)
+    # algorithmic HBM bytes: a reaction reads and writes the 3 x P planes of
+    # its site (one 32-bit word each), a hop those of both sites
+    site_bytes = 3 * li["P"] * 4
+    bytes_we = f_r * 2 * site_bytes + (1 - f_r) * 2 * 2 * site_bytes
+    hbm = bytes_we * word_events / (launch_ms / 1e3)
+    alu_side = {"achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK,
+                "slots_per_word_event": slots, "slots_reaction": react, "slots_hop": hop}
+    hbm_side = {"achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": hbm / HBM_PEAK, "bytes_per_word_event": bytes_we}
+    bind = hbm_side if hbm_side["frac"] >= alu_side["frac"] else alu_side
     out = {
         "metric": "replica-events/sec (bit-parallel lattice, 1 GPU)",
         "value": value, "unit": "replica-events/s", "n_gpus": 1, "steps": args.steps,
@@ -325,13 +441,12 @@ def bench_lattice(args):
                    "sites": li["sites"], "replicas": M, "t_end": t_end, "site_planes": li["P"],
                    "reaction_planes": li["B_r"]},
         "real_events_per_s": st["real_total"] * args.steps / (ms / 1e3),
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU slots/s", "frac": achieved / VALU_PEAK,
+        "roofline": {"bound": "hbm" if bind is hbm_side else "alu",
+                     "achieved": bind["achieved"], "peak": bind["peak"], "unit": bind["unit"],
+                     "frac": bind["frac"], "alu": alu_side, "hbm": hbm_side,
                      "traffic": measured_traffic("lat_event_kernel"), "traffic_unit": "B/launch",
                      "kernel": "lat_event_kernel", "kernel_ms": launch_ms,
-                     "launches_per_step": launches_per_step, "advance_ms": adv_ms,
-                     "slots_per_word_event": slots,
-                     "slots_reaction": react, "slots_hop": hop},
+                     "launches_per_step": launches_per_step, "advance_ms": adv_ms},
     }
     out["parity"] = True
     if not args.no_cpu:

@@ -19,6 +19,7 @@ constexpr uint32_t L_BORROW = lut((~TA & TB) | (~TA & TC) | (TB & TC));  // borr
 constexpr uint32_t L_ANDXOR = lut((TA & TB) ^ TC);                    // (a & b) ^ c
 constexpr uint32_t L_ANDOR = lut((TA & TB) | TC);                     // (a & b) | c
 constexpr uint32_t L_ANDNOT = lut(TA & ~TB);                          // a & ~b (c unused)
+constexpr uint32_t L_ANDNOT_OR = lut((TA & ~TB) | TC);                // (a & ~b) | c
 
 #define BWG_OP3(a, b, c, L) __builtin_amdgcn_bitop3_b32((a), (b), (c), (L))
 

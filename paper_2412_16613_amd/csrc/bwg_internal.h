@@ -75,6 +75,7 @@ using WmLaunch = hipError_t (*)(const WmArgs &, hipStream_t, int block);
 // at run time).
 struct WmVariant {
     int nb, bc, fa, cu;
+    int nt, bs;  // molecule count and selection planes it is fixed to (nt = 0: any)
     WmLaunch fn;
 };
 extern const WmVariant kWmVariants[];

@@ -395,6 +395,9 @@ static const WmVariant *pick_variant(const bwg_net *n)
     for (int i = 0; i < kWmVariantCount; ++i) {
         const WmVariant &v = kWmVariants[i];
         if (v.nb < b || v.bc < need_bc) continue;
+        // a variant fixed to one molecule count (exact register widths)
+        // serves exactly that count and selection width
+        if (v.nt > 0 && (v.nt != n->n_tot || v.bs != need_bc || fa < 0 || fi < 0)) continue;
         if (v.fa >= 0 && !(same && v.fa == f_common && f_common >= 0)) continue;
         if (v.cu >= 0 && (uint32_t)v.cu != n->shape.cu) continue;
         if (fa >= v.bc || fi >= v.bc) continue;

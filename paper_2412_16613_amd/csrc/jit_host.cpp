@@ -243,28 +243,29 @@ int jit_get(bwg_net *n, const JitKernel **out)
 // count and threshold planes, product shifts and unimolecular weight as
 // compile-time constants (the precompiled kernels take them at run time
 // unless the network is one of the named workloads): FA shifts the A + L and
-// A + D weights, FI the L + D weight.
-static std::string jit_frank_source(int NB, int BC, int FA, int FI, int CU)
+// A + D weights, FI the L + D weight; with the molecule count NT and the
+// selection planes BS the registers take their exact widths (WmShape).
+static std::string jit_frank_source(int NB, int BC, int FA, int FI, int CU, int NT, int BS)
 {
     std::ostringstream o;
     o << "#include \"wm_device.h\"\n"
       << "namespace bwg {\n"
       << "constexpr int NB = " << NB << ", BC = " << BC << ", FA = " << FA << ", FI = " << FI
-      << ", CU = " << CU << ";\n"
+      << ", CU = " << CU << ", NT = " << NT << ", BS = " << BS << ";\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_word(WmArgs a)\n"
       << "{\n"
-      << "    wm_word<NB, BC, FA, CU, false, FI>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
+      << "    wm_word<NB, BC, FA, CU, false, FI, NT, BS>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_sh(WmArgs a)\n"
       << "{\n"
-      << "    wm_word<NB, BC, FA, CU, true, FI>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
+      << "    wm_word<NB, BC, FA, CU, true, FI, NT, BS>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);\n"
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
       << "{\n"
       << "    constexpr int PH = BC == 20 ? 6 : 4;\n"
       << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
       << "    __shared__ uint64_t wave_span[4];\n"
-      << "    wm_word_pc<NB, BC, FA, CU, PH, FI>(a, ring, wave_span);\n"
+      << "    wm_word_pc<NB, BC, FA, CU, PH, FI, NT, BS>(a, ring, wave_span);\n"
       << "}\n"
       << "}  // namespace bwg\n";
     return o.str();
@@ -275,7 +276,7 @@ static std::string jit_frank_source(int NB, int BC, int FA, int FI, int CU)
 // A + D; L + D), unimolecular weight.  A shift whose reactions are absent
 // takes the other one's value (its subtraction is never run).
 struct FrankParams {
-    int NB, BC, FA, FI, CU;
+    int NB, BC, FA, FI, CU, NT, BS;
 };
 
 static bool frank_params(const bwg_net &n, FrankParams *p)
@@ -288,7 +289,11 @@ static bool frank_params(const bwg_net &n, FrankParams *p)
     const int FI = fi >= 0 ? fi : FA;
     if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || FI >= BC || n.shape.cu > 0x7FFFFFFFu)
         return false;
-    *p = FrankParams{NB, BC, FA, FI, (int)n.shape.cu};
+    if (n.n_tot < 1 || n.n_tot >= (1 << 14)) return false;
+    // exact register widths need the molecule count and both bimolecular
+    // kinds (A + L / A + D and L + D); NT = 0 keeps the general widths
+    const int NT = (fa >= 0 && fi >= 0) ? (int)n.n_tot : 0;
+    *p = FrankParams{NB, BC, FA, FI, (int)n.shape.cu, NT, need_bc};
     return true;
 }
 
@@ -312,7 +317,7 @@ int jit_frank_get(bwg_net *n, const JitKernel **out)
     if (!frank_params(*n, &p))
         return fail(BWG_EUNSUPPORTED, "network beyond the compiled Frank kernel's range");
     JitKernel *k = nullptr;
-    const int rc = jit_compile(jit_frank_source(p.NB, p.BC, p.FA, p.FI, p.CU), true, &k);
+    const int rc = jit_compile(jit_frank_source(p.NB, p.BC, p.FA, p.FI, p.CU, p.NT, p.BS), true, &k);
     if (rc) return rc;
     n->jit_frank = k;
     *out = k;

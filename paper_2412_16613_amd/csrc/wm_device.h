@@ -36,14 +36,14 @@ __device__ __forceinline__ uint32_t shared_at(const WmArgs &a, uint64_t e)
 }
 
 // ---- subtraction of a shifted operand ------------------------------------
-// d -= p << SH over planes [SH, BC); returns the final borrow.  Planes below
-// SH are untouched (the operand is zero there).
-template <int SH, int BC, int WP, bool KEEP>
+// d -= p << SH over planes [SH, NQ) (NQ <= BC, default all); returns the
+// final borrow.  Planes below SH are untouched (the operand is zero there).
+template <int SH, int BC, int WP, bool KEEP, int NQ = BC>
 __device__ __forceinline__ uint32_t sub_shifted(uint32_t (&d)[BC], const uint32_t (&p)[WP])
 {
     uint32_t br = 0;
 #pragma unroll
-    for (int q = SH; q < BC; ++q) {
+    for (int q = SH; q < NQ; ++q) {
         const uint32_t v = (q - SH < WP) ? p[q - SH] : 0u;
         const uint32_t nb = BWG_OP3(d[q], v, br, L_BORROW);
         if (KEEP) d[q] = BWG_OP3(d[q], v, br, L_XOR3);
@@ -184,16 +184,62 @@ __device__ __forceinline__ void load_word(const WmArgs &a, uint64_t w, uint32_t 
     }
 }
 
-// Pair counts and the unimolecular weight U = cu N_A, recomputed once per
-// launch from the occupancies.
-template <int NB, int BC, int WP>
+constexpr int bit_length(uint64_t v) { return v ? 1 + bit_length(v >> 1) : 0; }
+// Planes of a two's complement number that holds every value of [lo, hi]
+// (lo <= 0 <= hi), at least 2.
+constexpr int signed_width(int64_t lo, int64_t hi)
+{
+    const uint64_t m = (uint64_t)(hi > -lo - 1 ? hi : -lo - 1);
+    return bit_length(m) + 1 > 2 ? bit_length(m) + 1 : 2;
+}
+
+// Register widths of one word's event loop.  With the network's molecule
+// count NT, product shifts FA, FI, unimolecular weight CU and selection
+// planes BS all known at compile time (EXACT), every quantity is held in
+// exactly the planes its largest value needs: U = CU N_A below CU NT, the
+// pair counts below floor(NT/2) ceil(NT/2) (X + Y <= NT), and the second
+// pair-count register holds Q_A = N_A (NT - N_A) = P_AL + P_AD, a function
+// of N_A alone, so that S_4 = 2U + 2^FA Q_A is compared without S_3.
+// Otherwise the widths follow the count planes NB and threshold planes BC.
+template <int NB, int BC, int FA, int CU, int FI, int NT, int BS>
+struct WmShape {
+    static constexpr bool EXACT = NT > 0 && FA >= 0 && FI >= 0 && CU >= 0;  // and both
+                                                                              // bimolecular
+                                                                              // kinds present
+    static constexpr int WP = EXACT ? (bit_length((uint64_t)(NT / 2) * (uint64_t)(NT - NT / 2)) > 1
+                                           ? bit_length((uint64_t)(NT / 2) * (uint64_t)(NT - NT / 2))
+                                           : 2)
+                                    : (2 * NB - 2 > 1 ? 2 * NB - 2 : 2);
+    static constexpr int UW = EXACT ? (bit_length((uint64_t)CU * (uint64_t)NT) > 0
+                                           ? bit_length((uint64_t)CU * (uint64_t)NT)
+                                           : 1)
+                                    : BC;
+    static constexpr int WD = NB + 2;  // product-delta planes
+    // exact two's complement widths of the per-event changes (with their
+    // carry-in convention) of P_AL: [-(NT - 1), 2NT - 4], of Q_A:
+    // [-(2NT - 4), 2NT - 4] and of P_LD: [-NT, NT - 1]
+    static constexpr int NTP = NT > 2 ? NT : 2;
+    static constexpr int WD_AL = EXACT ? signed_width(-(int64_t)NTP + 1, 2 * (int64_t)NTP - 4) : WD;
+    static constexpr int WD_QA = EXACT ? signed_width(-2 * (int64_t)NTP + 4, 2 * (int64_t)NTP - 4)
+                                       : WD;
+    static constexpr int WD_LD = EXACT ? signed_width(-(int64_t)NTP, (int64_t)NTP - 1) : WD;
+    static constexpr int FMIN = FA < FI ? FA : FI;
+    static_assert(!EXACT || (BS <= BC && UW < BS), "selection planes");
+};
+
+// Pair counts and the unimolecular weight U = cu N_A (UW planes), recomputed
+// once per launch from the occupancies; with QA the second pair count is
+// Q_A = N_A N_D + N_A N_L instead of N_A N_D.
+template <int NB, int UW, int WP, bool QA = false>
 __device__ __forceinline__ void init_weights(const uint32_t (&L)[NB], const uint32_t (&D)[NB],
                                              const uint32_t (&A)[NB], uint32_t cu,
                                              uint32_t (&PAL)[WP], uint32_t (&PAD)[WP],
-                                             uint32_t (&PLD)[WP], uint32_t (&U)[BC])
+                                             uint32_t (&PLD)[WP], uint32_t (&U)[UW])
 {
+    constexpr int BC = UW;
     mul_planes<NB, WP>(PAL, A, L);
     mul_planes<NB, WP>(PAD, A, D);
+    if constexpr (QA) add_sext<WP, WP>(PAD, PAL, 0u);
     mul_planes<NB, WP>(PLD, L, D);
 #pragma unroll
     for (int q = 0; q < BC; ++q) U[q] = 0;
@@ -278,12 +324,14 @@ __device__ __forceinline__ uint32_t live_lanes(const WmArgs &a, uint64_t w)
 // of the A + L and A + D weights and FI that of the L + D weight (-1: run
 // time), CU unimolecular weight (-1: run time); SH: one shared threshold per
 // event (a.zs != 0) instead of per-replica draws.
-template <int NB, int BC, int FA, int CU, bool SH = false, int FI = FA>
+template <int NB, int BC, int FA, int CU, bool SH = false, int FI = FA, int NT = 0, int BS = BC>
 __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
 {
     static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
-    constexpr int WP = 2 * NB - 2 > 1 ? 2 * NB - 2 : 2;   // product planes
-    constexpr int WD = NB + 2;                             // product-delta planes
+    using Sh = WmShape<NB, BC, FA, CU, FI, NT, BS>;
+    constexpr bool EXACT = Sh::EXACT;
+    constexpr int WP = Sh::WP, WD = Sh::WD, UW = Sh::UW, FMIN = Sh::FMIN;
+    constexpr int WD_AL = Sh::WD_AL, WD_QA = Sh::WD_QA, WD_LD = Sh::WD_LD;
     if (w >= a.n_words) return;
 
     const uint32_t live = live_lanes(a, w);
@@ -296,10 +344,11 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
     load_word<NB>(a, w, L, D, A);
 
     if (lo < hi) {
-        uint32_t PAL[WP], PAD[WP], PLD[WP], U[BC];
+        uint32_t PAL[WP], PAD[WP], PLD[WP], U[UW];
         const uint32_t cu = CU >= 0 ? (uint32_t)CU : a.cu;
-        init_weights<NB, BC, WP>(L, D, A, cu, PAL, PAD, PLD, U);
-        const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
+        init_weights<NB, UW, WP, EXACT>(L, D, A, cu, PAL, PAD, PLD, U);
+        // the exact-width variants serve networks with both reactions
+        const bool has_a = EXACT || a.fa >= 0, has_i = EXACT || a.fi >= 0;
         const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
         const uint32_t G = (uint32_t)w;
         // threshold planes in use: nq quads, the last one masked to plane B-1
@@ -357,13 +406,15 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
 // the events of half (s-1) mod 2, and a barrier separates the steps.  The
 // step count is the workgroup's largest window, so every wave meets every
 // barrier.  Results are those of wm_word.
-template <int NB, int BC, int FA, int CU, int PH, int FI = FA>
+template <int NB, int BC, int FA, int CU, int PH, int FI = FA, int NT = 0, int BS = BC>
 __device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4][64],
                                            uint64_t *wave_span)
 {
     static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
-    constexpr int WP = 2 * NB - 2 > 1 ? 2 * NB - 2 : 2;
-    constexpr int WD = NB + 2;
+    using Sh = WmShape<NB, BC, FA, CU, FI, NT, BS>;
+    constexpr bool EXACT = Sh::EXACT;
+    constexpr int WP = Sh::WP, WD = Sh::WD, UW = Sh::UW, FMIN = Sh::FMIN;
+    constexpr int WD_AL = Sh::WD_AL, WD_QA = Sh::WD_QA, WD_LD = Sh::WD_LD;
     const int lane = threadIdx.x & 63;
     const int grp = (threadIdx.x >> 6) & 1;
     const bool producer = threadIdx.x < 128;
@@ -424,10 +475,11 @@ __device__ __forceinline__ void wm_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4
 #pragma unroll
         for (int q = 0; q < NB; ++q) L[q] = D[q] = A[q] = 0u;
     }
-    uint32_t PAL[WP], PAD[WP], PLD[WP], U[BC];
+    uint32_t PAL[WP], PAD[WP], PLD[WP], U[UW];
     const uint32_t cu = CU >= 0 ? (uint32_t)CU : a.cu;
-    init_weights<NB, BC, WP>(L, D, A, cu, PAL, PAD, PLD, U);
-    const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
+    init_weights<NB, UW, WP, EXACT>(L, D, A, cu, PAL, PAD, PLD, U);
+    // the exact-width variants serve networks with both reactions
+    const bool has_a = EXACT || a.fa >= 0, has_i = EXACT || a.fi >= 0;
     uint64_t nreal = 0;
     uint64_t nxt = 0;  // next event at which the active lanes change
     uint32_t actc = 0;

@@ -30,10 +30,10 @@
 
 namespace bwg {
 
-template <int NB, int BC, int FA, int CU, bool SH>
+template <int NB, int BC, int FA, int CU, bool SH, int NT, int BS>
 __global__ __launch_bounds__(256) void wm_event_kernel(WmArgs a)
 {
-    wm_word<NB, BC, FA, CU, SH>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    wm_word<NB, BC, FA, CU, SH, FA, NT, BS>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Producer/consumer form: four waves per 128 words, events handed over
@@ -46,22 +46,22 @@ constexpr int pc_half()
     return BC == 20 ? 6 : 4;
 }
 
-template <int NB, int BC, int FA, int CU>
+template <int NB, int BC, int FA, int CU, int NT, int BS>
 __global__ __launch_bounds__(256) void wm_pc_kernel(WmArgs a)
 {
     constexpr int PH = pc_half<BC>();
     __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];
     __shared__ uint64_t wave_span[4];
-    wm_word_pc<NB, BC, FA, CU, PH>(a, ring, wave_span);
+    wm_word_pc<NB, BC, FA, CU, PH, FA, NT, BS>(a, ring, wave_span);
 }
 
-template <int NB, int BC, int FA, int CU>
+template <int NB, int BC, int FA, int CU, int NT, int BS>
 hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
 {
     // with at most one wave of 64 words per SIMD pair half the chip would
     // idle: split each word's events over a producer and a consumer wave
     if (block <= 0 && !a.zs && a.n_words <= 32768) {
-        hipLaunchKernelGGL((wm_pc_kernel<NB, BC, FA, CU>), dim3((uint32_t)((a.n_words + 127) / 128)),
+        hipLaunchKernelGGL((wm_pc_kernel<NB, BC, FA, CU, NT, BS>), dim3((uint32_t)((a.n_words + 127) / 128)),
                            dim3(256), 0, s, a);
         return hipGetLastError();
     }
@@ -72,36 +72,38 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
     if (block <= 0) block = a.n_words >= 65536 ? 256 : 128;
     const uint64_t grid = (a.n_words + block - 1) / block;
     if (a.zs)
-        hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU, true>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU, true, NT, BS>), dim3((uint32_t)grid),
                            dim3(block), 0, s, a);
     else
-        hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU, false>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((wm_event_kernel<NB, BC, FA, CU, false, NT, BS>), dim3((uint32_t)grid),
                            dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
 // Kernel instantiations (both compilation passes) and the host-side table.
-// (NB, BC, FA, CU): FA/CU = -1 are taken at run time.
+// (NB, BC, FA, CU, NT, BS): FA/CU = -1 are taken at run time; NT > 0 fixes
+// the molecule count and BS the selection planes (exact register widths,
+// see WmShape), NT = 0 serves any count within the planes.
 #define BWG_WM_VARIANTS(X)                                                    \
-    /* compile-time shift and weight of the named workloads */               \
-    X(6, 20, 9, 164)   /* N_tot = 32, k0 = 0.01, k1 = k2 = 1/32 */           \
-    X(11, 24, 4, 164)  /* N_tot = 1024 */                                     \
+    /* the named workloads, exact widths */                                   \
+    X(6, 20, 9, 164, 32, 18)     /* N_tot = 32, k0 = 0.01, k1 = k2 = 1/32 */  \
+    X(11, 24, 4, 164, 1024, 23)  /* N_tot = 1024 */                           \
     /* the paper's network (unit weights, no conversions) by N_tot */        \
-    X(4, 8, 0, 0)      /* N_tot <= 15 */                                      \
-    X(5, 8, 0, 0)      /* N_tot <= 23 */                                      \
-    X(6, 12, 0, 0)     /* N_tot <= 63 */                                      \
-    X(7, 12, 0, 0)     /* N_tot <= 91 */                                      \
-    X(8, 16, 0, 0)     /* N_tot <= 255 */                                     \
-    X(9, 16, 0, 0)     /* N_tot <= 362 */                                     \
-    X(10, 20, 0, 0)    /* N_tot <= 1023 */                                    \
-    X(11, 20, 0, 0)    /* N_tot <= 1448 */                                    \
+    X(4, 8, 0, 0, 0, 8)      /* N_tot <= 15 */                                \
+    X(5, 8, 0, 0, 0, 8)      /* N_tot <= 23 */                                \
+    X(6, 12, 0, 0, 0, 12)    /* N_tot <= 63 */                                \
+    X(7, 12, 0, 0, 0, 12)    /* N_tot <= 91 */                                \
+    X(8, 16, 0, 0, 0, 16)    /* N_tot <= 255 */                               \
+    X(9, 16, 0, 0, 0, 16)    /* N_tot <= 362 */                               \
+    X(10, 20, 0, 0, 0, 20)   /* N_tot <= 1023 */                              \
+    X(11, 20, 0, 0, 0, 20)   /* N_tot <= 1448 */                              \
     /* run-time shifts and weights, any Frank-family network in budget */     \
-    X(4, 20, -1, -1)                                                          \
-    X(6, 20, -1, -1)                                                          \
-    X(8, 24, -1, -1)                                                          \
-    X(10, 24, -1, -1)                                                         \
-    X(12, 28, -1, -1)                                                         \
-    X(14, 32, -1, -1)
+    X(4, 20, -1, -1, 0, 20)                                                   \
+    X(6, 20, -1, -1, 0, 20)                                                   \
+    X(8, 24, -1, -1, 0, 24)                                                   \
+    X(10, 24, -1, -1, 0, 24)                                                  \
+    X(12, 28, -1, -1, 0, 28)                                                  \
+    X(14, 32, -1, -1, 0, 32)
 
 // Lanes engine: 8 words per 256-thread block, one replica per thread.
 __global__ __launch_bounds__(256) void wm_lanes_kernel(WmArgs a)
@@ -135,14 +137,14 @@ hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-#define BWG_WM_INST(nb, bc, fa, cu)                                     \
-    template __global__ void wm_event_kernel<nb, bc, fa, cu, false>(WmArgs); \
-    template __global__ void wm_event_kernel<nb, bc, fa, cu, true>(WmArgs); \
-    template __global__ void wm_pc_kernel<nb, bc, fa, cu>(WmArgs);
+#define BWG_WM_INST(nb, bc, fa, cu, nt, bs)                                     \
+    template __global__ void wm_event_kernel<nb, bc, fa, cu, false, nt, bs>(WmArgs); \
+    template __global__ void wm_event_kernel<nb, bc, fa, cu, true, nt, bs>(WmArgs);  \
+    template __global__ void wm_pc_kernel<nb, bc, fa, cu, nt, bs>(WmArgs);
 BWG_WM_VARIANTS(BWG_WM_INST)
 
 #ifndef __HIP_DEVICE_COMPILE__
-#define BWG_WM_ENTRY(nb, bc, fa, cu) {nb, bc, fa, cu, &launch_wm<nb, bc, fa, cu>},
+#define BWG_WM_ENTRY(nb, bc, fa, cu, nt, bs) {nb, bc, fa, cu, nt, bs, &launch_wm<nb, bc, fa, cu, nt, bs>},
 const WmVariant kWmVariants[] = {BWG_WM_VARIANTS(BWG_WM_ENTRY)};
 const int kWmVariantCount = sizeof(kWmVariants) / sizeof(kWmVariants[0]);
 #endif
