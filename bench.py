@@ -615,7 +615,8 @@ def bench_serve(args):
     reqs = serve_requests(rate=args.rate, duration=args.duration)
     n_lat = sum(1 for r in reqs if r["net"].get("lx"))
     srv = Server(chunk=args.chunk)
-    res = srv.serve(reqs, real_time=True)
+    res = srv.serve(reqs, real_time=True,
+                    progress=lambda m: print("serve " + m, file=sys.stderr, flush=True))
     s = summarize(res, srv.stats)
     out = {"metric": "p50/p99 request latency and replica-events/sec (served stream, 1 GPU)",
            "value": s["replica_events_per_s"], "unit": "replica-events/s", "n_gpus": 1,

@@ -10,9 +10,14 @@ request, so long chains yield to newly admitted requests between passes and
 their work overlaps in one launch.  Lattice requests run their own launches
 (at most `lattice_chunk` events of their component sequence per pass) on a
 second stream, beside the persistent launch.  A request completes when its
-pending-event bound reaches zero; its histogram (and, if asked, its counts)
-is read back, the latency (completion - arrival) recorded and its memory
-returned to the budget.
+pending-event bound reaches zero (a host-side bound: no device query); its
+histogram (and, if asked, its counts) and its event total are copied to
+pinned host memory behind its last pass, and HIP events mark the end of
+every pass on both streams.  The host does not wait for a pass it has just
+enqueued: it keeps up to `depth` passes in flight, admits arrivals and
+enqueues the next pass while the previous ones run, and retires a pass (its
+requests' latency, completion - arrival, recorded and their memory
+returned to the budget) once its events have completed.
 
 Results do not depend on the mix: every draw is keyed by (seed, net id,
 replica, event), so a request served among others gives bit for bit the
@@ -30,7 +35,7 @@ import paper_2412_16613_amd as bwg
 class Server:
     def __init__(self, hbm_budget=64 << 30, chunk=4096, max_members=1024,
                  max_items=1 << 16, waves=2048, n_bins=256, keep_counts=False,
-                 lattice_chunk=1 << 17, device="cuda"):
+                 lattice_chunk=1 << 17, depth=2, device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -43,6 +48,7 @@ class Server:
         self.waves = int(waves)
         self.n_bins = int(n_bins)
         self.keep_counts = keep_counts
+        self.depth = max(1, int(depth))
         self._nets = {}
         self.batch = None
 
@@ -61,11 +67,14 @@ class Server:
     def _items(M):
         return (((M + 31) // 32) + 63) // 64
 
-    def serve(self, requests, real_time=True, max_seconds=None, pass_time=1.0):
+    def serve(self, requests, real_time=True, max_seconds=None, pass_time=1.0, progress=None,
+              progress_every=20.0):
         """Serve requests (dicts with arrival, net, replicas, seed, net_id,
         init, t_end); returns one result dict per completed request.  With
         real_time=False the clock is simulated: it advances by pass_time per
-        pass (deterministic interleaving, for tests)."""
+        pass (deterministic interleaving, for tests).  progress, if given, is
+        called with a status string about every progress_every seconds of
+        wall time."""
         torch = self.torch
         reqs = sorted(requests, key=lambda r: r["arrival"])
         incoming = collections.deque(reqs)
@@ -84,10 +93,40 @@ class Server:
 
         def well_mixed(act):
             return [a["ens"] for a in act if not a["lattice"]]
+
+        def to_host(t):
+            h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+            h.copy_(t, non_blocking=True)
+            return h
+
+        inflight = collections.deque()   # passes: events on both streams, requests finished
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if real_time else None
         sim_now = 0.0
-        while incoming or waiting or active:
+
+        def retire(p):
+            """Requests of a completed pass: results, memory back to the budget."""
+            nonlocal used_bytes, used_items
+            t_done = clock() if real_time else p["sim_done"]
+            for a in p["done"]:
+                r = a["req"]
+                res = dict(id=r["net_id"], arrival=r["arrival"], admitted=a["admitted"],
+                           completed=t_done, latency=t_done - r["arrival"],
+                           hist=a["hist_host"].numpy().copy(), replicas=r["replicas"])
+                if self.keep_counts:
+                    res["counts"] = a["counts_host"].numpy().copy()
+                stats["replica_events"] += int(a["events_host"].numpy()[0])
+                results.append(res)
+                used_bytes -= a["bytes"]
+                used_items -= a["items"]
+
+        next_report = progress_every
+        while incoming or waiting or active or inflight:
+            if progress is not None and time.perf_counter() - t0 >= next_report:
+                next_report += progress_every
+                progress("t=%.0fs: %d done, %d active, %d waiting, %d not yet arrived, %d passes"
+                         % (time.perf_counter() - t0, len(results), len(active), len(waiting),
+                            len(incoming), stats["passes"]))
             now = clock() if real_time else sim_now
             if max_seconds is not None and now > max_seconds:
                 break
@@ -102,8 +141,8 @@ class Server:
                                    device=self.device)
                 nbytes = ens.state_bytes
                 items = 0 if lattice else self._items(r["replicas"])
-                if active and (used_bytes + nbytes > self.hbm_budget
-                               or used_items + items > self.max_items):
+                if (active or inflight) and (used_bytes + nbytes > self.hbm_budget
+                                             or used_items + items > self.max_items):
                     del ens
                     break
                 waiting.popleft()
@@ -116,50 +155,53 @@ class Server:
                 used_bytes += nbytes
                 used_items += items
                 changed = True
-            if not active:
-                if incoming:
-                    if real_time:
-                        time.sleep(max(0.0, incoming[0]["arrival"] - clock()))
-                    else:
-                        sim_now = incoming[0]["arrival"]
-                continue
-            stats["max_active"] = max(stats["max_active"], len(active))
-            if changed:
-                self.batch.set_members(well_mixed(active))
-            if any(not a["lattice"] for a in active):
-                self.batch.run(self.chunk)
-            with torch.cuda.stream(self.side):
-                for a in active:
-                    if a["lattice"]:
-                        a["ens"].run(self.lattice_chunk)
-            stats["passes"] += 1
-            done = [a for a in active if a["ens"].pending() == 0]
-            if done:
+            if active:
+                stats["max_active"] = max(stats["max_active"], len(active))
+                if changed:
+                    self.batch.set_members(well_mixed(active))
+                if any(not a["lattice"] for a in active):
+                    self.batch.run(self.chunk)
+                with torch.cuda.stream(self.side):
+                    for a in active:
+                        if a["lattice"]:
+                            a["ens"].run(self.lattice_chunk)
+                stats["passes"] += 1
+                if not real_time:
+                    sim_now += pass_time
+                # requests whose last events this pass ran: readouts behind it
+                done = [a for a in active if a["ens"].pending() == 0]
                 for a in done:
                     with torch.cuda.stream(self.side if a["lattice"] else main):
-                        a["hist_dev"] = a["ens"].histogram(self.n_bins)
+                        a["hist_host"] = to_host(a["ens"].histogram(self.n_bins))
+                        a["events_host"] = to_host(a["ens"].read_events()[0].sum().view(1))
                         if self.keep_counts:
-                            a["counts_dev"] = a["ens"].read_counts()
-            main.synchronize()
-            self.side.synchronize()
-            if not real_time:
-                sim_now += pass_time
-            if done:
-                t_done = clock() if real_time else sim_now
-                for a in done:
-                    r = a["req"]
-                    hist = a["hist_dev"].cpu().numpy()
-                    res = dict(id=r["net_id"], arrival=r["arrival"], admitted=a["admitted"],
-                               completed=t_done, latency=t_done - r["arrival"], hist=hist,
-                               replicas=r["replicas"])
-                    if self.keep_counts:
-                        res["counts"] = a["counts_dev"].cpu().numpy()
-                    stats["replica_events"] += a["ens"].stats()["events_total"]
-                    results.append(res)
-                    used_bytes -= a["bytes"]
-                    used_items -= a["items"]
-                active = [a for a in active if a["ens"].pending() != 0]
-                self.batch.set_members(well_mixed(active))
+                            a["counts_host"] = to_host(a["ens"].read_counts())
+                ev = (torch.cuda.Event(), torch.cuda.Event())
+                ev[0].record(main)
+                ev[1].record(self.side)
+                inflight.append(dict(ev=ev, done=done, sim_done=sim_now))
+                if done:
+                    active = [a for a in active if a["ens"].pending() != 0]
+                    self.batch.set_members(well_mixed(active))
+            elif not inflight and incoming:
+                if real_time:
+                    time.sleep(max(0.0, incoming[0]["arrival"] - clock()))
+                else:
+                    sim_now = incoming[0]["arrival"]
+                continue
+            # retire finished passes; wait for the oldest once depth passes are
+            # in flight, or when nothing new can be enqueued
+            while inflight:
+                p = inflight[0]
+                ready = p["ev"][0].query() and p["ev"][1].query()
+                if not ready and (len(inflight) >= self.depth or not active):
+                    p["ev"][0].synchronize()
+                    p["ev"][1].synchronize()
+                    ready = True
+                if not ready:
+                    break
+                inflight.popleft()
+                retire(p)
         stats["wall_s"] = (time.perf_counter() - t0)
         self.stats = stats
         return results
