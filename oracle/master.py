@@ -22,16 +22,30 @@ import numpy as np
 from .quantize import combinatorial_factor, state_change
 
 
-def states(n_tot, n_species=3):
-    if n_species != 3:
-        raise ValueError("3 species")
-    return [(a, b, n_tot - a - b) for a in range(n_tot + 1)
-            for b in range(n_tot - a + 1)]
+def _compositions(n, S):
+    if S == 1:
+        return [(n,)]
+    return [(a,) + rest for a in range(n + 1) for rest in _compositions(n - a, S - 1)]
+
+
+def states(n_tot, n_species=3, open_net=False):
+    """The state space: the simplex sum N = n_tot (closed networks; for 3
+    species in the order (a, b, n_tot - a - b)), or the box [0, n_tot]^S of an
+    open network."""
+    if open_net:
+        return [tuple(int(v) for v in s)
+                for s in np.ndindex(*([n_tot + 1] * n_species))]
+    if n_species == 3:
+        return [(a, b, n_tot - a - b) for a in range(n_tot + 1)
+                for b in range(n_tot - a + 1)]
+    return _compositions(n_tot, n_species)
 
 
 def weight_generator(net, q):
-    """Sparse integer generator: list of (from, to, weight)."""
-    st = states(net["n_tot"])
+    """Sparse integer generator: list of (from, to, weight).  In an open
+    network a firing that would pass the cap n_tot is no transition."""
+    open_net = bool(net.get("open"))
+    st = states(net["n_tot"], len(net["species"]), open_net)
     index = {s: i for i, s in enumerate(st)}
     nu = state_change(net)
     trans = []
@@ -41,6 +55,8 @@ def weight_generator(net, q):
             if w == 0 or not any(nu[j]):
                 continue
             t = tuple(a + d for a, d in zip(s, nu[j]))
+            if open_net and max(t) > net["n_tot"]:
+                continue
             trans.append((i, index[t], w))
     return st, index, trans
 

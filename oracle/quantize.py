@@ -19,12 +19,23 @@ The paper makes every propensity an integer by setting k_A = k_I = 1
     2^-8 relative).
   * the weight of reaction j is w_j(N) = c_j h_j(N); its rate per unit time
     is w_j / s.
-  * W = 2^B is the smallest power of two at or above the largest total weight
-    sum_j w_j(N) over every state of the simplex sum_X N_X = N_tot; the
-    uniformised chain makes Lambda = W / s events per unit time, each event
-    picking reaction j with probability w_j / W and doing nothing otherwise.
-    This is the role the ghost reactions play in the paper: they pad the total
-    propensity to a state-independent constant (Eq. (9)).
+  * W = 2^B is the smallest power of two at or above a bound of the total
+    weight sum_j w_j(N) over the state space; the uniformised chain makes
+    Lambda = W / s events per unit time, each event picking reaction j with
+    probability w_j / W and doing nothing otherwise.  This is the role the
+    ghost reactions play in the paper: they pad the total propensity to a
+    state-independent constant (Eq. (9)).  Any bound at or above the largest
+    total gives the same law; the bound used is
+      - 3 species, molecule count conserved (the Frank family): the largest
+        total over the simplex sum_X N_X = N_tot, by enumerating it;
+      - any other network: sum_j c_j max h_j, each reaction's largest factor
+        over the state space: on the simplex N for N_X, floor(N/2) ceil(N/2)
+        for N_X N_Y, N (N - 1) / 2 for N_X (N_X - 1) / 2; on the box of an
+        open network (every count at most the cap C = N_tot) C, C^2 and
+        C (C - 1) / 2 (all attained at the corner N = (C, ..., C)).
+  * open networks (net["open"]: reactions need not conserve the molecule
+    count, the general networks of Sec. 6): every species count is capped at
+    N_tot; a selected reaction that would pass the cap does nothing (ssa.c).
 """
 
 import math
@@ -52,7 +63,7 @@ def _validate(net):
             raise ValueError("stoichiometry width")
         if sum(rv) < 1 or sum(rv) > 2:
             raise ValueError("reaction order must be 1 or 2")
-        if sum(rv) != sum(pv):
+        if sum(rv) != sum(pv) and not net.get("open"):
             raise ValueError("reaction does not conserve the molecule count")
         if min(rv) < 0 or min(pv) < 0:
             raise ValueError("negative stoichiometry")
@@ -65,6 +76,27 @@ def _max_total_weight(net, c):
     """max over the simplex sum N = n_tot of sum_j c_j h_j(N), by enumeration
     of every state (int64; the guard keeps products far from overflow)."""
     return _total_weight_range(net, c)[1]
+
+
+def _factor_max(rv, n, open_net):
+    """Largest h(N) of one reaction over the simplex of n molecules, or over
+    the box [0, n]^S of an open network."""
+    xs = [x for x, r in enumerate(rv) for _ in range(r)]
+    if len(xs) == 1:
+        return n
+    if xs[0] != xs[1]:
+        return n * n if open_net else (n // 2) * (n - n // 2)
+    return n * (n - 1) // 2
+
+
+def total_weight_bound(net, c):
+    """(min or None, bound): the exact (min, max) total weight over the
+    simplex for 3-species closed networks, else (None, sum_j c_j max h_j)."""
+    if len(net["species"]) == 3 and not net.get("open"):
+        return _total_weight_range(net, c)
+    n = net["n_tot"]
+    return None, sum(cj * _factor_max(rv, n, net.get("open"))
+                     for cj, rv in zip(c, net["reactants"]))
 
 
 def _total_weight_range(net, c):
@@ -125,7 +157,7 @@ def quantize(net, precision_bits=7, max_total=None):
             raise ValueError("no scale reaches the precision")
     min_total = None
     if max_total is None:
-        min_total, max_total = _total_weight_range(net, c)
+        min_total, max_total = total_weight_bound(net, c)
     B = max(1, (max_total - 1).bit_length()) if max_total > 1 else 1
     W = 1 << B
     Lam = math.ldexp(1.0, B) / s

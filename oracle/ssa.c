@@ -18,6 +18,13 @@
  * Time enters only through the number of events each replica runs (the
  * budgets computed by the caller, see poisson.py).
  *
+ * Open networks (reactions that need not conserve the molecule count, the
+ * general networks the paper leaves to future work, Sec. 6): every species
+ * count is capped at cap = n_tot; a selected reaction whose firing would
+ * leave some count above the cap does nothing (a null event), which is the
+ * chain of the network on the truncated state space {0 <= N_x <= cap}.
+ * Step 4 then checks N >= 0 and N <= cap instead of conservation.
+ *
  * Random numbers follow the draw contract written independently in
  * philox.py (Philox4x32-10, Salmon et al. SC'11):
  *   key      = (seed low 32 bits, seed high 32 bits)
@@ -58,7 +65,9 @@ typedef struct {
     int64_t c[ORC_MAX_R];
     int32_t B;
     uint32_t z_shared;   /* Z of the SHARED draw */
-    int64_t n_tot;
+    int64_t n_tot;       /* conserved count; the per-species cap if open */
+    int32_t open;        /* 1: the count is not conserved (capped at n_tot) */
+    int32_t reserved;
 } orc_net;
 
 enum { ORC_DRAW_EVENT = 1, ORC_DRAW_PLAIN = 4, ORC_DRAW_SHARED = 6 };
@@ -153,19 +162,25 @@ static int select_reaction(const orc_net *net, const int64_t *N, uint32_t n)
     return -1;
 }
 
-/* One event of the direct method.  Returns the reaction index, or -1 for a
- * null event; returns -2 on an invariant violation. */
+/* One event of the direct method.  Returns the reaction index, -1 for a
+ * null event, -3 for a selected reaction blocked by the cap (open networks;
+ * the state is unchanged); returns -2 on an invariant violation. */
 static int one_event(const orc_net *net, int64_t *N, uint32_t n)
 {
     int r = select_reaction(net, N, n);
     if (r < 0) return -1;
+    if (net->open) {
+        /* a firing that would pass the cap does nothing */
+        for (int x = 0; x < net->n_species; ++x)
+            if (N[x] + net->products[r][x] - net->reactants[r][x] > net->n_tot) return -3;
+    }
     int64_t tot = 0;
     for (int x = 0; x < net->n_species; ++x) {
         N[x] += net->products[r][x] - net->reactants[r][x];
-        if (N[x] < 0) return -2;
+        if (N[x] < 0 || (net->open && N[x] > net->n_tot)) return -2;
         tot += N[x];
     }
-    if (tot != net->n_tot) return -2;
+    if (!net->open && tot != net->n_tot) return -2;
     return r;
 }
 

@@ -48,7 +48,8 @@ class _Net(ctypes.Structure):
                 ("reactants", (ctypes.c_int32 * _MAX_S) * _MAX_R),
                 ("products", (ctypes.c_int32 * _MAX_S) * _MAX_R),
                 ("c", ctypes.c_int64 * _MAX_R), ("B", ctypes.c_int32),
-                ("z_shared", ctypes.c_uint32), ("n_tot", ctypes.c_int64)]
+                ("z_shared", ctypes.c_uint32), ("n_tot", ctypes.c_int64),
+                ("open", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,6 +98,7 @@ def c_net(net, q):
     cn.B = q["B"]
     cn.z_shared = q.get("z_shared") or 0
     cn.n_tot = net["n_tot"]
+    cn.open = 1 if net.get("open") else 0
     return cn
 
 
@@ -125,8 +127,8 @@ def run_events(net, q, seed, net_id, first, counts, E0, K, draw=DRAW_EVENT,
                           _p(K, ctypes.c_uint64), _p(real, ctypes.c_uint64),
                           tp, traj_len, threads)
     if rc != 0:
-        raise AssertionError("oracle invariant violated (negative count or "
-                             "molecule count not conserved)")
+        raise AssertionError("oracle invariant violated (negative count, count above the "
+                             "cap, or molecule count not conserved)")
     return counts, real, traj
 
 
@@ -185,7 +187,12 @@ class OracleEnsemble:
     def init(self, mode):
         if mode[0] == "fixed":
             c = np.array(mode[1], dtype=np.int32)
-            if c.sum() != self.net["n_tot"] or (c < 0).any():
+            if len(c) != len(self.net["species"]) or (c < 0).any():
+                raise ValueError("one non-negative count per species")
+            if self.net.get("open"):
+                if (c > self.net["n_tot"]).any():
+                    raise ValueError("initial counts above the cap n_tot")
+            elif c.sum() != self.net["n_tot"]:
                 raise ValueError("initial counts must sum to N_tot")
             self.counts = np.tile(c, (self.n, 1))
         elif mode[0] == "multinomial":
@@ -269,8 +276,11 @@ def py_events(net, q, seed, net_id, replica, counts, E0, K, draw=DRAW_EVENT):
             if n < m:
                 r = j
                 break
+        if r >= 0 and net.get("open") and any(a + d > net["n_tot"] for a, d in zip(N, nu[r])):
+            r = -1          # open network: a firing past the cap does nothing
         picked.append(r)
         if r >= 0:
             N = [a + d for a, d in zip(N, nu[r])]
-            assert min(N) >= 0 and sum(N) == net["n_tot"]
+            assert min(N) >= 0
+            assert max(N) <= net["n_tot"] if net.get("open") else sum(N) == net["n_tot"]
     return N, picked
