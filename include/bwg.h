@@ -48,6 +48,13 @@ enum {
 
 /* flags of bwg_net_desc */
 #define BWG_EXACT_INTEGER 1u   /* rates are the integer weights (paper mode) */
+/* An open network: reactions need not conserve the molecule count (the
+ * general networks the paper leaves to future work, Sec. 6).  Every species
+ * count is capped at n_tot: a selected reaction whose firing would leave a
+ * count above n_tot does nothing (a null event; the chain on the truncated
+ * state space {0 <= N_x <= n_tot}).  Initial counts are each at most n_tot.
+ * Runs on the bit-sliced engine's kernel compiled for the network only. */
+#define BWG_OPEN 2u
 
 /* engines of bwg_opts */
 #define BWG_ENGINE_BITWISE 0   /* bit-sliced words, 32 replicas per lane: the
@@ -76,9 +83,13 @@ typedef struct bwg_ens bwg_ens;
  * A reaction network.  Reaction j consumes reactants[j*S + x] molecules of
  * species x and produces products[j*S + x]; total order 1 or 2; every
  * reaction must conserve the molecule count (the paper's networks conserve
- * N_tot, Sec. 2).  rates[j] is the mass-action constant: the propensity is
- * rates[j] * h_j(N) with h_j = N_X, N_X N_Y or N_X (N_X - 1)/2 (the forms of
- * Eq. (7) of the paper).  All pointers are read during the call only.
+ * N_tot, Sec. 2) unless the network is open (BWG_OPEN).  rates[j] is the
+ * mass-action constant: the propensity is rates[j] * h_j(N) with h_j = N_X,
+ * N_X N_Y or N_X (N_X - 1)/2 (the forms of Eq. (7) of the paper).  Networks
+ * of 3 species that conserve the count run every engine; other species
+ * counts (1..BWG_MAX_SPECIES) and open networks run the bit-sliced kernel
+ * compiled for the network, with changes of at most 2 per species and
+ * reaction.  All pointers are read during the call only.
  */
 typedef struct {
     int32_t n_species;          /* S, <= BWG_MAX_SPECIES                      */
@@ -91,7 +102,7 @@ typedef struct {
     const double *hop_rates;    /* [S] per molecule per direction, or NULL    */
     int32_t site_planes;        /* bits per species count on a lattice site   */
     int32_t precision_bits;     /* rate quantisation, 0 = default (7)         */
-    uint32_t flags;             /* BWG_EXACT_INTEGER                          */
+    uint32_t flags;             /* BWG_EXACT_INTEGER, BWG_OPEN                */
     uint32_t reserved;
 } bwg_net_desc;
 
@@ -208,10 +219,16 @@ typedef struct {
 /* ---- networks (host only, synchronous) ------------------------------- */
 
 /* Validate and quantise a network (integer weights c_j, scale, bound 2^B).
- * EINVAL: order not in {1,2}, not count-conserving, negative or non-finite
- * rate, n_tot < 1, sizes out of range; ERANGE: weights or bound beyond 32
- * threshold planes or n_tot beyond the count planes.  The returned handle is
- * owned by the caller (bwg_net_destroy). */
+ * The bound: for 3 species conserving the count, the largest total weight
+ * over the simplex (enumerated); else sum_j c_j max h_j, each reaction's
+ * largest factor over the simplex of n_tot molecules (N_X: n_tot, pairs
+ * floor(n/2) ceil(n/2), N_X (N_X - 1)/2: n(n-1)/2) or, open, over the box of
+ * counts at most n_tot (n, n^2, n(n-1)/2).
+ * EINVAL: order not in {1,2}, not count-conserving (and not open), negative
+ * or non-finite rate, n_tot < 1, sizes out of range; ERANGE: weights or
+ * bound beyond 32 threshold planes or n_tot beyond the count planes;
+ * EUNSUPPORTED: a lattice that is open or not of 3 species.  The returned
+ * handle is owned by the caller (bwg_net_destroy). */
 int bwg_net_create(const bwg_net_desc *desc, bwg_net **out);
 int bwg_net_quantized(const bwg_net *net, bwg_qnet *out);
 
@@ -254,8 +271,9 @@ int bwg_ensemble_create(const bwg_net *net, uint64_t n_replicas, uint64_t seed,
 
 /* Set every replica's initial state and reset time, event counters and the
  * advance index.  mode BWG_INIT_FIXED takes counts[S] (host pointer, summing
- * to n_tot); BWG_INIT_MULTINOMIAL draws the paper's racemic multinomial start
- * (Frank species only).  Lattices take BWG_INIT_FIXED (counts[3] on every
+ * to n_tot; open networks: each at most n_tot, ERANGE otherwise);
+ * BWG_INIT_MULTINOMIAL draws the paper's racemic multinomial start (Frank
+ * species only).  Lattices take BWG_INIT_FIXED (counts[3] on every
  * site), BWG_INIT_SITES (counts[sites*3]) or BWG_INIT_UNIFORM_SITE (counts =
  * {lo, hi}; the draw of replica i, site s is exact: 32-bit multiply-shift
  * with rejection on INIT draws); ERANGE if a site would exceed T.  Async. */

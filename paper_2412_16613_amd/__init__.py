@@ -61,7 +61,8 @@ class Network:
         d.hop_rates = self._hops
         d.site_planes = int(net.get("site_planes", 0))
         d.precision_bits = int(precision_bits)
-        d.flags = _abi.BWG_EXACT_INTEGER if net.get("exact_integer") else 0
+        d.flags = ((_abi.BWG_EXACT_INTEGER if net.get("exact_integer") else 0) |
+                   (_abi.BWG_OPEN if net.get("open") else 0))
         h = ctypes.c_void_p()
         _abi.check(L.bwg_net_create(ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
@@ -150,6 +151,7 @@ class Ensemble:
         self.handle = h
         self.groups = (self.M + 31) // 32
         self.engine = engine
+        self.n_species = len(network.net["species"])
 
     def _stream(self):
         return _stream_ptr(self.torch.cuda.current_stream(self.device))
@@ -215,7 +217,7 @@ class Ensemble:
     def read_counts(self, out=None):
         t = self.torch
         if out is None:
-            out = t.empty((self.M, 3), dtype=t.int32, device=self.device)
+            out = t.empty((self.M, self.n_species), dtype=t.int32, device=self.device)
         _abi.check(_lib().bwg_ensemble_read_counts(self.handle, ctypes.c_void_p(out.data_ptr()),
                                                    self._stream()))
         return out

@@ -18,6 +18,7 @@ ERROR_NAMES = {BWG_EINVAL: "EINVAL", BWG_ERANGE: "ERANGE", BWG_ENOMEM: "ENOMEM",
 BWG_MAX_SPECIES = 8
 BWG_MAX_REACTIONS = 16
 BWG_EXACT_INTEGER = 1
+BWG_OPEN = 2
 BWG_ENGINE_BITWISE = 0
 BWG_ENGINE_PLAIN = 1
 BWG_ENGINE_LANES = 2

@@ -9,19 +9,17 @@ namespace bwg {
 
 // Every replica starts from the same counts: plane q of species x is all ones
 // on live lanes where bit q of counts[x] is set.
-__global__ void init_fixed_kernel(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
-                                  int32_t c0, int32_t c1, int32_t c2, uint64_t *E,
-                                  uint64_t *Et, uint64_t *real)
+__global__ void init_fixed_kernel(uint32_t *planes, int S, int nb, uint64_t wp, uint64_t M,
+                                  SpeciesCounts c, uint64_t *E, uint64_t *Et, uint64_t *real)
 {
     const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= wp) return;
     const uint64_t base = 32 * w;
     uint32_t live = 0;
     if (base < M) live = (M - base) >= 32 ? 0xFFFFFFFFu : ((1u << (M - base)) - 1u);
-    const int32_t c[3] = {c0, c1, c2};
-    for (int x = 0; x < 3; ++x)
+    for (int x = 0; x < S; ++x)
         for (int q = 0; q < nb; ++q)
-            planes[((uint64_t)x * nb + q) * wp + w] = ((c[x] >> q) & 1) ? live : 0u;
+            planes[((uint64_t)x * nb + q) * wp + w] = ((c.v[x] >> q) & 1) ? live : 0u;
     for (int l = 0; l < 32; ++l) {
         E[base + l] = 0;
         Et[base + l] = 0;
@@ -128,14 +126,14 @@ __device__ __forceinline__ int32_t plane_count(const uint32_t *planes, int x, in
     return v;
 }
 
-__global__ void read_counts_planes_kernel(const uint32_t *planes, int nb, uint64_t wp,
+__global__ void read_counts_planes_kernel(const uint32_t *planes, int S, int nb, uint64_t wp,
                                           uint64_t M, int32_t *dst)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const uint64_t w = i >> 5;
     const int lane = (int)(i & 31);
-    for (int x = 0; x < 3; ++x) dst[3 * i + x] = plane_count(planes, x, nb, wp, w, lane);
+    for (int x = 0; x < S; ++x) dst[S * i + x] = plane_count(planes, x, nb, wp, w, lane);
 }
 
 __global__ void read_counts_plain_kernel(const int32_t *counts, uint64_t M, int32_t *dst)
@@ -247,12 +245,15 @@ static inline dim3 grid_for(uint64_t n, int block)
     return dim3((uint32_t)((n + block - 1) / block));
 }
 
-hipError_t launch_init_fixed(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
-                             const int32_t c[3], uint64_t *E, uint64_t *Et, uint64_t *real,
+hipError_t launch_init_fixed(uint32_t *planes, int S, int nb, uint64_t wp, uint64_t M,
+                             const int32_t *c, uint64_t *E, uint64_t *Et, uint64_t *real,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(init_fixed_kernel, grid_for(wp, 128), dim3(128), 0, s, planes, nb, wp,
-                       M, c[0], c[1], c[2], E, Et, real);
+    if (S < 1 || S > 8) return hipErrorInvalidValue;  // SpeciesCounts holds 8
+    SpeciesCounts sc{};
+    for (int x = 0; x < S; ++x) sc.v[x] = c[x];
+    hipLaunchKernelGGL(init_fixed_kernel, grid_for(wp, 128), dim3(128), 0, s, planes, S, nb, wp,
+                       M, sc, E, Et, real);
     return hipGetLastError();
 }
 
@@ -288,10 +289,10 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_read_counts_planes(const uint32_t *planes, int nb, uint64_t wp, uint64_t M,
-                                     int32_t *dst, hipStream_t s)
+hipError_t launch_read_counts_planes(const uint32_t *planes, int S, int nb, uint64_t wp,
+                                     uint64_t M, int32_t *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(read_counts_planes_kernel, grid_for(M, 256), dim3(256), 0, s, planes,
+    hipLaunchKernelGGL(read_counts_planes_kernel, grid_for(M, 256), dim3(256), 0, s, planes, S,
                        nb, wp, M, dst);
     return hipGetLastError();
 }

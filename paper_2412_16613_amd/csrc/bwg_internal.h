@@ -73,6 +73,11 @@ using WmLaunch = hipError_t (*)(const WmArgs &, hipStream_t, int block);
 // Table of bit-sliced kernel instantiations: species planes NB, threshold
 // plane capacity BC, product shift FA and unimolecular weight CU (-1: taken
 // at run time).
+// Initial counts of up to BWG_MAX_SPECIES species, passed by value.
+struct SpeciesCounts {
+    int32_t v[8];
+};
+
 struct WmVariant {
     int nb, bc, fa, cu;
     int nt, bs;  // molecule count and selection planes it is fixed to (nt = 0: any)
@@ -214,9 +219,9 @@ hipError_t launch_lat_sites(const uint32_t *planes, int S, int P, uint64_t first
 hipError_t launch_lat_histogram(const int32_t *tot, uint64_t M, int n_bins, uint64_t *dst,
                                 hipStream_t s);
 
-hipError_t launch_init_fixed(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
-                             const int32_t counts[3], uint64_t *E, uint64_t *Etgt,
-                             uint64_t *real, hipStream_t s);
+hipError_t launch_init_fixed(uint32_t *planes, int S, int nb, uint64_t wp, uint64_t M,
+                             const int32_t *c, uint64_t *E, uint64_t *Et, uint64_t *real,
+                             hipStream_t s);
 hipError_t launch_init_multinomial(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
                                    int64_t n_tot, uint64_t seed, uint32_t net_id,
                                    uint64_t *E, uint64_t *Etgt, uint64_t *real,
@@ -230,7 +235,7 @@ hipError_t launch_budget(const uint64_t *table, uint64_t len, int64_t k_lo,
                          const uint64_t *E, uint64_t *Etgt, hipStream_t s);
 hipError_t launch_add_u64(uint64_t *p, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
-hipError_t launch_read_counts_planes(const uint32_t *planes, int nb, uint64_t wp,
+hipError_t launch_read_counts_planes(const uint32_t *planes, int S, int nb, uint64_t wp,
                                      uint64_t M, int32_t *dst, hipStream_t s);
 hipError_t launch_read_counts_plain(const int32_t *counts, uint64_t M, int32_t *dst,
                                     hipStream_t s);

@@ -58,13 +58,64 @@ __device__ __forceinline__ void add_one_three(uint32_t (&acc)[WP], uint32_t a1, 
     }
 }
 
+// Lanes whose count x is at least the constant K (K < 2^NB): the complement
+// of the borrow of x - K, one instruction per plane.
+template <int NB, uint32_t K>
+__device__ __forceinline__ uint32_t geq_const(const uint32_t (&x)[NB])
+{
+    uint32_t br = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) br = ((K >> q) & 1u) ? (~x[q] | br) : (~x[q] & br);
+    return ~br;
+}
+
+// Counts of S species of word w (planes at or above the stored count are
+// zero), and back after a launch that ran the word's events up to hi.
+template <int S, int NB>
+__device__ __forceinline__ void load_species(const WmArgs &a, uint64_t w, uint32_t (&N)[S][NB])
+{
+    if constexpr (S == 3) {
+        load_word<NB>(a, w, N[0], N[1], N[2]);
+    } else {
+        const int nbm = a.nb_mem;
+#pragma unroll
+        for (int x = 0; x < S; ++x)
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                N[x][q] = q < nbm ? a.planes[((uint64_t)x * nbm + q) * a.wp + w] : 0u;
+    }
+}
+
+template <int S, int NB>
+__device__ __forceinline__ void store_species(const WmArgs &a, uint64_t w, uint32_t live,
+                                              uint64_t hi, const uint32_t (&N)[S][NB])
+{
+    if constexpr (S == 3) {
+        store_word<NB>(a, w, live, hi, N[0], N[1], N[2]);
+    } else {
+        const int nbm = a.nb_mem;
+#pragma unroll
+        for (int x = 0; x < S; ++x)
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < nbm) a.planes[((uint64_t)x * nbm + q) * a.wp + w] = N[x][q];
+        uint64_t *Ew = a.E + 32 * w;
+        const uint64_t *T = a.Etgt + 32 * w;
+        for (int l = 0; l < 32; ++l) {
+            if (!((live >> l) & 1u)) continue;
+            const uint64_t x = Ew[l], y = T[l];
+            Ew[l] = hi < x ? x : (hi > y ? y : hi);
+        }
+    }
+}
+
 // Word loops of the per-network kernels: the event itself is a functor
 // ev(d, act, N, nreal) that takes the threshold planes d (consumed), the
 // active lanes and the counts N[species][plane], and adds its real lanes to
 // nreal; ev.init(N) runs once per launch before the first event (the functor
-// may keep quantities it updates from event to event).  gen_word: one thread
-// per word, as wm_word.
-template <int NB, int BC, typename Event>
+// may keep quantities it updates from event to event).  S species (3 unless
+// given).  gen_word: one thread per word, as wm_word.
+template <int NB, int BC, int S = 3, typename Event>
 __device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, Event ev)
 {
     if (w >= a.n_words) return;
@@ -72,8 +123,8 @@ __device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, Event ev)
     const uint64_t *E = a.E + 32 * w;
     const uint64_t *T = a.Etgt + 32 * w;
     const WordWindow win = word_window(a, E, T, live);
-    uint32_t N[3][NB];
-    load_word<NB>(a, w, N[0], N[1], N[2]);
+    uint32_t N[S][NB];
+    load_species<S, NB>(a, w, N);
     if (win.lo < win.hi) {
         const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
         const int nq = (a.B + 3) / 4;
@@ -93,13 +144,13 @@ __device__ __forceinline__ void gen_word(const WmArgs &a, uint64_t w, Event ev)
         }
         a.real[w] += nreal;
     }
-    store_word<NB>(a, w, live, win.hi, N[0], N[1], N[2]);
+    store_species<S, NB>(a, w, live, win.hi, N);
 }
 
 // gen_word_pc: the producer/consumer form of wm_word_pc (four waves per 128
 // words, Philox planes handed over through rings of 2 x PH events in LDS, a
 // barrier per PH events, the workgroup's largest window as step count).
-template <int NB, int BC, int PH, typename Event>
+template <int NB, int BC, int PH, int S = 3, typename Event>
 __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 4][64],
                                             uint64_t *wave_span, Event ev)
 {
@@ -154,12 +205,14 @@ __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 
         return;
     }
 
-    uint32_t N[3][NB];
+    uint32_t N[S][NB];
     if (valid) {
-        load_word<NB>(a, w, N[0], N[1], N[2]);
+        load_species<S, NB>(a, w, N);
     } else {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) N[0][q] = N[1][q] = N[2][q] = 0u;
+        for (int x = 0; x < S; ++x)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) N[x][q] = 0u;
     }
     ev.init(N);
     uint64_t nreal = 0;
@@ -190,7 +243,7 @@ __device__ __forceinline__ void gen_word_pc(const WmArgs &a, uint4 (*ring)[BC / 
     }
     if (valid) {
         if (lo < hi) a.real[w] += nreal;
-        store_word<NB>(a, w, live, hi, N[0], N[1], N[2]);
+        store_species<S, NB>(a, w, live, hi, N);
     }
 }
 

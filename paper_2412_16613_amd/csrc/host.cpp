@@ -77,6 +77,34 @@ static void total_weight_range(const bwg_net &n, int64_t *lo, int64_t *hi)
     *hi = best;
 }
 
+// Bound of the total weight for every network but the 3-species closed
+// ones: sum_j c_j max h_j, each reaction's largest factor over the state
+// space -- the simplex of n_tot molecules (N_X: n, N_X N_Y: floor(n/2)
+// ceil(n/2), N_X (N_X - 1) / 2: n (n - 1) / 2) or, for an open network, the
+// box of counts at most n_tot (n, n^2, n (n - 1) / 2: the corner).  Returns
+// false if the bound passes 2^62.
+static bool total_weight_bound(const bwg_net &n, int64_t *hi)
+{
+    const __int128 N = n.n_tot;
+    __int128 t = 0;
+    for (int j = 0; j < n.R; ++j) {
+        int xs[2], k = 0;
+        for (int x = 0; x < n.S; ++x)
+            for (int m = 0; m < n.reac[j * n.S + x]; ++m) xs[k++] = x;
+        __int128 h;
+        if (k == 1)
+            h = N;
+        else if (xs[0] != xs[1])
+            h = n.open ? N * N : (N / 2) * (N - N / 2);
+        else
+            h = N * (N - 1) / 2;
+        t += (__int128)n.q.c[j] * h;
+        if (t > ((__int128)1 << 62)) return false;
+    }
+    *hi = (int64_t)t;
+    return true;
+}
+
 static int ilog2_exact(int64_t c)  // log2 of a power of two, else -2
 {
     if (c <= 0 || (c & (c - 1))) return -2;
@@ -89,7 +117,7 @@ static int ilog2_exact(int64_t c)  // log2 of a power of two, else -2
 static void classify(bwg_net &n)
 {
     n.shape_ok = false;
-    if (n.S != 3) return;
+    if (n.S != 3 || n.open) return;
     static const int32_t RX[5][2][3] = {
         {{0, 0, 1}, {1, 0, 0}},  // A -> L
         {{0, 0, 1}, {0, 1, 0}},  // A -> D
@@ -131,7 +159,7 @@ static void classify(bwg_net &n)
 static void classify_plain(bwg_net &n)
 {
     n.plain_ok = false;
-    if (n.S != 3 || n.R > 16) return;
+    if (n.S != 3 || n.open || n.R > 16) return;
     for (int j = 0; j < n.R; ++j) {
         const int32_t *r = &n.reac[j * 3], *p = &n.prod[j * 3];
         PlainReaction &rx = n.prx[j];
@@ -159,10 +187,27 @@ static void classify_plain(bwg_net &n)
 // Reaction table of the general bit-sliced kernel: the weight kind of each
 // reaction (N_X; N_L N_D, N_L N_A, N_D N_A; N_X (N_X - 1) / 2), its integer
 // weight and state change.
+// Networks of other than 3 species and open networks: the compiled general
+// kernel takes any such table whose weights fit 32 bits and whose changes
+// are in {-2..2} per species.
+static void classify_wide(bwg_net &n)
+{
+    n.wide_ok = false;
+    if (!n.wide || n.R > bwg::kGenMaxR) return;
+    for (int j = 0; j < n.R; ++j) {
+        if (n.q.c[j] >= (1ll << 32)) return;
+        for (int x = 0; x < n.S; ++x) {
+            const int dv = n.prod[j * n.S + x] - n.reac[j * n.S + x];
+            if (dv < -2 || dv > 2) return;
+        }
+    }
+    n.wide_ok = true;
+}
+
 static void classify_generic(bwg_net &n)
 {
     n.gen_ok = false;
-    if (n.S != 3 || n.R > bwg::kGenMaxR) return;
+    if (n.S != 3 || n.open || n.R > bwg::kGenMaxR) return;
     bwg::GenNet &g = n.gen;
     g = bwg::GenNet{};
     g.R = n.R;
@@ -202,10 +247,14 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     if (!d->reactants || !d->products || !d->rates) return fail(BWG_EINVAL, "null table");
     if (d->n_tot < 1) return fail(BWG_EINVAL, "n_tot must be >= 1");
     const bool lattice = d->lx || d->ly;
-    if (S != 3) return fail(BWG_EUNSUPPORTED, "the GPU engines implement 3 species");
+    const bool open_net = (d->flags & BWG_OPEN) != 0;
+    if (lattice && (S != 3 || open_net))
+        return fail(BWG_EUNSUPPORTED, "lattices are closed networks of 3 species");
     if (!lattice && d->n_tot >= (1ll << 14)) return fail(BWG_ERANGE, "n_tot beyond 14 count planes");
     auto n = new bwg_net();
     n->S = S;
+    n->open = open_net;
+    n->wide = S != 3 || open_net;
     n->R = R;
     n->reac.assign(d->reactants, d->reactants + S * R);
     n->prod.assign(d->products, d->products + S * R);
@@ -226,7 +275,7 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
             delete n;
             return fail(BWG_EINVAL, "reaction %d: order %d not in {1, 2}", j, o);
         }
-        if (o != op) {
+        if (o != op && !open_net) {
             delete n;
             return fail(BWG_EINVAL, "reaction %d does not conserve the molecule count", j);
         }
@@ -305,8 +354,15 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
             q.c[j] = (int64_t)c;
         }
     }
-    int64_t min_total;
-    total_weight_range(*n, &min_total, &q.max_total);
+    int64_t min_total = -1;
+    if (n->wide) {
+        if (!total_weight_bound(*n, &q.max_total)) {
+            delete n;
+            return fail(BWG_ERANGE, "total weight beyond 32 threshold planes");
+        }
+    } else {
+        total_weight_range(*n, &min_total, &q.max_total);
+    }
     int B = 1;
     while (B < 63 && (1ll << B) < q.max_total) ++B;
     if (B > 32) {
@@ -326,7 +382,8 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     classify(*n);
     classify_plain(*n);
     classify_generic(*n);
-    q.gpu_ok = (n->shape_ok || n->gen_ok) ? 1 : 0;
+    classify_wide(*n);
+    q.gpu_ok = (n->shape_ok || n->gen_ok || n->wide_ok) ? 1 : 0;
     *out = n;
     return BWG_OK;
 }
@@ -426,7 +483,7 @@ static Layout layout(const bwg_net *n, uint64_t M, int engine, uint64_t table_ca
     uint64_t off = 0;
     if (engine != BWG_ENGINE_PLAIN) {
         L.planes = off;
-        off = align256(off + 3ull * (uint64_t)n->q.b * L.wp * 4);
+        off = align256(off + (uint64_t)n->S * (uint64_t)n->q.b * L.wp * 4);
         L.counts = ~0ull;
     } else {
         L.counts = off;
@@ -468,6 +525,13 @@ static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
 {
     *v = nullptr;
     if (gv) *gv = nullptr;
+    if (engine == BWG_ENGINE_BITWISE && n->wide) {
+        // only the kernel compiled for the network (checked at creation)
+        if (!n->wide_ok)
+            return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for this network (changes beyond "
+                                          "+-2 or weights beyond 32 bits)");
+        return BWG_OK;
+    }
     if (engine == BWG_ENGINE_BITWISE && (generic || !n->shape_ok)) {
         const GenVariant *g = pick_gen_variant(n);
         if (!g)
@@ -569,7 +633,9 @@ int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint3
     if (n->lat) return lat_bind(e);
     check_engine(n, e->engine, &e->var, &e->gvar, o && (o->flags & BWG_OPT_GENERIC_KERNEL));
     const bool jit_ok = !(o && (o->flags & BWG_OPT_NO_JIT));
-    if (e->gvar && jit_ok) {
+    if (n->wide && e->engine == BWG_ENGINE_BITWISE && !jit_ok)
+        return fail(BWG_EUNSUPPORTED, "this network runs only its compiled kernel (no BWG_OPT_NO_JIT)");
+    if ((e->gvar || (n->wide && e->engine == BWG_ENGINE_BITWISE)) && jit_ok) {
         const int rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
         if (rc) return rc;
     }
@@ -689,24 +755,30 @@ extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts
     hipStream_t s = (hipStream_t)stream;
     const bwg_net *n = e->net;
     if (e->lat) return lat_init(e, mode, counts, s);
-    int32_t c[3] = {0, 0, 0};
+    int32_t c[BWG_MAX_SPECIES] = {};
     if (mode == BWG_INIT_FIXED) {
         if (!counts) return fail(BWG_EINVAL, "fixed init needs counts");
         int64_t sum = 0;
-        for (int x = 0; x < 3; ++x) {
+        for (int x = 0; x < n->S; ++x) {
             if (counts[x] < 0) return fail(BWG_EINVAL, "negative initial count");
+            if (n->open && counts[x] > n->n_tot)
+                return fail(BWG_ERANGE, "initial count %d above the cap n_tot = %lld", counts[x],
+                            (long long)n->n_tot);
             c[x] = counts[x];
             sum += counts[x];
         }
-        if (sum != n->n_tot)
+        if (!n->open && sum != n->n_tot)
             return fail(BWG_EINVAL, "initial counts sum to %lld, not n_tot = %lld", (long long)sum,
                         (long long)n->n_tot);
-    } else if (mode != BWG_INIT_MULTINOMIAL) {
+    } else if (mode == BWG_INIT_MULTINOMIAL) {
+        if (n->wide) return fail(BWG_EINVAL, "the multinomial start is for the Frank species");
+    } else {
         return fail(BWG_EINVAL, "unknown init mode %d", mode);
     }
     if (e->engine != BWG_ENGINE_PLAIN) {
         if (mode == BWG_INIT_FIXED)
-            HIP_TRY(launch_init_fixed(e->planes, e->nb, e->wp, e->M, c, e->E, e->Et, e->real, s));
+            HIP_TRY(launch_init_fixed(e->planes, n->S, e->nb, e->wp, e->M, c, e->E, e->Et, e->real,
+                                      s));
         else
             HIP_TRY(launch_init_multinomial(e->planes, e->nb, e->wp, e->M, n->n_tot, e->seed,
                                             e->net_id, e->E, e->Et, e->real, s));
@@ -1010,7 +1082,7 @@ extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)
     hipStream_t s = (hipStream_t)stream;
     if (e->lat) return lat_read_counts(e, dst, s);
     if (e->engine != BWG_ENGINE_PLAIN)
-        HIP_TRY(launch_read_counts_planes(e->planes, e->nb, e->wp, e->M, dst, s));
+        HIP_TRY(launch_read_counts_planes(e->planes, e->net->S, e->nb, e->wp, e->M, dst, s));
     else
         HIP_TRY(launch_read_counts_plain(e->counts, e->M, dst, s));
     return BWG_OK;
@@ -1020,6 +1092,7 @@ extern "C" int bwg_ensemble_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst,
 {
     if (!e || !dst) return fail(BWG_EINVAL, "null argument");
     if (n_bins < 1 || n_bins > 16384) return fail(BWG_EINVAL, "n_bins %d out of range", n_bins);
+    if (e->net->wide) return fail(BWG_EUNSUPPORTED, "the histogram is of the Frank species");
     hipStream_t s = (hipStream_t)stream;
     if (e->lat) return lat_histogram(e, n_bins, dst, s);
     HIP_TRY(launch_histogram(e->engine != BWG_ENGINE_PLAIN ? e->planes : nullptr, e->counts,
@@ -1034,6 +1107,7 @@ extern "C" int bwg_ensemble_record(bwg_ens *e, const double *t_grid, uint32_t n_
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     if (e->lat) return fail(BWG_EUNSUPPORTED, "record runs on well-mixed ensembles");
+    if (e->net->wide) return fail(BWG_EUNSUPPORTED, "record follows the Frank species");
     if (n_points && !t_grid) return fail(BWG_EINVAL, "null time grid");
     if (n_points && n_sel && (!dev_sel || !dev_out))
         return fail(BWG_EINVAL, "null selection or output");

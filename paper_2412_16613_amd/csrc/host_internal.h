@@ -52,6 +52,11 @@ struct bwg_net {
     bool plain_ok = false;
     bwg::GenNet gen{};      // reaction table of the general bit-sliced kernel
     bool gen_ok = false;
+    // open networks (BWG_OPEN: counts capped at n_tot, not conserved) and
+    // networks of other than 3 species run only kernels compiled for them
+    bool open = false;
+    bool wide = false;      // S != 3 or open
+    bool wide_ok = false;   // such a network fits the compiled general kernel
     // lattice networks
     bool lat = false;
     bwg::LatShape lsh{};

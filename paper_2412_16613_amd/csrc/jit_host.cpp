@@ -177,6 +177,151 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
     return o.str();
 }
 
+// Source of the kernels of a network of S species (any S up to 8) or an open
+// network (counts capped at n_tot): the same structure as jit_source with
+// the weight kinds of S species -- N_X, the pair counts N_X N_Y (x < y) and
+// N_X (N_X - 1) / 2 -- and, for an open network, each reaction's selected
+// lanes cleared where a count it raises by dv would pass the cap (count >=
+// cap - dv + 1 before the event): the oracle's blocked firing.
+static std::string jit_source_wide(const bwg_net &n, int NB, int BC)
+{
+    const int S = n.S, R0 = n.R;
+    auto dv = [&](int j, int x) { return n.prod[j * S + x] - n.reac[j * S + x]; };
+    auto changes = [&](int j) {
+        for (int x = 0; x < S; ++x)
+            if (dv(j, x)) return true;
+        return false;
+    };
+    int R = R0;
+    while (R > 0 && !changes(R - 1)) --R;
+    // weight operand of each reaction: species x (unimolecular), pair (x, y)
+    // or dimer x
+    std::vector<std::string> opnd(R);
+    std::vector<bool> wide_op(R);
+    bool pair_used[8][8] = {}, dimer_used[8] = {};
+    for (int j = 0; j < R; ++j) {
+        int xs[2], k = 0;
+        for (int x = 0; x < S; ++x)
+            for (int m = 0; m < n.reac[j * S + x]; ++m) xs[k++] = x;
+        if (k == 1) {
+            opnd[j] = "N[" + std::to_string(xs[0]) + "]";
+            wide_op[j] = false;
+        } else if (xs[0] != xs[1]) {
+            opnd[j] = "hp" + std::to_string(xs[0]) + std::to_string(xs[1]);
+            wide_op[j] = true;
+            if (n.q.c[j]) pair_used[xs[0]][xs[1]] = true;
+        } else {
+            opnd[j] = "hd" + std::to_string(xs[0]);
+            wide_op[j] = true;
+            if (n.q.c[j]) dimer_used[xs[0]] = true;
+        }
+    }
+    int last_j = -1, last_bit = -1;
+    for (int j = 0; j < R; ++j)
+        if (n.q.c[j]) {
+            last_j = j;
+            last_bit = 63 - __builtin_clzll((uint64_t)n.q.c[j]);
+        }
+    std::ostringstream o;
+    o << "#include \"gen_device.h\"\n"
+      << "namespace bwg {\n"
+      << "constexpr int NB = " << NB << ", BC = " << BC << ", S = " << S << ", WH = 2 * NB;\n"
+      << "struct NetEvent {\n";
+    for (int x = 0; x < S; ++x)
+        for (int y = x + 1; y < S; ++y)
+            if (pair_used[x][y]) o << "    uint32_t hp" << x << y << "[WH];\n";
+    for (int x = 0; x < S; ++x)
+        if (dimer_used[x]) o << "    uint32_t hd" << x << "[WH];\n";
+    o << "    __device__ __forceinline__ void init(const uint32_t (&N)[S][NB])\n"
+      << "    {\n";
+    for (int x = 0; x < S; ++x)
+        for (int y = x + 1; y < S; ++y)
+            if (pair_used[x][y])
+                o << "        mul_planes<NB, WH>(hp" << x << y << ", N[" << x << "], N[" << y << "]);\n";
+    for (int x = 0; x < S; ++x) {
+        if (!dimer_used[x]) continue;
+        o << "        {\n"
+          << "            uint32_t xm[NB], p[WH];\n"
+          << "#pragma unroll\n"
+          << "            for (int q = 0; q < NB; ++q) xm[q] = N[" << x << "][q];\n"
+          << "            add_pm1<NB>(xm, 0u, ~0u);\n"
+          << "            mul_planes<NB, WH>(p, N[" << x << "], xm);\n"
+          << "#pragma unroll\n"
+          << "            for (int q = 0; q < WH; ++q) hd" << x << "[q] = q + 1 < WH ? p[q + 1] : 0u;\n"
+          << "        }\n";
+    }
+    o << "    }\n"
+      << "    __device__ __forceinline__ void operator()(uint32_t (&d)[BC], uint32_t act,\n"
+      << "                                               uint32_t (&N)[S][NB], uint64_t &nreal)\n"
+      << "    {\n"
+      << "        uint32_t lt = 0, realm = 0;\n"
+      << "        uint32_t mk[S][4] = {};\n";
+    static const int kSlot[5] = {3, 1, -1, 0, 2};  // change -2..2 -> mask index
+    for (int j = 0; j < R; ++j) {
+        const uint64_t c = (uint64_t)n.q.c[j];
+        if (!c) continue;  // weight 0: never selected
+        o << "        {  // reaction " << j << "\n"
+          << "            uint32_t br = 0;\n";
+        for (int b = 0; b < 32; ++b) {
+            if (!((c >> b) & 1u)) continue;
+            const bool keep = !(j == last_j && b == last_bit);
+            o << "            br |= sub_shifted<" << b << ", BC, " << (wide_op[j] ? "WH" : "NB")
+              << ", " << (keep ? "true" : "false") << ">(d, " << opnd[j] << ");\n";
+        }
+        o << "            const uint32_t ltj = lt | br;\n"
+          << "            uint32_t xi = ltj & ~lt & act;\n"
+          << "            lt = ltj;\n";
+        if (n.open) {
+            for (int x = 0; x < S; ++x)
+                if (dv(j, x) > 0)
+                    o << "            xi &= ~geq_const<NB, " << (n.n_tot - dv(j, x) + 1) << "u>(N[" << x
+                      << "]);\n";
+        }
+        if (changes(j)) o << "            realm |= xi;\n";
+        for (int x = 0; x < S; ++x)
+            if (dv(j, x)) o << "            mk[" << x << "][" << kSlot[dv(j, x) + 2] << "] |= xi;\n";
+        o << "        }\n";
+    }
+    o << "        nreal += (uint32_t)__builtin_popcount(realm);\n";
+    // species in order: each pair count takes the change of x times the
+    // other species' current count (X'Y' - XY = dX Y + dY X'), X (X - 1) / 2
+    // takes dX X + dX (dX - 1) / 2; then the count itself changes
+    for (int x = 0; x < S; ++x) {
+        bool any = false;
+        for (int j = 0; j < R; ++j) any |= n.q.c[j] && dv(j, x);
+        if (!any) continue;
+        const std::string X = std::to_string(x);
+        const std::string m = "mk[" + X + "][0], mk[" + X + "][1], mk[" + X + "][2], mk[" + X + "][3]";
+        for (int y = 0; y < S; ++y) {
+            if (y == x) continue;
+            const int a = x < y ? x : y, b = x < y ? y : x;
+            if (pair_used[a][b])
+                o << "        add_scaled<NB, WH>(hp" << a << b << ", N[" << y << "], " << m << ");\n";
+        }
+        if (dimer_used[x])
+            o << "        add_scaled<NB, WH>(hd" << x << ", N[" << x << "], " << m << ");\n"
+              << "        add_one_three<WH>(hd" << x << ", mk[" << x << "][1] | mk[" << x
+              << "][2], mk[" << x << "][3]);\n";
+        o << "        add_delta<NB>(N[" << x << "], " << m << ");\n";
+    }
+    o << "    }\n"
+      << "};\n"
+      << "extern \"C\" __global__ __launch_bounds__(" << kJitBlockLarge
+      << ") void bwg_jit_word(WmArgs a)\n"
+      << "{\n"
+      << "    gen_word<NB, BC, S>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, NetEvent{});\n"
+      << "}\n"
+      << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
+      << "{\n"
+      << "    constexpr int PH = " << kJitPcHalf << ";\n"
+      << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
+      << "    __shared__ uint64_t wave_span[4];\n"
+      << "    gen_word_pc<NB, BC, PH, S>(a, ring, wave_span, NetEvent{});\n"
+      << "}\n"
+      << "}  // namespace bwg\n";
+    return o.str();
+}
+
 // Compiles src with hipRTC for gfx950 and loads its kernels (one wave per
 // word and producer/consumer; for the Frank kernels also the
 // shared-threshold instantiation).
@@ -227,12 +372,14 @@ int jit_get(bwg_net *n, const JitKernel **out)
         *out = n->jit;
         return BWG_OK;
     }
-    if (!n->gen_ok) return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
+    if (!n->gen_ok && !n->wide_ok)
+        return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
     const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
     const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
     if (BC > 32 || NB > 14) return fail(BWG_EUNSUPPORTED, "network beyond 14 count / 32 threshold planes");
     JitKernel *k = nullptr;
-    const int rc = jit_compile(jit_source(*n, NB, BC), false, &k);
+    const int rc =
+        jit_compile(n->wide ? jit_source_wide(*n, NB, BC) : jit_source(*n, NB, BC), false, &k);
     if (rc) return rc;
     n->jit = k;
     *out = k;

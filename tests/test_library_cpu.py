@@ -262,3 +262,32 @@ def test_lattice_state_bytes():
     _abi.check(_abi.load().bwg_ensemble_state_bytes(n.handle, 1 << 16, None, ctypes.byref(b)))
     planes = 2048 * 4096 * 12 * 4
     assert planes <= b.value < planes + (64 << 20)
+
+
+def test_quantisation_of_wide_and_open_networks_matches_oracle():
+    # other species counts and open networks: the library's bound and
+    # weights equal the oracle's rule (sum of each reaction's largest factor)
+    from workloads import open_network, random_wide_network
+    nets = [open_network(n, c) for n, c in (("death", 20), ("birth", 1000),
+                                            ("lotka_volterra", 12))]
+    nets += [random_wide_network(s, S, n, R, o) for s, S, n, R, o in
+             ((0, 4, 8, 5, False), (1, 2, 10, 6, True), (2, 8, 6, 10, False),
+              (3, 5, 20, 8, True), (6, 6, 12, 16, True), (7, 2, 200, 7, False))]
+    for net in nets:
+        q_lib = bwg.Network(net).quantized()
+        q_orc = quantize(net)
+        assert q_lib["c"] == q_orc["c"] and q_lib["B"] == q_orc["B"]
+        assert q_lib["max_total"] == q_orc["max_total"] and q_lib["b"] == q_orc["b"]
+        assert q_lib["Lambda"] == q_orc["Lambda"] and q_lib["gpu_ok"]
+
+
+def test_wide_network_limits():
+    from workloads import open_network
+    big_jump = open_network("birth", 50)
+    big_jump["products"] = [(4,)]                 # A -> 4A: a change of 3
+    assert not bwg.Network(big_jump).quantized()["gpu_ok"]
+    lat = open_network("lotka_volterra", 12)
+    lat.update(lx=4, ly=4, site_planes=4)
+    with pytest.raises(bwg.BwgError) as e:
+        bwg.Network(lat)
+    assert e.value.code == _abi.BWG_EUNSUPPORTED

@@ -16,4 +16,4 @@ from .frank import (  # noqa: F401
     batch_networks,
     serve_requests,
 )
-from .general import random_network  # noqa: F401
+from .general import random_network, random_wide_network, open_network  # noqa: F401
