@@ -134,13 +134,16 @@ def main():
     ap.add_argument("--cpu-replicas", type=int, default=65536)
     ap.add_argument("--cpu-replicas-lattice", type=int, default=64)
     ap.add_argument("--workload", default="well-mixed",
-                    choices=["well-mixed", "lattice", "batch", "serve", "gain", "trajectory",
-                             "general"],
+                    choices=["well-mixed", "lattice", "batch", "serve", "gain", "gain-cpu",
+                             "trajectory", "general"],
                     help="lattice: 64x64 compartments, 2^16 replicas; batch: the 256 uneven "
                          "networks in one persistent launch; gain: the paper's Q(N) sweep")
     ap.add_argument("--gain-n", default="8,16,32,64,128,256,512,1024",
                     help="gain: molecule counts N_tot of the paper's network")
-    ap.add_argument("--gain-replicas", type=int, default=1 << 22)
+    ap.add_argument("--gain-replicas", default="4194304,64",
+                    help="gain: replica counts M, one table each (64: the paper's M)")
+    ap.add_argument("--gain-widths", default="16,32,64",
+                    help="gain: replicas per thread of the bit-parallel engine")
     ap.add_argument("--gain-steps", type=int, default=100000)
     ap.add_argument("--gain-repeats", type=int, default=3,
                     help="gain: timed steps of T per bit-parallel mode (median taken)")
@@ -172,6 +175,8 @@ def main():
         return
     if args.valu_ref:
         return valu_ref()
+    if args.workload == "gain-cpu":
+        return bench_gain_cpu(args)
     import paper_2412_16613_amd as bwg
     from workloads import config
     if args.workload == "batch":
@@ -639,60 +644,121 @@ def bench_gain(args):
     (1) the plain engine, one replica per thread with its own random number
     per step (the serial algorithm run M times), (2) the bit-parallel engine
     with a random threshold per replica, and (3) the bit-parallel engine with
-    one shared threshold on [0, Z) per step (the paper's variant).  Q is the
-    plain engine's time over the bit-parallel one's (median of the repeats;
-    each repeat continues the same replicas for another T steps)."""
+    one shared threshold on [0, Z) per step (the paper's variant), (2) and (3)
+    at every word width (16, 32 or 64 replicas per thread; the paper's words
+    are 64-bit).  Q is the plain engine's time over the bit-parallel one's
+    (median of the repeats; each repeat continues the same replicas for
+    another T steps).  One table per replica count M: 2^22 fills the GPU, 64
+    is the paper's own M (one or two words: a latency measurement)."""
     import torch
     import paper_2412_16613_amd as bwg
     from workloads import paper_network
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    M, T = args.gain_replicas, args.gain_steps
-    modes = (("plain", "plain", False), ("bitwise", "bitwise", False),
-             ("shared", "bitwise", True))
-    rows = []
-    for N in [int(x) for x in args.gain_n.split(",")]:
-        network = bwg.Network(paper_network(N))
-        q = network.quantized()
-        row = {"n_tot": N, "B": q["B"], "b": q["b"], "Z": q["z_shared"]}
-        for name, engine, shared in modes:
-            ens = bwg.Ensemble(network, M, seed=1, net_id=N, engine=engine, device=dev,
-                               shared_threshold=shared, time_kernels=True)
-            ens.init(("multinomial",))
-            ens.step(max(1, T // 100))                   # warm-up
-            torch.cuda.synchronize()
-            ens.kernel_time()
-            runs = []
-            # the plain engine's time varies by well under 1 % between runs
-            for _ in range(1 if engine == "plain" else args.gain_repeats):
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record()
-                ens.step(T)
-                b.record()
+    T = args.gain_steps
+    widths = [int(x) for x in args.gain_widths.split(",")]
+    modes = [("plain", "plain", False, 32)]
+    for wb in widths:
+        modes += [("bitwise_w%d" % wb, "bitwise", False, wb), ("shared_w%d" % wb, "bitwise", True, wb)]
+    tables = []
+    for M in [int(x) for x in str(args.gain_replicas).split(",")]:
+        rows = []
+        for N in [int(x) for x in args.gain_n.split(",")]:
+            network = bwg.Network(paper_network(N))
+            q = network.quantized()
+            row = {"n_tot": N, "B": q["B"], "b": q["b"], "Z": q["z_shared"]}
+            for name, engine, shared, wb in modes:
+                ens = bwg.Ensemble(network, M, seed=1, net_id=N, engine=engine, device=dev,
+                                   shared_threshold=shared, time_kernels=True,
+                                   word_bits=wb if engine == "bitwise" else 0)
+                ens.init(("multinomial",))
+                ens.step(max(1, T // 100))                   # warm-up
                 torch.cuda.synchronize()
-                runs.append(a.elapsed_time(b) / 1e3)
-            s = sorted(runs)[len(runs) // 2]
-            kt_ms, kt_n = ens.kernel_time()
-            row[name] = {"s": s, "runs_s": runs, "replica_steps_per_s": M * T / s,
-                         "kernel_ms": kt_ms / kt_n, "launches": kt_n}
-            del ens
-        for name in ("bitwise", "shared"):
-            row["Q_" + name] = row["plain"]["s"] / row[name]["s"]
-        rows.append(row)
-        print("gain N=%d: plain %.3f s, bitwise %.3f s, shared %.3f s, Q %.2f / %.2f"
-              % (N, row["plain"]["s"], row["bitwise"]["s"], row["shared"]["s"],
-                 row["Q_bitwise"], row["Q_shared"]), file=sys.stderr, flush=True)
-    last = rows[-1]
+                ens.kernel_time()
+                runs = []
+                # the plain engine's time varies by well under 1 % between runs
+                for _ in range(1 if engine == "plain" else args.gain_repeats):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    ens.step(T)
+                    b.record()
+                    torch.cuda.synchronize()
+                    runs.append(a.elapsed_time(b) / 1e3)
+                s = sorted(runs)[len(runs) // 2]
+                kt_ms, kt_n = ens.kernel_time()
+                row[name] = {"s": s, "runs_s": runs, "replica_steps_per_s": M * T / s,
+                             "kernel_ms": kt_ms / kt_n, "launches": kt_n}
+                del ens
+            for name, engine, _, _ in modes:
+                if engine == "bitwise":
+                    row["Q_" + name] = row["plain"]["s"] / row[name]["s"]
+            rows.append(row)
+            print("gain M=%d N=%d: plain %.4f s, " % (M, N, row["plain"]["s"]) +
+                  ", ".join("%s %.4f s (Q %.2f)" % (m[0], row[m[0]]["s"], row["Q_" + m[0]])
+                            for m in modes[1:]), file=sys.stderr, flush=True)
+        tables.append({"replicas": M, "rows": rows})
+    last = tables[0]["rows"][-1]
     out = {"metric": "gain Q = plain-SSA time / bit-parallel shared-threshold time "
                      "(same replicas and steps, 1 GPU)",
-           "value": last["Q_shared"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+           "value": last["Q_shared_w32"] if "Q_shared_w32" in last else None, "unit": "x",
+           "n_gpus": 1, "higher_is_better": True,
            "vs_baseline": None, "dtype": "u32 bit-planes", "data": "synthetic",
            "config": {"workload": "paper's Frank network with ghosts, multinomial start, "
-                                  "%d replicas, T=%d steps, N_tot in %s"
-                                  % (M, T, args.gain_n),
-                      "value_at_n_tot": last["n_tot"]},
-           "rows": rows}
+                                  "M in %s, T=%d steps, N_tot in %s, word widths %s"
+                                  % (args.gain_replicas, T, args.gain_n, args.gain_widths),
+                      "value_at": {"replicas": tables[0]["replicas"], "n_tot": last["n_tot"],
+                                   "word_bits": 32}},
+           "tables": tables}
+    print(json.dumps(out))
+
+
+def bench_gain_cpu(args):
+    """The paper's gain experiment as the paper ran it: on one host CPU core,
+    64-bit words, M = 64 copies (one word), T = 10^5 iterations, one shared
+    threshold per iteration, the paper's network with its ghosts; Q = time of
+    the direct method run once per copy over the time of the bit-parallel
+    method (cpu_gain/gain_cpu.c; both give the same counts, checked here)."""
+    import ctypes
+    from oracle import ssa
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2412_16613_amd", "libbwg_cpugain.so"))
+    P = ctypes.POINTER(ctypes.c_int32)
+    for f in (lib.bwg_cpu_gain_bitwise, lib.bwg_cpu_gain_serial):
+        f.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, P,
+                      ctypes.c_uint64, P]
+        f.restype = ctypes.c_int
+    M, T = 64, args.gain_steps
+    rows = []
+    for N in [int(x) for x in args.gain_n.split(",")]:
+        init = np.ascontiguousarray(ssa.init_multinomial(1, N, 0, M, N))
+        outs, times = [], []
+        for f in (lib.bwg_cpu_gain_serial, lib.bwg_cpu_gain_bitwise):
+            out = np.zeros((M, 3), dtype=np.int32)
+            best = None
+            for _ in range(3):
+                t = time.perf_counter()
+                rc = f(N, M, 1, N, init.ctypes.data_as(P), T, out.ctypes.data_as(P))
+                dt = time.perf_counter() - t
+                assert rc == 0
+                best = dt if best is None else min(best, dt)
+            outs.append(out)
+            times.append(best)
+        same = bool(np.array_equal(outs[0], outs[1]))
+        rows.append({"n_tot": N, "serial_s": times[0], "bitwise_s": times[1],
+                     "Q": times[0] / times[1], "same_counts": same})
+        print("cpu gain N=%d: serial %.3f s, bitwise %.3f s, Q %.1f" % (N, times[0], times[1],
+              times[0] / times[1]), file=sys.stderr, flush=True)
+        if not same:
+            print("the two CPU engines disagree", file=sys.stderr)
+            sys.exit(1)
+    out = {"metric": "gain Q = direct-method time / bit-parallel time (host CPU, 1 core, "
+                     "64-bit words, M = 64)",
+           "value": rows[0]["Q"], "unit": "x", "higher_is_better": True, "vs_baseline": None,
+           "dtype": "u64 bit-planes", "data": "synthetic",
+           "config": {"workload": "paper's Frank network with ghosts, multinomial start, "
+                                  "M=64, T=%d, shared threshold, N_tot in %s" % (T, args.gain_n),
+                      "value_at_n_tot": rows[0]["n_tot"]},
+           "cpu": cpu_model(), "rows": rows}
     print(json.dumps(out))
 
 

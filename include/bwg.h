@@ -205,7 +205,18 @@ typedef struct {
     uint64_t table_capacity;     /* Poisson-table entries, 0 = default 65536  */
     uint64_t events_per_launch;  /* 0 = whole advance in one launch           */
     uint64_t flags;              /* BWG_OPT_*                                 */
-    uint64_t reserved[3];
+    uint64_t word_bits;          /* replicas per thread of the bit-sliced
+                                    engine: 0 or 32 (a 32-bit word), 16 (half
+                                    a word) or 64 (two words); the draws are
+                                    keyed by the 32-lane word and the lane, so
+                                    results do not depend on it.  16 and 64
+                                    run the one-wave-per-thread form on
+                                    precompiled compile-time weights only (the
+                                    named workloads, the paper's network):
+                                    EUNSUPPORTED otherwise, EINVAL for other
+                                    values.  The paper's words are 64-bit
+                                    integers (Sec. 4, Sec. 5).               */
+    uint64_t reserved[2];
 } bwg_opts;
 
 typedef struct {

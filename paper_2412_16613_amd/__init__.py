@@ -120,7 +120,8 @@ class Ensemble:
 
     def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
                  device="cuda", events_per_launch=0, table_capacity=0, block=0,
-                 time_kernels=False, shared_threshold=False, generic=False, jit=True):
+                 time_kernels=False, shared_threshold=False, generic=False, jit=True,
+                 word_bits=0):
         import torch
         self.torch = torch
         L = _lib()
@@ -132,6 +133,7 @@ class Ensemble:
         o.block = block
         o.table_capacity = table_capacity
         o.events_per_launch = events_per_launch
+        o.word_bits = word_bits
         o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
                    (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0) |
                    (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0) |

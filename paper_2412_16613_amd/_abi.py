@@ -77,7 +77,8 @@ class LatticeInfo(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("table_capacity", ctypes.c_uint64), ("events_per_launch", ctypes.c_uint64),
-                ("flags", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 3)]
+                ("flags", ctypes.c_uint64), ("word_bits", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 2)]
 
 
 class Stats(ctypes.Structure):

@@ -69,7 +69,9 @@ struct PlainArgs {
 };
 
 // Launchers (defined in the .hip files).  Each returns a hipError_t.
-using WmLaunch = hipError_t (*)(const WmArgs &, hipStream_t, int block);
+// block: threads per block (0: default); word_bits: replicas per thread (32,
+// or 16 / 64 for the compile-time variants)
+using WmLaunch = hipError_t (*)(const WmArgs &, hipStream_t, int block, int word_bits);
 // Table of bit-sliced kernel instantiations: species planes NB, threshold
 // plane capacity BC, product shift FA and unimolecular weight CU (-1: taken
 // at run time).

@@ -570,6 +570,17 @@ extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_
     const bool generic = o && (o->flags & BWG_OPT_GENERIC_KERNEL);
     if (generic && (n->lat || engine != BWG_ENGINE_BITWISE))
         return fail(BWG_EUNSUPPORTED, "the general kernel is a well-mixed bit-sliced engine");
+    const uint64_t wb = o ? o->word_bits : 0;
+    if (wb != 0 && wb != 16 && wb != 32 && wb != 64)
+        return fail(BWG_EINVAL, "word_bits %llu: 16, 32 or 64", (unsigned long long)wb);
+    if (wb == 16 || wb == 64) {
+        const WmVariant *v = nullptr;
+        if (engine != BWG_ENGINE_BITWISE || n->lat || generic || !n->shape_ok ||
+            !(v = pick_variant(n)) || v->fa < 0 || v->cu < 0)
+            return fail(BWG_EUNSUPPORTED,
+                        "%llu-replica words run the precompiled compile-time Frank kernels only",
+                        (unsigned long long)wb);
+    }
     if (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) {
         if (n->lat || engine == BWG_ENGINE_PLAIN)
             return fail(BWG_EUNSUPPORTED,
@@ -627,6 +638,7 @@ int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint3
     e->table_cap = (o && o->table_capacity) ? o->table_capacity : 65536;
     e->epl = o ? o->events_per_launch : 0;
     e->timed = o && (o->flags & BWG_OPT_TIME_KERNELS);
+    e->word_bits = (o && o->word_bits) ? (int)o->word_bits : 32;
     e->zs = (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) ? (uint32_t)n->q.z_shared : 0;
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
@@ -855,7 +867,7 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
         else if (e->gvar)
             HIP_TRY(e->gvar->fn(a, n->gen, s));
         else
-            HIP_TRY(e->var->fn(a, s, e->block));
+            HIP_TRY(e->var->fn(a, s, e->block, e->word_bits));
         rc = mark_end(e, s, ev);
         if (rc) return rc;
     } else {

@@ -82,6 +82,7 @@ struct bwg_ens {
     uint64_t M = 0, seed = 0;
     uint32_t net_id = 0;
     int engine = 0, block = 0;
+    int word_bits = 32;   // replicas per thread of the bit-sliced engine
     uint64_t table_cap = 0, epl = 0;
     uint8_t *buf = nullptr;
     uint64_t bytes = 0;

@@ -384,6 +384,149 @@ __device__ __forceinline__ void wm_word(const WmArgs &a, const uint64_t w)
     store_word<NB>(a, w, live, hi, L, D, A);
 }
 
+// Word widths other than 32 replicas per thread (WW = 16 or 64); the
+// results are those of wm_word, since every draw is keyed by the 32-lane
+// word and the lane.  WW = 64: thread t runs the 32-replica words 2t and
+// 2t + 1 -- two states, one event loop over the union of their windows, each
+// word with its own threshold planes and active lanes, the two event bodies
+// in one basic block.  WW = 16: thread t runs the lanes 16 (t mod 2) .. +15
+// of word t / 2: it loads the whole word but only its half's lanes are
+// active (the other half's planes pass through unchanged), and it stores
+// the planes back as 16-bit halves and adds its real events atomically, so
+// the two threads of a word never write the same bytes.  The instructions
+// per event are those of a 32-replica word (a 16-bit bit-plane operation
+// issues at the 32-bit rate).
+template <int NB, int BC, int FA, int CU, bool SH, int FI, int NT, int BS, int WW>
+__device__ __forceinline__ void wm_word_w(const WmArgs &a, const uint64_t t)
+{
+    static_assert(WW == 16 || WW == 64, "16 or 64 replicas per thread");
+    static_assert(BC % 4 == 0, "threshold planes come in Philox quads");
+    using Sh = WmShape<NB, BC, FA, CU, FI, NT, BS>;
+    constexpr bool EXACT = Sh::EXACT;
+    constexpr int WP = Sh::WP, WD = Sh::WD, UW = Sh::UW, FMIN = Sh::FMIN;
+    constexpr int WD_AL = Sh::WD_AL, WD_QA = Sh::WD_QA, WD_LD = Sh::WD_LD;
+    constexpr int WPT = WW == 64 ? 2 : 1;
+    uint64_t wv[WPT];
+    uint32_t livev[WPT];
+    WordWindow win[WPT];
+    uint64_t lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+        wv[i] = WW == 64 ? 2 * t + i : t >> 1;
+        const bool valid = wv[i] < a.n_words;
+        uint32_t lv = valid ? live_lanes(a, wv[i]) : 0u;
+        if (WW == 16) lv &= (t & 1) ? 0xFFFF0000u : 0x0000FFFFu;
+        livev[i] = lv;
+        win[i] = word_window(a, a.E + 32 * (valid ? wv[i] : 0), a.Etgt + 32 * (valid ? wv[i] : 0),
+                             lv);
+        if (win[i].lo < win[i].hi) {
+            lo = win[i].lo < lo ? win[i].lo : lo;
+            hi = win[i].hi > hi ? win[i].hi : hi;
+        }
+    }
+    if (hi == 0) lo = 0;
+    if (wv[0] >= a.n_words) return;
+
+    uint32_t Ls[WPT][NB], Ds[WPT][NB], As[WPT][NB];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+        if (wv[i] < a.n_words) {
+            load_word<NB>(a, wv[i], Ls[i], Ds[i], As[i]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) Ls[i][q] = Ds[i][q] = As[i][q] = 0u;
+        }
+    }
+    uint64_t nrealv[WPT];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) nrealv[i] = 0;
+    if (lo < hi) {
+        uint32_t PALs[WPT][WP], PADs[WPT][WP], PLDs[WPT][WP], Us[WPT][UW];
+        const uint32_t cu = CU >= 0 ? (uint32_t)CU : a.cu;
+#pragma unroll
+        for (int i = 0; i < WPT; ++i)
+            init_weights<NB, UW, WP, EXACT>(Ls[i], Ds[i], As[i], cu, PALs[i], PADs[i], PLDs[i],
+                                            Us[i]);
+        const bool has_a = EXACT || a.fa >= 0, has_i = EXACT || a.fi >= 0;
+        const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+        const int nq = (a.B + 3) / 4;
+        uint32_t lastm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lastm[j] = (4 * (nq - 1) + j < a.B) ? ~0u : 0u;
+        uint32_t nv_next = SH ? shared_at(a, lo) : 0u;
+        uint64_t nxt[WPT];
+        uint32_t actc[WPT];
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+            nxt[i] = 0;
+            actc[i] = 0;
+        }
+        for (uint64_t e = lo; e < hi; ++e) {
+            uint32_t nsh[BC];
+            if constexpr (SH) {
+                const uint32_t nv = nv_next;
+                if (e + 1 < hi) nv_next = shared_at(a, e + 1);
+#pragma unroll
+                for (int q = 0; q < BC; ++q)
+                    nsh[q] = q < 32 ? (uint32_t)((int32_t)(nv << (31 - q)) >> 31) : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < WPT; ++i) {
+                const uint64_t *E = a.E + 32 * wv[i];
+                const uint64_t *T = a.Etgt + 32 * wv[i];
+                if (e >= nxt[i]) actc[i] = lane_mask_next(E, T, win[i].pend, e, win[i].blo, nxt[i]);
+                const uint32_t act = actc[i];
+                uint32_t n[BC];
+                if constexpr (SH) {
+#pragma unroll
+                    for (int q = 0; q < BC; ++q) n[q] = nsh[q];
+                } else {
+                    philox_planes<BC>(n, e, (uint32_t)wv[i], a.net_id, k0, k1, nq, lastm);
+                }
+                uint32_t(&L)[NB] = Ls[i];
+                uint32_t(&D)[NB] = Ds[i];
+                uint32_t(&A)[NB] = As[i];
+                uint32_t(&PAL)[WP] = PALs[i];
+                uint32_t(&PAD)[WP] = PADs[i];
+                uint32_t(&PLD)[WP] = PLDs[i];
+                uint32_t(&U)[UW] = Us[i];
+                uint64_t &nreal = nrealv[i];
+#include "wm_event_body.inc"
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+        const uint64_t w = wv[i];
+        if (w >= a.n_words) continue;
+        if (WW == 16) {
+            // this thread's half of every plane, and its lanes' event counts
+            uint16_t *ph = reinterpret_cast<uint16_t *>(a.planes);
+            const int nbm = a.nb_mem;
+            const int sh = (t & 1) ? 16 : 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q < nbm) {
+                    ph[(((uint64_t)0 * nbm + q) * a.wp + w) * 2 + (t & 1)] = (uint16_t)(Ls[i][q] >> sh);
+                    ph[(((uint64_t)1 * nbm + q) * a.wp + w) * 2 + (t & 1)] = (uint16_t)(Ds[i][q] >> sh);
+                    ph[(((uint64_t)2 * nbm + q) * a.wp + w) * 2 + (t & 1)] = (uint16_t)(As[i][q] >> sh);
+                }
+            }
+            uint64_t *Ew = a.E + 32 * w;
+            const uint64_t *T = a.Etgt + 32 * w;
+            for (int l = 0; l < 32; ++l) {
+                if (!((livev[i] >> l) & 1u)) continue;
+                const uint64_t x = Ew[l], y = T[l];
+                Ew[l] = hi < x ? x : (hi > y ? y : hi);
+            }
+            if (nrealv[i]) atomicAdd((unsigned long long *)&a.real[w], (unsigned long long)nrealv[i]);
+        } else {
+            if (win[i].lo < win[i].hi) a.real[w] += nrealv[i];
+            store_word<NB>(a, w, livev[i], hi, Ls[i], Ds[i], As[i]);
+        }
+    }
+}
+
 // 64-bit maximum over the 64 lanes of a wave.
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
 {

@@ -55,9 +55,40 @@ __global__ __launch_bounds__(256) void wm_pc_kernel(WmArgs a)
     wm_word_pc<NB, BC, FA, CU, PH, FA, NT, BS>(a, ring, wave_span);
 }
 
-template <int NB, int BC, int FA, int CU, int NT, int BS>
-hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
+// Other word widths (16 or 64 replicas per thread), one wave per 64 threads.
+template <int NB, int BC, int FA, int CU, bool SH, int NT, int BS, int WW>
+__global__ __launch_bounds__(256) void wm_event_w_kernel(WmArgs a)
 {
+    wm_word_w<NB, BC, FA, CU, SH, FA, NT, BS, WW>(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+template <int NB, int BC, int FA, int CU, int NT, int BS, int WW>
+hipError_t launch_wm_w(const WmArgs &a, hipStream_t s, int block)
+{
+    const uint64_t threads = WW == 64 ? (a.n_words + 1) / 2 : 2 * a.n_words;
+    if (block <= 0) block = threads >= 65536 ? 256 : 128;
+    const uint64_t grid = (threads + block - 1) / block;
+    if (a.zs)
+        hipLaunchKernelGGL((wm_event_w_kernel<NB, BC, FA, CU, true, NT, BS, WW>),
+                           dim3((uint32_t)grid), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((wm_event_w_kernel<NB, BC, FA, CU, false, NT, BS, WW>),
+                           dim3((uint32_t)grid), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NB, int BC, int FA, int CU, int NT, int BS>
+hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block, int word_bits)
+{
+    if (word_bits == 16 || word_bits == 64) {
+        // compile-time weights only (the host checks before any launch)
+        if constexpr (FA >= 0 && CU >= 0) {
+            return word_bits == 16 ? launch_wm_w<NB, BC, FA, CU, NT, BS, 16>(a, s, block)
+                                   : launch_wm_w<NB, BC, FA, CU, NT, BS, 64>(a, s, block);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     // with at most one wave of 64 words per SIMD pair half the chip would
     // idle: split each word's events over a producer and a consumer wave
     if (block <= 0 && !a.zs && a.n_words <= 32768) {
@@ -84,7 +115,8 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
 // (NB, BC, FA, CU, NT, BS): FA/CU = -1 are taken at run time; NT > 0 fixes
 // the molecule count and BS the selection planes (exact register widths,
 // see WmShape), NT = 0 serves any count within the planes.
-#define BWG_WM_VARIANTS(X)                                                    \
+#define BWG_WM_VARIANTS(X) BWG_WM_VARIANTS_CT(X) BWG_WM_VARIANTS_RT(X)
+#define BWG_WM_VARIANTS_CT(X)                                                 \
     /* the named workloads, exact widths */                                   \
     X(6, 20, 9, 164, 32, 18)     /* N_tot = 32, k0 = 0.01, k1 = k2 = 1/32 */  \
     X(11, 24, 4, 164, 1024, 23)  /* N_tot = 1024 */                           \
@@ -96,7 +128,8 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block)
     X(8, 16, 0, 0, 0, 16)    /* N_tot <= 255 */                               \
     X(9, 16, 0, 0, 0, 16)    /* N_tot <= 362 */                               \
     X(10, 20, 0, 0, 0, 20)   /* N_tot <= 1023 */                              \
-    X(11, 20, 0, 0, 0, 20)   /* N_tot <= 1448 */                              \
+    X(11, 20, 0, 0, 0, 20)   /* N_tot <= 1448 */
+#define BWG_WM_VARIANTS_RT(X)                                                 \
     /* run-time shifts and weights, any Frank-family network in budget */     \
     X(4, 20, -1, -1, 0, 20)                                                   \
     X(6, 20, -1, -1, 0, 20)                                                   \
@@ -142,6 +175,14 @@ hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
     template __global__ void wm_event_kernel<nb, bc, fa, cu, true, nt, bs>(WmArgs);  \
     template __global__ void wm_pc_kernel<nb, bc, fa, cu, nt, bs>(WmArgs);
 BWG_WM_VARIANTS(BWG_WM_INST)
+
+// 16 and 64 replicas per thread for the compile-time variants
+#define BWG_WM_INST_W(nb, bc, fa, cu, nt, bs)                                         \
+    template __global__ void wm_event_w_kernel<nb, bc, fa, cu, false, nt, bs, 16>(WmArgs); \
+    template __global__ void wm_event_w_kernel<nb, bc, fa, cu, true, nt, bs, 16>(WmArgs);  \
+    template __global__ void wm_event_w_kernel<nb, bc, fa, cu, false, nt, bs, 64>(WmArgs); \
+    template __global__ void wm_event_w_kernel<nb, bc, fa, cu, true, nt, bs, 64>(WmArgs);
+BWG_WM_VARIANTS_CT(BWG_WM_INST_W)
 
 #ifndef __HIP_DEVICE_COMPILE__
 #define BWG_WM_ENTRY(nb, bc, fa, cu, nt, bs) {nb, bc, fa, cu, nt, bs, &launch_wm<nb, bc, fa, cu, nt, bs>},
