@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64, 2) void wm_persistent_kernel(const BatchEns *en
                                                               uint32_t *counter,
                                                               uint64_t max_events)
 {
-    __shared__ uint32_t sq[2][32];
+    __shared__ __align__(16) uint32_t sq[2][kLanesHalfWords];
     for (;;) {
         uint32_t it = 0;
         if (threadIdx.x == 0) it = atomicAdd(counter, 1u);

@@ -167,9 +167,10 @@ static int set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, hipStream_t
         b->bucket.push_back(bk);
         const PersistVariant &v = kPersistVariants[bk];
         // per-event issue cost of one item (orders the queue only): a lanes
-        // item makes one Philox call and unpacks B planes per event
+        // item's event takes ~50 instructions plus its share of the draws and
+        // the transposition of 32 events' planes
         b->cost.push_back(100.0 * ((nt->q.B + 3) / 4) + 8.0 * v.bc + 40.0 * v.nb);
-        b->lane_cost.push_back(140.0 + 3.0 * nt->q.B);
+        b->lane_cost.push_back(60.0 + 1.5 * nt->q.B);
         BatchEns &d = b->h_ens[k];
         memset(&d, 0, sizeof d);
         WmArgs &a = d.a;

@@ -548,6 +548,11 @@ static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
         if (!*v)
             return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for b=%d B=%d fa=%d fi=%d",
                         n->q.b, n->q.B, n->shape.fa, n->shape.fi);
+        // the lanes engine compares in 32-bit arithmetic: every cumulative
+        // weight must stay below 2^32 (it does whenever a bucket holds the
+        // planes; checked here for the record)
+        if (engine == BWG_ENGINE_LANES && (n->q.B > 32 || n->q.max_total >= (1ll << 32)))
+            return fail(BWG_EUNSUPPORTED, "lanes engine needs total weights below 2^32");
         return BWG_OK;
     }
     if (engine == BWG_ENGINE_PLAIN) {
@@ -700,8 +705,13 @@ extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)
     if (e->lat) return fail(BWG_EINVAL, "lattices have one engine");
     if (e->engine == BWG_ENGINE_PLAIN || (engine != BWG_ENGINE_BITWISE && engine != BWG_ENGINE_LANES))
         return fail(BWG_EINVAL, "only the bit-sliced and lanes engines share a state layout");
-    if (engine == BWG_ENGINE_LANES && e->gvar)
+    if (engine == BWG_ENGINE_LANES && (e->gvar || e->jit))
         return fail(BWG_EINVAL, "the lanes engine runs Frank-family networks on their own kernel");
+    if (engine == BWG_ENGINE_LANES) {
+        const WmVariant *v = nullptr;
+        const int rc = check_engine(e->net, BWG_ENGINE_LANES, &v);
+        if (rc) return rc;
+    }
     if (engine == BWG_ENGINE_BITWISE && !e->var && !e->gvar) {
         e->var = pick_variant(e->net);
         if (!e->var) return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for this network");

@@ -669,14 +669,45 @@ namespace bwg {
 // One word of an ensemble with one replica per thread ("lanes" engine): the
 // 32 threads of one half of a wave hold the word's 32 replicas as int32
 // counts, unpacked from the bit planes at the start and packed back at the
-// end.  Every event draws the same EVENT planes as wm_word (thread q < 8 of
-// the half makes the Philox call of plane-quad q and shares it through sq,
-// this half's LDS), and each thread compares its own threshold with the
-// cumulative weights in integer arithmetic; the result is bit for bit the
-// one wm_word gives.  The work per event is a few hundred instructions for
-// 32 replicas instead of about 1200 for the bit-sliced word, so a word's
-// chain of events finishes several times sooner at a higher cost per
+// end.  Every event uses the same EVENT planes as wm_word, and each thread
+// compares its own threshold with the cumulative weights in integer
+// arithmetic, so the result is bit for bit the one wm_word gives.
+//
+// The planes are drawn for runs of 32 events: thread t makes the nq =
+// ceil(B / 4) Philox calls of event e0 + t, transposes the 32 x 32 bit matrix
+// of its event's planes in registers (plane q's bit l becomes bit q of row l:
+// replica l's threshold) and stores the 32 thresholds in sq, this half's LDS
+// (event g's row at [36 g, 36 g + 32); the stride of 36 words spreads the
+// rows' stores over the banks).  Each event then costs a thread one LDS read
+// and the comparisons in 32-bit arithmetic (every cumulative weight is below
+// 2^32: the threshold planes are at most 32 and the largest total weight is
+// below 2^B, or B < 32): about 60 instructions for 32 replicas per event,
+// against about 750 for the bit-sliced word, so a word's chain of events
+// finishes an order of magnitude sooner at about twice the work per
 // replica-event: the choice for long chains on few replicas.
+constexpr int kLanesRow = 36;                 // words per event row in sq
+constexpr int kLanesHalfWords = 32 * kLanesRow;  // sq words per half wave
+
+// In-register transpose of a 32 x 32 bit matrix: afterwards bit q of x[l] is
+// bit l of the original x[q].  Five levels of block swaps (j = 16, 8, 4, 2,
+// 1): the bits of row k at columns with bit j set trade places with those of
+// row k + j at columns with bit j clear.
+__device__ __forceinline__ void transpose32(uint32_t (&x)[32])
+{
+    constexpr uint32_t M[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+    for (int lv = 0; lv < 5; ++lv) {
+        const int j = 16 >> lv;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (k & j) continue;
+            const uint32_t t = ((x[k] >> j) ^ x[k + j]) & M[lv];
+            x[k + j] ^= t;
+            x[k] ^= t << j;
+        }
+    }
+}
+
 __device__ __forceinline__ void wm_lanes(const WmArgs &a, const uint64_t w, uint32_t *sq)
 {
     if (w >= a.n_words) return;
@@ -706,75 +737,74 @@ __device__ __forceinline__ void wm_lanes(const WmArgs &a, const uint64_t w, uint
         cD |= (int32_t)((a.planes[((uint64_t)1 * nbm + q) * a.wp + w] >> l) & 1u) << q;
         cA |= (int32_t)((a.planes[((uint64_t)2 * nbm + q) * a.wp + w] >> l) & 1u) << q;
     }
-    const int B = a.B;
-    const int nq = (B + 3) / 4;
+    const int B = a.B;  // at most 32 (the host's plane buckets)
     const uint64_t cu = a.cu;
     const bool has_a = a.fa >= 0, has_i = a.fi >= 0;
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const uint32_t zs = a.zs;
     uint32_t nreal = 0;
-    for (uint64_t e = lo; e < hi; ++e) {
-        if (zs) {
-            // shared threshold: the same n for every thread
-            const uint64_t n = shared_at(a, e);
-            const bool act = mine && E0 <= e && e < T0;
-            if (act) {
-                const uint64_t U = cu * (uint64_t)cA;
-                const uint64_t S2 = 2 * U;
-                const uint64_t S3 = S2 + (has_a ? ((uint64_t)cA * (uint64_t)cL) << a.fa : 0);
-                const uint64_t S4 = S3 + (has_a ? ((uint64_t)cA * (uint64_t)cD) << a.fa : 0);
-                const uint64_t S5 = S4 + (has_i ? ((uint64_t)cL * (uint64_t)cD) << a.fi : 0);
-                const int r = n < U ? 0 : n < S2 ? 1 : n < S3 ? 2 : n < S4 ? 3 : n < S5 ? 4 : -1;
-                cL += (r == 0 || r == 2) - (r == 4);
-                cD += (r == 1 || r == 3) - (r == 4);
-                cA += (r == 4) * 2 - (r >= 0 && r < 4);
-                nreal += r >= 0;
+    // the reaction whose cumulative weight first exceeds n: with b_r = [n <
+    // S_r] (monotone in r, S_1 = U, S_2 = 2U, ...), reaction r fires where
+    // b_r and not b_(r-1); the count changes below are those of the five
+    // reactions (A -> L, A -> D, A + L -> 2L, A + D -> 2D, L + D -> 2A)
+    // summed over these indicators
+    const uint32_t cu32 = (uint32_t)cu;
+    const uint32_t amask = has_a ? ~0u : 0u, imask = has_i ? ~0u : 0u;
+    const int fa = has_a ? a.fa : 0, fi = has_i ? a.fi : 0;
+    auto apply = [&](uint32_t n, bool act) {
+        const uint32_t A = (uint32_t)cA, L = (uint32_t)cL, D = (uint32_t)cD;
+        const uint32_t U = cu32 * A;
+        const uint32_t S2 = 2 * U;
+        const uint32_t S3 = S2 + (((uint32_t)__umul24(A, L) & amask) << fa);
+        const uint32_t S4 = S3 + (((uint32_t)__umul24(A, D) & amask) << fa);
+        const uint32_t S5 = S4 + (((uint32_t)__umul24(L, D) & imask) << fi);
+        const int32_t b0 = act && n < U, b1 = act && n < S2, b2 = act && n < S3;
+        const int32_t b3 = act && n < S4, b4 = act && n < S5;
+        cL += b0 - b1 + b2 + b3 - b4;
+        cD += b1 - b0 - b2 + 2 * b3 - b4;
+        cA += 2 * b4 - 3 * b3;
+        nreal += (uint32_t)b4;
+    };
+    if (a.zs) {
+        // shared threshold: the same n for every thread
+        for (uint64_t e = lo; e < hi; ++e)
+            apply(shared_at(a, e), mine && E0 <= e && e < T0);
+    } else {
+        const int nq = (B + 3) / 4;
+        const uint32_t bmask = B >= 32 ? ~0u : ((1u << B) - 1u);
+        for (uint64_t e0 = lo; e0 < hi; e0 += 32) {
+            const uint64_t ed = e0 + (uint64_t)l;
+            if (ed < hi) {
+                uint32_t x[32];
+#pragma unroll
+                for (int q4 = 0; q4 < 8; ++q4) {
+                    uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+                    if (q4 < nq)
+                        philox4x32_10((uint32_t)ed,
+                                      (DOM_EVENT << 24) | ((uint32_t)q4 << 16) |
+                                          ((uint32_t)(ed >> 32) & 0xFFFFu),
+                                      (uint32_t)w, a.net_id, k0, k1, o0, o1, o2, o3);
+                    x[4 * q4] = o0;
+                    x[4 * q4 + 1] = o1;
+                    x[4 * q4 + 2] = o2;
+                    x[4 * q4 + 3] = o3;
+                }
+                transpose32(x);
+                uint4 *row = reinterpret_cast<uint4 *>(sq + kLanesRow * l);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    row[c] = make_uint4(x[4 * c] & bmask, x[4 * c + 1] & bmask,
+                                        x[4 * c + 2] & bmask, x[4 * c + 3] & bmask);
             }
-            continue;
-        }
-        if (l < nq) {
-            uint32_t o0, o1, o2, o3;
-            philox4x32_10((uint32_t)e,
-                          (DOM_EVENT << 24) | ((uint32_t)l << 16) | ((uint32_t)(e >> 32) & 0xFFFFu),
-                          (uint32_t)w, a.net_id, k0, k1, o0, o1, o2, o3);
-            sq[4 * l + 0] = o0;
-            sq[4 * l + 1] = o1;
-            sq[4 * l + 2] = o2;
-            sq[4 * l + 3] = o3;
-        }
-        __builtin_amdgcn_wave_barrier();
-        uint64_t n = 0;
-        for (int q = 0; q < B; ++q) n |= (uint64_t)((sq[q] >> l) & 1u) << q;
-        __builtin_amdgcn_wave_barrier();
-        const bool act = mine && E0 <= e && e < T0;
-        if (act) {
-            const uint64_t U = cu * (uint64_t)cA;
-            const uint64_t S2 = 2 * U;
-            const uint64_t S3 = S2 + (has_a ? ((uint64_t)cA * (uint64_t)cL) << a.fa : 0);
-            const uint64_t S4 = S3 + (has_a ? ((uint64_t)cA * (uint64_t)cD) << a.fa : 0);
-            const uint64_t S5 = S4 + (has_i ? ((uint64_t)cL * (uint64_t)cD) << a.fi : 0);
-            if (n < U) {
-                cL += 1;
-                cA -= 1;
-                ++nreal;
-            } else if (n < S2) {
-                cD += 1;
-                cA -= 1;
-                ++nreal;
-            } else if (n < S3) {
-                cL += 1;
-                cA -= 1;
-                ++nreal;
-            } else if (n < S4) {
-                cD += 1;
-                cA -= 1;
-                ++nreal;
-            } else if (n < S5) {
-                cL -= 1;
-                cD -= 1;
-                cA += 2;
-                ++nreal;
+            // the half's LDS operations run in program order: the reads below
+            // see every lane's stores, and the next run's stores follow them
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t left = hi - e0;
+            const int gn = left < 32 ? (int)left : 32;
+            for (int g = 0; g < gn; ++g) {
+                const uint64_t e = e0 + (uint64_t)g;
+                apply(sq[kLanesRow * g + l], mine && E0 <= e && e < T0);
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     // pack the counts back into the planes of the word (lane 0 of the half stores)

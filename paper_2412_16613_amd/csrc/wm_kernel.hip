@@ -141,7 +141,7 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block, int word_bits)
 // Lanes engine: 8 words per 256-thread block, one replica per thread.
 __global__ __launch_bounds__(256) void wm_lanes_kernel(WmArgs a)
 {
-    __shared__ uint32_t sq[8][32];
+    __shared__ __align__(16) uint32_t sq[8][kLanesHalfWords];
     const int half = threadIdx.x >> 5;
     wm_lanes(a, 8 * (uint64_t)blockIdx.x + half, sq[half]);
 }

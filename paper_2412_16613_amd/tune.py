@@ -13,12 +13,15 @@ timing runs use scratch ensembles, and the tuned batch gives bit for bit
 what any other configuration gives.
 
 Why lanes: a batch finishes when its longest word chain does.  A bit-sliced
-word runs its replicas' events one after another at ~1200 VALU slots per
-event, while a lanes item runs the same events at a few hundred per event
-(for 64 replicas), at about five times the work per replica-event.  The
-candidates move the k longest chains (events per replica x cost per event)
-to lanes, k = 0, 1, 2, 3, 4, 6, 8, 12; each is timed on a tenth of the
-horizons (both the longest chain and the total work scale with it).
+word runs its 32 replicas' events one after another at ~750-1200 wave
+instructions per event (one lane per word), while a lanes item draws the
+thresholds of 32 events at once, transposes them in registers and then runs
+each event in ~50 instructions for 64 replicas (one replica per lane): about
+twice the work per replica-event of the bit-sliced word on compile-time
+weights, but chains an order of magnitude shorter.  The candidates move the k
+longest chains (events per replica x cost per event) to lanes, k from 0 to
+every member; each is timed on a tenth of the horizons (both the longest
+chain and the total work scale with it).
 """
 
 import hashlib
@@ -31,7 +34,7 @@ CACHE = os.environ.get("BWG_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                     "tune_cache.json"))
 GRIDS = [(w, o) for w in (1024, 2048, 3072, 4096) for o in (0,)] + [(2048, 1)]
-TOP_K = [0, 1, 2, 3, 4, 6, 8, 12]
+TOP_K = [0, 2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256]
 
 
 def signature(items):
@@ -102,8 +105,10 @@ def tune(items, horizon_scale=0.1, device="cuda", force=False):
     _time(bwg, torch, items, nets, 2048, 0, set(), horizon_scale, device)   # warm caches
     for k in TOP_K:
         if k > len(items):
-            break
+            k = len(items)
         lanes = sorted(by_chain[:k])
+        if "lanes=%d/2048/0" % k in timings:
+            break
         dt = _time(bwg, torch, items, nets, 2048, 0, set(lanes), horizon_scale, device)
         timings["lanes=%d/2048/0" % k] = dt
         if best is None or dt < best[0]:
