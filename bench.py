@@ -13,6 +13,7 @@ a bounded sample.
 
 import argparse
 import json
+import math
 
 import numpy as np
 import os
@@ -78,8 +79,8 @@ MEASURED_TRAFFIC = {
     "wm_pc_kernel": ("74d32918df9c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
                      int((2 * 10822.625 + 12672) * 1024), "profiles/wm_pc_kernel_frank1024_2p20.md"),
-    "lat_event_kernel": ("1233d02af292", ("bitops.h", "lattice.hip"),
-                         (2 * 3994154 + 8337447) * 1024,
+    "lat_event_kernel": ("96ce50d96af1", ("bitops.h", "lattice.hip"),
+                         (2 * 3004255 + 6513929) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
 }
 
@@ -151,6 +152,11 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: arrival window (s)")
     ap.add_argument("--chunk", type=int, default=4096, help="serve: events per word per pass")
+    ap.add_argument("--no-lds-stage", action="store_true",
+                    help="lattice: the event kernel that keeps every site in memory")
+    ap.add_argument("--lanes-events", type=float, default=1e5,
+                    help="serve: requests expecting at least this many events per replica run "
+                         "on the lanes engine (0: none)")
     ap.add_argument("--compare-nets", type=int, default=32,
                     help="networks for the one-network-per-launch comparison")
     ap.add_argument("--copy-ref", action="store_true",
@@ -385,7 +391,7 @@ def bench_lattice(args):
     network = bwg.Network(net)
     q, li = network.quantized(), network.lattice()
     ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], device=dev,
-                       time_kernels=True)
+                       time_kernels=True, lds_stage=not args.no_lds_stage)
     counts = torch.empty((M, 3), dtype=torch.int32, device=dev)
     hist = torch.empty(256, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -424,16 +430,29 @@ def bench_lattice(args):
     launch_ms = kt_ms / kt_n
     word_events = events / 32.0 / launches_per_step          # per launch
     achieved = slots * word_events / (launch_ms / 1e3)
-    # algorithmic HBM bytes: a reaction reads and writes the 3 x P planes of
-    # its site (one 32-bit word each), a hop those of both sites
+    # site-plane bytes: a reaction reads and writes the 3 x P planes of its
+    # site (one 32-bit word each), a hop those of both sites.  The event
+    # kernel keeps the first BWG_LAT_STAGE_SITES sites of every word in LDS
+    # for a pass of 16 chunks: its algorithmic HBM bytes are one copy of
+    # those sites in and out per word and pass, and the site-plane bytes of
+    # the events on the other sites
+    from paper_2412_16613_amd import _abi
     site_bytes = 3 * li["P"] * 4
-    bytes_we = f_r * 2 * site_bytes + (1 - f_r) * 2 * 2 * site_bytes
-    hbm = bytes_we * word_events / (launch_ms / 1e3)
+    plane_bytes_we = f_r * 2 * site_bytes + (1 - f_r) * 2 * 2 * site_bytes
+    words = (M + 31) // 32
+    n_stage = (min(li["sites"], _abi.BWG_LAT_STAGE_SITES)
+               if words >= 512 and not args.no_lds_stage else 0)
+    passes = math.ceil(events / M / (16 * 8192))
+    stage_bytes = passes * words * 2 * n_stage * site_bytes / launches_per_step
+    hbm_bytes = stage_bytes + (1 - n_stage / li["sites"]) * plane_bytes_we * word_events
+    bytes_we = hbm_bytes / word_events
+    hbm = hbm_bytes / (launch_ms / 1e3)
     alu_side = {"achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                 "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK,
                 "slots_per_word_event": slots, "slots_reaction": react, "slots_hop": hop}
     hbm_side = {"achieved": hbm / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": hbm / HBM_PEAK, "bytes_per_word_event": bytes_we}
+                "frac": hbm / HBM_PEAK, "bytes_per_word_event": bytes_we,
+                "site_plane_bytes_per_word_event": plane_bytes_we, "sites_in_lds": n_stage}
     bind = hbm_side if hbm_side["frac"] >= alu_side["frac"] else alu_side
     out = {
         "metric": "replica-events/sec (bit-parallel lattice, 1 GPU)",
@@ -444,7 +463,7 @@ def bench_lattice(args):
                                "average (A uniform 9..15), d=0.1, 2^16 replicas, t_end=20, "
                                "seed 0",
                    "sites": li["sites"], "replicas": M, "t_end": t_end, "site_planes": li["P"],
-                   "reaction_planes": li["B_r"]},
+                   "reaction_planes": li["B_r"], "sites_in_lds_per_word": n_stage},
         "real_events_per_s": st["real_total"] * args.steps / (ms / 1e3),
         "roofline": {"bound": "hbm" if bind is hbm_side else "alu",
                      "achieved": bind["achieved"], "peak": bind["peak"], "unit": bind["unit"],
@@ -619,7 +638,7 @@ def bench_serve(args):
     from workloads import serve_requests
     reqs = serve_requests(rate=args.rate, duration=args.duration)
     n_lat = sum(1 for r in reqs if r["net"].get("lx"))
-    srv = Server(chunk=args.chunk)
+    srv = Server(chunk=args.chunk, lanes_events=args.lanes_events)
     res = srv.serve(reqs, real_time=True,
                     progress=lambda m: print("serve " + m, file=sys.stderr, flush=True))
     s = summarize(res, srv.stats)
@@ -629,7 +648,8 @@ def bench_serve(args):
            "config": {"workload": "Poisson arrivals %.0f/s for %.0f s, 30%% lattice variants"
                                   % (args.rate, args.duration),
                       "requests": len(reqs), "lattice_requests": n_lat,
-                      "chunk_events": args.chunk, "lattice_chunk_events": srv.lattice_chunk},
+                      "chunk_events": args.chunk, "lattice_chunk_events": srv.lattice_chunk,
+                      "lanes_events": args.lanes_events},
            "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
            "summary": s}
     print(json.dumps(out))

@@ -196,6 +196,15 @@ typedef struct {
  * precompiled run-time weight kernels.  This flag keeps the precompiled
  * kernels instead. */
 #define BWG_OPT_NO_JIT 8u
+/* Lattices: run the event kernel that keeps every site's planes in memory.
+ * By default ensembles of 512 words (16384 replicas) and more, on a lattice
+ * with 4 planes per species and the weights of the precompiled lattice kernel,
+ * run the kernel that keeps the planes of the first BWG_LAT_STAGE_SITES sites
+ * of each word in LDS for the whole launch (copied in at the start and back at
+ * the end); the results are the same either way.  Ignored for well-mixed
+ * networks. */
+#define BWG_OPT_NO_LDS_STAGE 16u
+#define BWG_LAT_STAGE_SITES 840
 
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */

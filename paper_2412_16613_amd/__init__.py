@@ -121,7 +121,7 @@ class Ensemble:
     def __init__(self, network, n_replicas, seed=0, net_id=0, engine="bitwise",
                  device="cuda", events_per_launch=0, table_capacity=0, block=0,
                  time_kernels=False, shared_threshold=False, generic=False, jit=True,
-                 word_bits=0):
+                 word_bits=0, lds_stage=True):
         import torch
         self.torch = torch
         L = _lib()
@@ -137,7 +137,8 @@ class Ensemble:
         o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
                    (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0) |
                    (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0) |
-                   (0 if jit else _abi.BWG_OPT_NO_JIT))
+                   (0 if jit else _abi.BWG_OPT_NO_JIT) |
+                   (0 if lds_stage else _abi.BWG_OPT_NO_LDS_STAGE))
         self._opts = o
         nbytes = ctypes.c_uint64()
         _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),

@@ -30,6 +30,8 @@ BWG_OPT_TIME_KERNELS = 1
 BWG_OPT_SHARED_THRESHOLD = 2
 BWG_OPT_GENERIC_KERNEL = 4
 BWG_OPT_NO_JIT = 8
+BWG_OPT_NO_LDS_STAGE = 16
+BWG_LAT_STAGE_SITES = 840
 
 # Every symbol include/bwg.h declares.
 SYMBOLS = (

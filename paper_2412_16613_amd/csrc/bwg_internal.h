@@ -204,6 +204,7 @@ struct LatVariant {
     int P, bc;
     int64_t cu, ca, ci;
     int ws, block;
+    int stage;  // sites whose planes the launch keeps in LDS (0: none)
     LatLaunch fn;
 };
 extern const LatVariant kLatVariants[];

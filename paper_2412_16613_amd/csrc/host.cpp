@@ -643,6 +643,7 @@ int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint3
     e->table_cap = (o && o->table_capacity) ? o->table_capacity : 65536;
     e->epl = o ? o->events_per_launch : 0;
     e->timed = o && (o->flags & BWG_OPT_TIME_KERNELS);
+    e->lat_stage = !(o && (o->flags & BWG_OPT_NO_LDS_STAGE));
     e->word_bits = (o && o->word_bits) ? (int)o->word_bits : 32;
     e->zs = (o && (o->flags & BWG_OPT_SHARED_THRESHOLD)) ? (uint32_t)n->q.z_shared : 0;
     e->buf = (uint8_t *)dev_buf;

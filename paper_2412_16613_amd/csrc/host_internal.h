@@ -118,6 +118,7 @@ struct bwg_ens {
     uint64_t base = 0, n_chunks = 0, cursor = 0;  // chunk window of the advance
     // event-kernel timing (BWG_OPT_TIME_KERNELS)
     bool timed = false;
+    bool lat_stage = true;                      // lattices: LDS-staged event kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;  // recorded, not yet read
     std::vector<hipEvent_t> spare;
     ~bwg_ens()

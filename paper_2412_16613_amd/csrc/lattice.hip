@@ -20,6 +20,7 @@
 // order that only permutes commuting events.
 
 #include "bitops.h"
+#include "bwg.h"
 #include "bwg_internal.h"
 
 namespace bwg {
@@ -472,10 +473,11 @@ __device__ __forceinline__ void event_planes(uint32_t (&n)[BC], uint64_t seed, u
     }
 }
 
-// Reaction component of site p (planes l, d, x already loaded) for the
-// lanes in act; returns the lanes whose state changed.
+// Reaction component of a site (planes l, d, x already loaded, updated in
+// place) for the lanes in act; returns the lanes whose state changed (the
+// caller stores the planes if any did).
 template <int P, int BC, int64_t CU, int64_t CA, int64_t CI>
-__device__ __forceinline__ uint32_t lat_reaction(uint32_t *p, uint32_t (&l)[P], uint32_t (&d)[P],
+__device__ __forceinline__ uint32_t lat_reaction(uint32_t (&l)[P], uint32_t (&d)[P],
                                                  uint32_t (&x)[P], const LatArgs &a, uint32_t G,
                                                  uint64_t e, uint32_t act)
 {
@@ -515,17 +517,17 @@ __device__ __forceinline__ uint32_t lat_reaction(uint32_t *p, uint32_t (&l)[P], 
         add_pm1<P>(l, mL, mI);
         add_pm1<P>(d, mD, mI);
         add_m1_p2<P>(x, mL | mD, mI);
-        store_site<P>(p, l, d, x);
     }
     return ch;
 }
 
-// Hop component out of site p into site p2 (planes already loaded; p2 == p:
-// the lattice is one site wide along that axis and the hop changes
-// nothing).  Sets the lanes that moved and the lanes blocked by a full
+// Hop component out of one site into another (planes already loaded,
+// updated in place; self: the lattice is one site wide along that axis and
+// the hop changes nothing).  Sets the lanes that moved (the caller stores
+// both sites' planes if any did) and the lanes blocked by a full
 // destination.
 template <int P>
-__device__ __forceinline__ void lat_hop(uint32_t *p, uint32_t *p2, bool self, uint32_t (&l)[P],
+__device__ __forceinline__ void lat_hop(bool self, uint32_t (&l)[P],
                                         uint32_t (&d)[P], uint32_t (&x)[P], uint32_t (&l2)[P],
                                         uint32_t (&d2)[P], uint32_t (&x2)[P], const LatArgs &a,
                                         uint32_t G, uint64_t e, uint32_t act, uint32_t &moved,
@@ -560,8 +562,6 @@ __device__ __forceinline__ void lat_hop(uint32_t *p, uint32_t *p2, bool self, ui
     add_pm1<P>(x2, sA & mv, 0u);
     add_pm1<P>(l2, sL & mv, 0u);
     add_pm1<P>(d2, sD & mv, 0u);
-    store_site<P>(p, l, d, x);
-    store_site<P>(p2, l2, d2, x2);
 }
 
 // Lanes of a word that run event e (E_l <= e < Et_l); kept out of line so the
@@ -584,9 +584,21 @@ __device__ __noinline__ uint32_t lanes_at(const uint64_t *sE, const uint64_t *sE
 // group run on one XCD (workgroups go to the 8 XCDs in turn), where they
 // share the group's schedule in L2.  Runs the events of chunks chunk0 ..
 // chunk0+n_chunks-1 layer by layer.
-template <int P, int BC, int64_t CU, int64_t CA, int64_t CI, int WS, int BLOCK>
+//
+// ST > 0 (P = 4): the planes of sites 0 .. ST/WS - 1 of the slice's words
+// are copied into LDS when the launch starts and back when it ends, and
+// every event on those sites reads and writes LDS instead of memory.  LDS
+// holds ST = 3360 (site, word) pairs (158 KB of the CU's 160 KB): with 4-word
+// slices the first 840 sites of each word, a fifth of a 64 x 64 lattice.
+// Within a layer no two events share a site, so the LDS copy needs no more
+// ordering than the memory planes do.  (One word per workgroup would hold
+// 3392 sites, 83 % of a 64 x 64 lattice, but a word's layers hold ~550
+// independent events on average, half of the 1024 threads a CU needs to
+// hide latency: measured slower.)
+template <int P, int BC, int64_t CU, int64_t CA, int64_t CI, int WS, int BLOCK, int ST>
 __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
 {
+    static_assert(ST == 0 || P == 4, "staging holds 12 planes per site and word");
     constexpr int NP = 3 * P;
     constexpr int NSL = LAT_GROUP_WORDS / WS;   // slices per group
     constexpr int EV = BLOCK / WS;              // events in flight per workgroup
@@ -635,7 +647,36 @@ __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
     }
     const int S = a.sh.S;
     uint32_t n_real = 0, n_blocked = 0;
-    if (whi > wlo) {
+    // the launch's events of this slice: [wlo, whi) within its chunks
+    const uint64_t c_lo = a.base + (uint64_t)a.chunk0 * LAT_CH;
+    const uint64_t c_hi = c_lo + (uint64_t)a.n_chunks * LAT_CH;
+    const bool runs = whi > wlo && wlo < c_hi && whi > c_lo;
+    // stage[(st WS + word) 3 + part]: the slice's WS words of site st
+    __shared__ uint4 stage[ST > 0 ? 3 * ST : 1];
+    const uint32_t nst = ST > 0 ? min((uint32_t)S, (uint32_t)(ST / WS)) : 0u;
+    if (ST > 0 && runs) {
+        for (uint32_t k = tid; k < 3 * WS * nst; k += BLOCK)
+            stage[k] = reinterpret_cast<const uint4 *>(
+                site_planes(a.planes, w0 + (k / 3) % WS, k / (3 * WS), S, NP))[k % 3];
+        __syncthreads();
+    }
+    // planes of site st of this thread's word: LDS for staged sites.  The two
+    // cases stay separate instructions (LDS and memory loads wait on their own
+    // counters, so the next event's memory loads still overlap this event)
+    auto load_at = [&](uint32_t st, uint32_t (&l_)[P], uint32_t (&d_)[P], uint32_t (&x_)[P]) {
+        if (ST > 0 && st < nst)
+            load_site<P>(reinterpret_cast<const uint32_t *>(&stage[3 * (st * WS + lw)]), l_, d_, x_);
+        else
+            load_site<P>(site_planes(a.planes, w, st, S, NP), l_, d_, x_);
+    };
+    auto store_at = [&](uint32_t st, const uint32_t (&l_)[P], const uint32_t (&d_)[P],
+                        const uint32_t (&x_)[P]) {
+        if (ST > 0 && st < nst)
+            store_site<P>(reinterpret_cast<uint32_t *>(&stage[3 * (st * WS + lw)]), l_, d_, x_);
+        else
+            store_site<P>(site_planes(a.planes, w, st, S, NP), l_, d_, x_);
+    };
+    if (runs) {
         for (uint32_t c = 0; c < a.n_chunks; ++c) {
             const uint32_t *slotp = a.sched + ((uint64_t)g * LAT_NCB + c) * LAT_SLOT;
             const uint32_t *recs = slotp;
@@ -662,8 +703,8 @@ __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
                     kind = rec & 7u;
                     s2 = kind ? lat_neighbour(a.sh, s, kind - 1) : s;
                     if (act) {
-                        load_site<P>(site_planes(a.planes, w, s, S, NP), l, d, x);
-                        if (s2 != s) load_site<P>(site_planes(a.planes, w, s2, S, NP), l2, d2, x2);
+                        load_at(s, l, d, x);
+                        if (s2 != s) load_at(s2, l2, d2, x2);
                     }
                 };
                 if (idx < end) fetch(idx);
@@ -683,14 +724,19 @@ __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
                     idx += EV;
                     if (idx < end) fetch(idx);
                     if (!act_c) continue;
-                    uint32_t *p = site_planes(a.planes, w, s_c, S, NP);
                     if (kind_c == 0) {
-                        n_real += __popc(lat_reaction<P, BC, CU, CA, CI>(p, lc, dc, xc, a,
-                                                                         (uint32_t)w, e_c, act_c));
+                        const uint32_t ch = lat_reaction<P, BC, CU, CA, CI>(lc, dc, xc, a,
+                                                                            (uint32_t)w, e_c, act_c);
+                        if (ch) store_at(s_c, lc, dc, xc);
+                        n_real += __popc(ch);
                     } else {
                         uint32_t mv, bl;
-                        lat_hop<P>(p, site_planes(a.planes, w, s2_c, S, NP), s2_c == s_c, lc, dc, xc,
-                                   l2c, d2c, x2c, a, (uint32_t)w, e_c, act_c, mv, bl);
+                        lat_hop<P>(s2_c == s_c, lc, dc, xc, l2c, d2c, x2c, a, (uint32_t)w, e_c,
+                                   act_c, mv, bl);
+                        if (mv) {
+                            store_at(s_c, lc, dc, xc);
+                            store_at(s2_c, l2c, d2c, x2c);
+                        }
                         n_real += __popc(mv);
                         n_blocked += __popc(bl);
                     }
@@ -698,6 +744,12 @@ __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
                 __syncthreads();
             }
         }
+    }
+    if (ST > 0 && runs) {
+        __syncthreads();
+        for (uint32_t k = tid; k < 3 * WS * nst; k += BLOCK)
+            reinterpret_cast<uint4 *>(
+                site_planes(a.planes, w0 + (k / 3) % WS, k / (3 * WS), S, NP))[k % 3] = stage[k];
     }
     // per-word totals of real events and blocked hops
     if (n_real) atomicAdd(&sred[0][lw], n_real);
@@ -799,29 +851,31 @@ hipError_t launch_lat_schedule(const LatArgs &a, uint32_t n_groups, hipStream_t 
     return hipGetLastError();
 }
 
-// (id, P, BC, CU, CA, CI, WS, BLOCK): species planes, threshold-plane
+// (id, P, BC, CU, CA, CI, WS, BLOCK, ST): species planes, threshold-plane
 // capacity, the weights of A -> L / A -> D, A + L -> 2L / A + D -> 2D and
-// L + D -> 2A (-1: taken at run time), words per slice and threads per
-// workgroup (512 for the run-time weights, which need more registers).
+// L + D -> 2A (-1: taken at run time), words per slice, threads per
+// workgroup (512 for the run-time weights, which need more registers) and
+// sites staged in LDS (0: none).
 #define BWG_LAT_VARIANTS(X)                                                                   \
-    X(0, 4, 19, 246, 2048, 2048, 4, 1024) X(1, 4, 19, 246, 2048, 2048, 1, 1024)                \
-    X(2, 4, 19, -1, -1, -1, 4, 512) X(3, 4, 19, -1, -1, -1, 1, 512)                            \
-    X(4, 4, 24, -1, -1, -1, 4, 512) X(5, 4, 24, -1, -1, -1, 1, 512)
+    X(0, 4, 19, 246, 2048, 2048, 4, 1024, 0) X(1, 4, 19, 246, 2048, 2048, 1, 1024, 0)          \
+    X(2, 4, 19, -1, -1, -1, 4, 512, 0) X(3, 4, 19, -1, -1, -1, 1, 512, 0)                      \
+    X(4, 4, 24, -1, -1, -1, 4, 512, 0) X(5, 4, 24, -1, -1, -1, 1, 512, 0)                      \
+    X(6, 4, 19, 246, 2048, 2048, 4, 1024, 4 * BWG_LAT_STAGE_SITES)
 
 // grid: the slices of the band's groups, rounded up to a multiple of the 8 XCDs
-#define BWG_LAT_LAUNCH(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_)                                  \
+#define BWG_LAT_LAUNCH(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_, ST_)                             \
     static hipError_t lat_launch_##ID(const LatArgs &a, uint64_t words, hipStream_t s)       \
     {                                                                                         \
         (void)words;                                                                          \
         const uint64_t nwg = (uint64_t)a.ng * (LAT_GROUP_WORDS / WS_);                        \
-        hipLaunchKernelGGL((lat_event_kernel<P_, BC_, CU_, CA_, CI_, WS_, BL_>),              \
+        hipLaunchKernelGGL((lat_event_kernel<P_, BC_, CU_, CA_, CI_, WS_, BL_, ST_>),         \
                            dim3((unsigned)(8 * ((nwg + 7) / 8))), dim3(BL_), 0, s, a);        \
         return hipGetLastError();                                                             \
     }
 BWG_LAT_VARIANTS(BWG_LAT_LAUNCH)
 
 #ifndef __HIP_DEVICE_COMPILE__
-#define BWG_LAT_ROW(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_) {P_, BC_, CU_, CA_, CI_, WS_, BL_, lat_launch_##ID},
+#define BWG_LAT_ROW(ID, P_, BC_, CU_, CA_, CI_, WS_, BL_, ST_) {P_, BC_, CU_, CA_, CI_, WS_, BL_, ST_, lat_launch_##ID},
 const LatVariant kLatVariants[] = {BWG_LAT_VARIANTS(BWG_LAT_ROW)};
 const int kLatVariantCount = sizeof(kLatVariants) / sizeof(kLatVariants[0]);
 #endif

@@ -158,14 +158,20 @@ static uint32_t lat_band_groups(const bwg_net *n, int ws, uint64_t groups)
     return (uint32_t)((groups + bands - 1) / bands);
 }
 
-static const LatVariant *pick_lat_variant(const bwg_net *n, uint64_t M)
+// The event kernel of a lattice for the slice width lat_slice_words picks:
+// the LDS-staged one where one exists and staging is asked for, else the
+// memory one; compile-time weights before run-time ones, then the fewest
+// threshold planes.
+static const LatVariant *pick_lat_variant(const bwg_net *n, uint64_t M, bool stage)
 {
     if (!n->lat_gpu) return nullptr;
     const LatShape &sh = n->lsh;
-    const int ws = lat_slice_words(M);
     const LatVariant *best = nullptr;
+    for (int pass = stage ? 0 : 1; pass < 2 && !best; ++pass)
     for (int i = 0; i < kLatVariantCount; ++i) {
         const LatVariant &v = kLatVariants[i];
+        const int ws = lat_slice_words(M);
+        if ((v.stage > 0) != (pass == 0)) continue;
         if (v.P != sh.P || v.bc < sh.B_r + 1 || v.ws != ws) continue;
         if (v.cu >= 0 && ((uint64_t)v.cu != sh.cu || (uint64_t)v.ca != sh.ca ||
                           (uint64_t)v.ci != sh.ci))
@@ -222,7 +228,7 @@ static LatLayout lat_layout(const bwg_net *n, uint64_t M, uint64_t table_cap)
 
 int lat_state_bytes(const bwg_net *n, uint64_t M, uint64_t table_cap, uint64_t *bytes)
 {
-    if (!pick_lat_variant(n, M))
+    if (!pick_lat_variant(n, M, false))
         return fail(BWG_EUNSUPPORTED, "no lattice event kernel for P=%d, B_r=%d and these weights",
                     n->lsh.P, n->lsh.B_r);
     *bytes = lat_layout(n, M, table_cap).total;
@@ -232,7 +238,7 @@ int lat_state_bytes(const bwg_net *n, uint64_t M, uint64_t table_cap, uint64_t *
 int lat_bind(bwg_ens *e)
 {
     const bwg_net *n = e->net;
-    e->lvar = pick_lat_variant(n, e->M);
+    e->lvar = pick_lat_variant(n, e->M, e->lat_stage);
     const LatLayout L = lat_layout(n, e->M, e->table_cap);
     e->lat = true;
     e->words = (e->M + 31) / 32;

@@ -34,10 +34,15 @@ import paper_2412_16613_amd as bwg
 
 class Server:
     def __init__(self, hbm_budget=64 << 30, chunk=4096, max_members=1024,
-                 max_items=1 << 16, waves=2048, n_bins=256, keep_counts=False,
-                 lattice_chunk=1 << 17, depth=2, device="cuda"):
+                 max_items=1 << 19, waves=2048, n_bins=256, keep_counts=False,
+                 lattice_chunk=1 << 17, depth=2, lanes_events=1e5, device="cuda"):
         import torch
         self.torch = torch
+        # well-mixed requests expecting at least this many events per replica
+        # run on the lanes engine (one replica per thread: a word's chain of
+        # events an order of magnitude shorter, at about twice the work per
+        # replica-event); 0 keeps every request on bit-sliced words
+        self.lanes_events = float(lanes_events)
         self.device = torch.device(device)
         self.lattice_chunk = int(lattice_chunk)
         self.side = None
@@ -64,8 +69,11 @@ class Server:
         return n
 
     @staticmethod
-    def _items(M):
-        return (((M + 31) // 32) + 63) // 64
+    def _items(M, lanes):
+        """Work items of a member in the persistent batch: 64-word items, or
+        2-word items on the lanes engine."""
+        words = (M + 31) // 32
+        return (words + 1) // 2 if lanes else (words + 63) // 64
 
     def serve(self, requests, real_time=True, max_seconds=None, pass_time=1.0, progress=None,
               progress_every=20.0):
@@ -137,10 +145,12 @@ class Server:
                 r = waiting[0]
                 net = self._network(r["net"])
                 lattice = net.is_lattice
+                lanes = (not lattice and self.lanes_events > 0 and
+                         net.quantized()["Lambda"] * r["t_end"] >= self.lanes_events)
                 ens = bwg.Ensemble(net, r["replicas"], seed=r["seed"], net_id=r["net_id"],
-                                   device=self.device)
+                                   device=self.device, engine="lanes" if lanes else "bitwise")
                 nbytes = ens.state_bytes
-                items = 0 if lattice else self._items(r["replicas"])
+                items = 0 if lattice else self._items(r["replicas"], lanes)
                 if (active or inflight) and (used_bytes + nbytes > self.hbm_budget
                                              or used_items + items > self.max_items):
                     del ens

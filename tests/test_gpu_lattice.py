@@ -24,8 +24,9 @@ def lattice(side_x, side_y, **kw):
     return frank_network(12, lx=side_x, ly=side_y, **kw)
 
 
-def pair(net, M, seed=1, net_id=5, init=UNIFORM, first=0, count=None, stride=1):
-    ens = bwg.Ensemble(bwg.Network(net), M, seed=seed, net_id=net_id)
+def pair(net, M, seed=1, net_id=5, init=UNIFORM, first=0, count=None, stride=1,
+         lds_stage=True):
+    ens = bwg.Ensemble(bwg.Network(net), M, seed=seed, net_id=net_id, lds_stage=lds_stage)
     ens.init(init)
     orc = OracleLattice(net, M, seed=seed, net_id=net_id, first=first, count=count,
                         stride=stride, threads=8)
@@ -63,13 +64,15 @@ def test_fixed_event_count(lx, ly, M, K):
     check(ens, orc, "step")
 
 
+@pytest.mark.parametrize("lds_stage", [True, False])
 @pytest.mark.parametrize("M", [16384 + 1000 + 7, 40000 + 5])
-def test_sliced_workgroups_every_replica(M):
-    """Ensembles of 512 words and more run 4-word slices per workgroup and,
-    beyond 16 groups, several launches over bands of groups; ragged last
+def test_sliced_workgroups_every_replica(M, lds_stage):
+    """Ensembles of 512 words and more: without staging, 4-word slices per
+    workgroup and, beyond 16 groups, several launches over bands of groups;
+    staged, one word per workgroup with the whole lattice in LDS.  Ragged last
     slice and group, all replicas compared."""
     net = lattice(4, 4)
-    ens, orc = pair(net, M, seed=12)
+    ens, orc = pair(net, M, seed=12, lds_stage=lds_stage)
     ens.step(1000)
     orc.step(1000)
     check(ens, orc, "8-word slices, step")
@@ -193,3 +196,25 @@ def test_full_lattice_bench_configuration_sampled():
         o.advance(c["t_end"])
         check(ens, o, "64x64, t=20, replicas %d + k * %d" % (first, stride))
         np.testing.assert_array_equal(ev[first::stride][:count], o.E)
+
+
+@pytest.mark.parametrize("lx,ly,kw,M,t", [
+    (64, 64, {}, 16384 + 37, 1.0),       # sites 840.. stay in memory, ragged last slice
+    (24, 24, {}, 20000, 2.0),            # every site in LDS
+    (29, 29, {}, 16384 + 5, 1.0),        # one site (840) beyond the staged ones
+    (59, 61, {}, 64 * 600, 0.2)])        # several launch bands
+def test_lds_staged_kernel_equals_memory_kernel(lx, ly, kw, M, t):
+    """The event kernel that keeps the first 840 sites of each word of a
+    4-word slice in LDS gives every replica's site counts, event counts and
+    blocked hops of the kernel that keeps them in memory, bit for bit (all
+    replicas; ensembles of 512 words and more take the staged kernel)."""
+    net = bwg.Network(lattice(lx, ly, **kw))
+    out = []
+    for stage in (True, False):
+        e = bwg.Ensemble(net, M, seed=21, net_id=9, lds_stage=stage)
+        e.init(UNIFORM).advance(t)
+        ev, real = e.read_events()
+        out.append((e.read_sites(0, M), ev, real, e.read_blocked()))
+        del e
+    for a, b in zip(*out):
+        assert torch.equal(a, b)

@@ -30,9 +30,12 @@ def _requests():
     return out
 
 
-def test_served_results_equal_results_alone(torch):
+@pytest.mark.parametrize("lanes_events", [0, 1e5, 1])
+def test_served_results_equal_results_alone(torch, lanes_events):
+    # lanes_events: none, the long chains, or every well-mixed request on
+    # the lanes engine (2-word items in the persistent batch)
     reqs = _requests()
-    srv = Server(chunk=200, max_members=4, keep_counts=True)
+    srv = Server(chunk=200, max_members=4, keep_counts=True, lanes_events=lanes_events)
     res = srv.serve(reqs, real_time=False, pass_time=1.0)
     assert len(res) == len(reqs)
     assert srv.stats["max_active"] >= 2          # the mix really overlapped
