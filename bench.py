@@ -154,7 +154,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=4096, help="serve: events per word per pass")
     ap.add_argument("--no-lds-stage", action="store_true",
                     help="lattice: the event kernel that keeps every site in memory")
-    ap.add_argument("--lanes-events", type=float, default=1e5,
+    ap.add_argument("--lanes-events", type=float, default=0.0,
                     help="serve: requests expecting at least this many events per replica run "
                          "on the lanes engine (0: none)")
     ap.add_argument("--compare-nets", type=int, default=32,

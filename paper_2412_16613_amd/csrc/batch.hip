@@ -96,7 +96,9 @@ __global__ __launch_bounds__(64, 2) void wm_persistent_kernel(const BatchEns *en
                                                               uint32_t *counter,
                                                               uint64_t max_events)
 {
-    __shared__ __align__(16) uint32_t sq[2][kLanesHalfWords];
+    // the lanes items' event rows (2 x kLanesHalfWords words), allocated at
+    // launch only when the queue holds lanes items
+    extern __shared__ __align__(16) uint32_t sq_dyn[];
     for (;;) {
         uint32_t it = 0;
         if (threadIdx.x == 0) it = atomicAdd(counter, 1u);
@@ -105,7 +107,8 @@ __global__ __launch_bounds__(64, 2) void wm_persistent_kernel(const BatchEns *en
         const BatchItem bi = items[it];
         if (bi.ens & BATCH_ITEM_LANES) {
             const int half = threadIdx.x >> 5;
-            wm_lanes_item(&ens[bi.ens & ~BATCH_ITEM_LANES].a, (uint64_t)bi.word0 + half, sq[half],
+            wm_lanes_item(&ens[bi.ens & ~BATCH_ITEM_LANES].a, (uint64_t)bi.word0 + half,
+                          sq_dyn + half * kLanesHalfWords,
                           max_events);
             continue;
         }
@@ -170,9 +173,11 @@ __global__ void batch_epilogue_kernel(const BatchBudget *bb, int n_ens)
 }
 
 hipError_t launch_persistent(const BatchEns *ens, const BatchItem *items, uint32_t n_items,
-                             uint32_t *counter, int waves, uint64_t max_events, hipStream_t s)
+                             uint32_t *counter, int waves, uint64_t max_events, bool lanes,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(wm_persistent_kernel, dim3((uint32_t)waves), dim3(64), 0, s, ens, items,
+    const size_t lds = lanes ? 2 * kLanesHalfWords * sizeof(uint32_t) : 0;
+    hipLaunchKernelGGL(wm_persistent_kernel, dim3((uint32_t)waves), dim3(64), lds, s, ens, items,
                        n_items, counter, max_events);
     return hipGetLastError();
 }

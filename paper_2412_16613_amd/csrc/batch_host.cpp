@@ -22,6 +22,7 @@ struct bwg_batch {
     int cap_ens = 0;
     uint64_t cap_items = 0;
     uint64_t n_items = 0;          // items of the current members
+    bool lanes_items = false;      // the staged queue holds lanes items
     // device layout (caller buffer)
     BatchEns *d_ens = nullptr;
     BatchBudget *d_budget = nullptr;
@@ -258,6 +259,7 @@ static int stage_items(bwg_batch *b, hipStream_t s)
 {
     std::vector<std::pair<double, BatchItem>> q;
     q.reserve(b->n_items);
+    b->lanes_items = false;
     for (size_t k = 0; k < b->ens.size(); ++k) {
         const bwg_ens *e = b->ens[k];
         const uint64_t words = (e->M + 31) / 32, split = std::min(lanes_split(e), words);
@@ -267,6 +269,7 @@ static int stage_items(bwg_batch *b, hipStream_t s)
             q.push_back({cw, BatchItem{(uint32_t)k, (uint32_t)w0}});
         for (uint64_t w0 = split; w0 < words; w0 += 2)
             q.push_back({cl, BatchItem{(uint32_t)k | BATCH_ITEM_LANES, (uint32_t)w0}});
+        if (split < words) b->lanes_items = true;
     }
     if (b->order == 0)
         std::stable_sort(q.begin(), q.end(),
@@ -346,7 +349,7 @@ static int enqueue_pass(bwg_batch *b, uint64_t max_events, hipStream_t s)
     if (!b->n_items) return BWG_OK;
     HIP_TRY(launch_batch_prologue(b->d_counter, s));
     HIP_TRY(launch_persistent(b->d_ens, b->d_items, (uint32_t)b->n_items, b->d_counter, b->waves,
-                              max_events, s));
+                              max_events, b->lanes_items, s));
     return BWG_OK;
 }
 

@@ -147,7 +147,8 @@ extern const PersistVariant kPersistVariants[];
 extern const int kPersistVariantCount;
 
 hipError_t launch_persistent(const BatchEns *ens, const BatchItem *items, uint32_t n_items,
-                             uint32_t *counter, int waves, uint64_t max_events, hipStream_t s);
+                             uint32_t *counter, int waves, uint64_t max_events, bool lanes,
+                             hipStream_t s);
 hipError_t launch_batch_budget(const BatchBudget *bb, int n_ens, uint64_t total, hipStream_t s);
 hipError_t launch_batch_prologue(uint32_t *counter, hipStream_t s);
 hipError_t launch_batch_epilogue(const BatchBudget *bb, int n_ens, hipStream_t s);

@@ -55,24 +55,49 @@ static int64_t comb_h(const int32_t *r, const int64_t *N, int S)
     return v;
 }
 
+// Total weight sum_j c_j h_j(N) of the 3-species state (a, b, c).
+static int64_t total_weight_at(const bwg_net &n, int64_t a, int64_t b, int64_t c)
+{
+    const int64_t st[3] = {a, b, c};
+    int64_t t = 0;
+    for (int j = 0; j < n.R; ++j)
+        if (n.q.c[j]) t += n.q.c[j] * comb_h(&n.reac[j * 3], st, 3);
+    return t;
+}
+
 // Smallest and largest total weight over every state with n_tot molecules
-// (3 species).
+// (3 species), exactly and in O(n_tot): with the first count a fixed, every
+// h_j is a polynomial of degree at most 2 in the second count t (the third
+// is n_tot - a - t), so the total is an integer quadratic W(t) on [0, M],
+// M = n_tot - a.  Its extremes over the integers lie at the ends of the range
+// or at the integers next to the vertex t* = 1/2 - (W(1) - W(0)) / d2, d2 =
+// W(2) - 2 W(1) + W(0) (the maximum there when d2 < 0, the minimum when
+// d2 > 0); every candidate is evaluated exactly in int64, and the window
+// around t* is wide enough for the rounding of t* in binary64.
 static void total_weight_range(const bwg_net &n, int64_t *lo, int64_t *hi)
 {
     int64_t best = 0, least = INT64_MAX;
     const int64_t N = n.n_tot;
-    int64_t st[3];
-    for (int64_t a = 0; a <= N; ++a)
-        for (int64_t b = 0; b <= N - a; ++b) {
-            st[0] = a;
-            st[1] = b;
-            st[2] = N - a - b;
-            int64_t t = 0;
-            for (int j = 0; j < n.R; ++j)
-                if (n.q.c[j]) t += n.q.c[j] * comb_h(&n.reac[j * n.S], st, n.S);
-            if (t > best) best = t;
-            if (t < least) least = t;
-        }
+    for (int64_t a = 0; a <= N; ++a) {
+        const int64_t M = N - a;
+        auto take = [&](int64_t t) {
+            if (t < 0 || t > M) return;
+            const int64_t v = total_weight_at(n, a, t, M - t);
+            if (v > best) best = v;
+            if (v < least) least = v;
+        };
+        take(0);
+        take(M);
+        if (M < 2) continue;
+        const int64_t w0 = total_weight_at(n, a, 0, M), w1 = total_weight_at(n, a, 1, M - 1),
+                      w2 = total_weight_at(n, a, 2, M - 2);
+        const int64_t d2 = w2 - 2 * w1 + w0;
+        if (d2 == 0) continue;  // linear in t: the ends
+        const double ts = 0.5 - (double)(w1 - w0) / (double)d2;
+        if (!(ts > -2.0 && ts < (double)M + 2.0)) continue;
+        const int64_t f = (int64_t)std::floor(ts);
+        for (int64_t t = f - 1; t <= f + 2; ++t) take(t);
+    }
     *lo = least;
     *hi = best;
 }

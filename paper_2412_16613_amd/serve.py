@@ -35,13 +35,15 @@ import paper_2412_16613_amd as bwg
 class Server:
     def __init__(self, hbm_budget=64 << 30, chunk=4096, max_members=1024,
                  max_items=1 << 19, waves=2048, n_bins=256, keep_counts=False,
-                 lattice_chunk=1 << 17, depth=2, lanes_events=1e5, device="cuda"):
+                 lattice_chunk=1 << 17, depth=2, lanes_events=0, device="cuda"):
         import torch
         self.torch = torch
         # well-mixed requests expecting at least this many events per replica
         # run on the lanes engine (one replica per thread: a word's chain of
         # events an order of magnitude shorter, at about twice the work per
-        # replica-event); 0 keeps every request on bit-sliced words
+        # replica-event); 0 (the default: served at 200 arrivals/s it changes
+        # the latencies by a few per cent and costs throughput at saturation)
+        # keeps every request on bit-sliced words
         self.lanes_events = float(lanes_events)
         self.device = torch.device(device)
         self.lattice_chunk = int(lattice_chunk)

@@ -11,7 +11,7 @@ import paper_2412_16613_amd as bwg
 from paper_2412_16613_amd import _abi
 from oracle.poisson import poisson_table as oracle_table
 from oracle.quantize import quantize
-from workloads import batch_networks, frank_network, paper_network
+from workloads import batch_networks, frank_network, paper_network, random_network
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -59,6 +59,22 @@ def test_quantisation_matches_oracle_on_random_rates():
             _qcmp(net)
         except bwg.BwgError as e:
             # beyond 32 threshold planes: the oracle's bound agrees
+            assert e.code == _abi.BWG_ERANGE and quantize(net)["B"] > 32
+
+
+def test_total_weight_range_matches_enumeration_on_random_networks():
+    # the library finds the largest and smallest total weight over the simplex
+    # from the quadratic in the second count (ends and the integers next to
+    # the vertex); the oracle enumerates every state.  Random 3-species tables
+    # with dimerisations (concave and convex quadratics), exact-integer and
+    # real rates, down to one and two molecules
+    rng = np.random.default_rng(11)
+    for k in range(60):
+        n = int(rng.choice([1, 2, 3, 4, 7])) if k < 15 else int(rng.integers(5, 260))
+        net = random_network(1000 + k, n, int(rng.integers(1, 9)), exact_integer=bool(k % 2))
+        try:
+            _qcmp(net)
+        except bwg.BwgError as e:
             assert e.code == _abi.BWG_ERANGE and quantize(net)["B"] > 32
 
 
