@@ -5,7 +5,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "host_internal.h"
@@ -32,6 +35,8 @@ struct bwg_batch {
     BatchEns *h_ens = nullptr;
     BatchBudget *h_budget = nullptr;
     BatchItem *h_items = nullptr;
+    uint64_t *h_tables = nullptr;  // Poisson tables of an advance, back to back
+    uint64_t h_tables_cap = 0;     // entries
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
     ~bwg_batch()
@@ -41,6 +46,7 @@ struct bwg_batch {
         if (h_ens) (void)hipHostFree(h_ens);
         if (h_budget) (void)hipHostFree(h_budget);
         if (h_items) (void)hipHostFree(h_items);
+        if (h_tables) (void)hipHostFree(h_tables);
     }
 };
 
@@ -283,29 +289,70 @@ static int stage_items(bwg_batch *b, hipStream_t s)
 }
 
 // Tables and budget descriptors of one advance of every member to t_end[k].
+// The members' Poisson tables (binary128 sums, up to a few ms each for long
+// horizons) are built on up to 16 host threads, then staged back to back in
+// the batch's pinned buffer (reused once its last upload has completed).
 static int stage_budgets(bwg_batch *b, const double *t_end, hipStream_t s,
                          std::vector<uint64_t> &kmin, std::vector<uint64_t> &kmax)
 {
     const int n = (int)b->ens.size();
     kmin.assign(n, 0);
     kmax.assign(n, 0);
-    uint64_t offset = 0;
+    std::vector<double> mu(n, 0.0);
+    int need = 0;
     for (int k = 0; k < n; ++k) {
-        bwg_ens *e = b->ens[k];
+        const bwg_ens *e = b->ens[k];
         if (!e->inited) return fail(BWG_EINVAL, "ensemble %d not initialised", k);
         if (!(t_end[k] >= e->t_now))
             return fail(BWG_EINVAL, "ensemble %d: t_end %g before t_now %g", k, t_end[k], e->t_now);
-        const double mu = e->net->q.lambda * (t_end[k] - e->t_now);
+        mu[k] = e->net->q.lambda * (t_end[k] - e->t_now);
+        if (mu[k] > 0) ++need;
+    }
+    std::vector<const Table *> tab(n, nullptr);
+    std::vector<int> rc(n, BWG_OK);
+    std::vector<std::string> msg(n);
+    std::atomic<int> next(0);
+    auto work = [&]() {
+        for (int k; (k = next.fetch_add(1)) < n;) {
+            if (!(mu[k] > 0)) continue;
+            rc[k] = get_table(b->ens[k]->net, mu[k], &tab[k], false);
+            if (rc[k]) msg[k] = bwg_last_error();
+        }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = std::min<int>(need, (int)std::min(16u, hw));
+    std::vector<std::thread> pool;
+    for (int i = 1; i < nt; ++i) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
+    uint64_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        if (rc[k]) return fail(rc[k], "ensemble %d: %s", k, msg[k].c_str());
+        if (!tab[k]) continue;
+        if (tab[k]->len > b->ens[k]->table_cap)
+            return fail(BWG_ERANGE, "ensemble %d: Poisson table of %llu entries exceeds %llu", k,
+                        (unsigned long long)tab[k]->len,
+                        (unsigned long long)b->ens[k]->table_cap);
+        total += tab[k]->len;
+    }
+    if (total > b->h_tables_cap) {
+        if (b->h_tables) HIP_TRY(hipHostFree(b->h_tables));
+        b->h_tables = nullptr;
+        b->h_tables_cap = 0;
+        const uint64_t cap = total + total / 4;
+        HIP_TRY(hipHostMalloc((void **)&b->h_tables, cap * sizeof(uint64_t), hipHostMallocDefault));
+        b->h_tables_cap = cap;
+    }
+    uint64_t offset = 0, toff = 0;
+    for (int k = 0; k < n; ++k) {
+        bwg_ens *e = b->ens[k];
         BatchBudget &bb = b->h_budget[k];
         memset(&bb, 0, sizeof bb);
-        if (mu > 0) {
-            const Table *t;
-            int rc = get_table(e->net, mu, &t);
-            if (rc) return rc;
-            if (t->len > e->table_cap)
-                return fail(BWG_ERANGE, "ensemble %d: Poisson table of %llu entries exceeds %llu",
-                            k, (unsigned long long)t->len, (unsigned long long)e->table_cap);
-            HIP_TRY(hipMemcpyAsync(e->table, t->host, t->len * 8, hipMemcpyHostToDevice, s));
+        if (const Table *t = tab[k]) {
+            memcpy(b->h_tables + toff, t->vals.data(), t->len * sizeof(uint64_t));
+            HIP_TRY(hipMemcpyAsync(e->table, b->h_tables + toff, t->len * 8, hipMemcpyHostToDevice,
+                                   s));
+            toff += t->len;
             bb.T = e->table;
             bb.len = t->len;
             bb.k_lo = t->k_lo;
