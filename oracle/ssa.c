@@ -31,11 +31,12 @@
  *   counter  = (c0, (domain << 24) | (quad << 16) | hi16, c2, net_id)
  *   EVENT  (1): c0 = event low 32, hi16 = event bits 32..47, c2 = replica/32;
  *               bit (replica mod 32) of output (q mod 4) of quad q/4 is bit q
- *               of n.
+ *               of n (B planes, up to 62: n is 64-bit).
  *   BUDGET (2): c0 = advance index low 32, c2 = replica; u = out0 | out1<<32.
  *   INIT   (3): c0 = chunk, c2 = replica.
  *   PLAIN  (4): c0 = (event/4) low 32, hi16 = bits 32..47 of event/4,
- *               c2 = replica; n = out[event mod 4] mod 2^B.
+ *               c2 = replica; n = out[event mod 4] mod 2^B (B <= 32; the
+ *               runner refuses wider weights with -4).
  *   SHARED (6): the paper's variant in which one n serves every copy at an
  *               event (Sec. 4, the remark after the bitwise step; Sec. 6):
  *               c0 = event low 32, quad field = attempt, c2 = 0; n uniform
@@ -96,22 +97,25 @@ void orc_philox(const uint32_t ctr[4], uint64_t seed, uint32_t out[4])
     philox(ctr[0], ctr[1], ctr[2], ctr[3], seed, out);
 }
 
-/* n for replica i at event e, bit-plane contract (EVENT domain). */
-static uint32_t draw_event(uint64_t seed, uint32_t net_id, uint64_t i,
+/* n for replica i at event e, bit-plane contract (EVENT domain); B up to
+ * 62 planes (weights beyond 32 bits need more than 8 quads). */
+static uint64_t draw_event(uint64_t seed, uint32_t net_id, uint64_t i,
                            uint64_t e, int B)
 {
-    uint32_t G = (uint32_t)(i >> 5), lane = (uint32_t)(i & 31u), n = 0, out[4];
+    uint32_t G = (uint32_t)(i >> 5), lane = (uint32_t)(i & 31u), out[4];
+    uint64_t n = 0;
     for (int quad = 0; 4 * quad < B; ++quad) {
         philox((uint32_t)e,
                (1u << 24) | ((uint32_t)quad << 16) | (uint32_t)((e >> 32) & 0xFFFFu),
                G, net_id, seed, out);
         for (int j = 0; j < 4 && 4 * quad + j < B; ++j)
-            n |= ((out[j] >> lane) & 1u) << (4 * quad + j);
+            n |= (uint64_t)((out[j] >> lane) & 1u) << (4 * quad + j);
     }
     return n;
 }
 
-/* n for replica i at event e, one-replica-per-thread contract (PLAIN). */
+/* n for replica i at event e, one-replica-per-thread contract (PLAIN; one
+ * 32-bit output, so B <= 32). */
 static uint32_t draw_plain(uint64_t seed, uint32_t net_id, uint64_t i,
                            uint64_t e, int B)
 {
@@ -152,12 +156,12 @@ static int64_t comb(const orc_net *net, int j, const int64_t *N)
 
 /* CDF search (Eqs. (10)-(11)): first reaction r, in table order, with
  * n < sum_{p<=r} w_p(N); -1 (null event) if n is at or above the total. */
-static int select_reaction(const orc_net *net, const int64_t *N, uint32_t n)
+static int select_reaction(const orc_net *net, const int64_t *N, uint64_t n)
 {
-    int64_t m = 0;
+    int64_t m = 0;  /* weights are non-negative: m >= 0 */
     for (int j = 0; j < net->n_reactions; ++j) {
         m += net->c[j] * comb(net, j, N);
-        if ((int64_t)n < m) return j;
+        if (n < (uint64_t)m) return j;
     }
     return -1;
 }
@@ -165,7 +169,7 @@ static int select_reaction(const orc_net *net, const int64_t *N, uint32_t n)
 /* One event of the direct method.  Returns the reaction index, -1 for a
  * null event, -3 for a selected reaction blocked by the cap (open networks;
  * the state is unchanged); returns -2 on an invariant violation. */
-static int one_event(const orc_net *net, int64_t *N, uint32_t n)
+static int one_event(const orc_net *net, int64_t *N, uint64_t n)
 {
     int r = select_reaction(net, N, n);
     if (r < 0) return -1;
@@ -193,7 +197,7 @@ static int changes_state(const orc_net *net, int r)
     return 0;
 }
 
-int orc_select(const orc_net *net, const int32_t *counts, uint32_t n)
+int orc_select(const orc_net *net, const int32_t *counts, uint64_t n)
 {
     int64_t N[ORC_MAX_S];
     for (int x = 0; x < net->n_species; ++x) N[x] = counts[x];
@@ -215,6 +219,7 @@ int orc_wm_run(const orc_net *net, uint64_t seed, uint32_t net_id,
 {
     const int S = net->n_species;
     int bad = 0;
+    if (draw_mode == ORC_DRAW_PLAIN && net->B > 32) return -4;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 32) reduction(| : bad)
@@ -225,7 +230,7 @@ int orc_wm_run(const orc_net *net, uint64_t seed, uint32_t net_id,
         uint64_t i = first + (uint64_t)k, nreal = 0;
         for (uint64_t t = 0; t < K[k]; ++t) {
             uint64_t e = E0[k] + t;
-            uint32_t thr = draw_mode == ORC_DRAW_PLAIN
+            uint64_t thr = draw_mode == ORC_DRAW_PLAIN
                                ? draw_plain(seed, net_id, i, e, net->B)
                                : draw_mode == ORC_DRAW_SHARED
                                      ? orc_draw_shared(seed, net_id, e, net->z_shared)

@@ -72,7 +72,7 @@ def lib():
         L.orc_init_multinomial.argtypes = [u64, u32, u64, u64, i64, P(i32)]
         L.orc_philox.argtypes = [P(u32), u64, P(u32)]
         L.orc_max_threads.restype = ctypes.c_int
-        L.orc_select.argtypes = [P(_Net), P(i32), u32]
+        L.orc_select.argtypes = [P(_Net), P(i32), u64]
         L.orc_draw_shared.argtypes = [u64, u32, u64, u32]
         L.orc_draw_shared.restype = u32
         L.orc_select.restype = ctypes.c_int
@@ -126,6 +126,9 @@ def run_events(net, q, seed, net_id, first, counts, E0, K, draw=DRAW_EVENT,
                           _p(counts, ctypes.c_int32), _p(E0, ctypes.c_uint64),
                           _p(K, ctypes.c_uint64), _p(real, ctypes.c_uint64),
                           tp, traj_len, threads)
+    if rc == -4:
+        raise ValueError("the PLAIN draw is one 32-bit word: weights of %d planes need the "
+                         "EVENT draw" % q["B"])
     if rc != 0:
         raise AssertionError("oracle invariant violated (negative count, count above the "
                              "cap, or molecule count not conserved)")
@@ -262,6 +265,8 @@ def py_events(net, q, seed, net_id, replica, counts, E0, K, draw=DRAW_EVENT):
     nu = state_change(net)
     N = list(counts)
     picked = []
+    if draw == DRAW_PLAIN and q["B"] > 32:
+        raise ValueError("the PLAIN draw is one 32-bit word")
     for e in range(E0, E0 + K):
         if draw == DRAW_PLAIN:
             n = _ph.plain_threshold(seed, net_id, replica, e, q["B"])

@@ -157,3 +157,55 @@ def test_open_network_refuses_counts_above_the_cap(oracle_lib):
         ssa.OracleEnsemble(lotka_volterra(), 4).init(("fixed", (13, 0)))
     with pytest.raises(ValueError):
         quantize({**lotka_volterra(), "open": False})   # not count-conserving
+
+
+# ---- weights beyond 32 threshold planes (fixed-point rates at higher precision)
+
+def frank_fine(n_tot=10, k0=0.0137, bits=26):
+    """The Frank network with k1 = k2 = 1/N_tot quantised to 26 bits of
+    precision: c = (7.4e7, 7.4e7, 2^29, 2^29, 2^29), W = 2^35."""
+    from workloads import frank_network
+    net = frank_network(n_tot, k0=k0)
+    return net, quantize(net, precision_bits=bits)
+
+
+def test_wide_thresholds_follow_the_master_equation(oracle_lib):
+    # 35 threshold planes: every event draws 9 Philox quads per word and
+    # compares a 35-bit n; dropping the planes above 32 would make reactions
+    # 8 times likelier and fail both laws
+    net, q = frank_fine()
+    assert q["B"] == 35 and max(q["c"]) < (1 << 32)
+    start = (0, 0, 10)
+    E = ssa.OracleEnsemble(net, 16384, seed=31, net_id=7, q=q)
+    E.init(("fixed", start))
+    E.step(400)
+    st, probs = master.fixed_k_probs(net, q, start, 400)
+    assert chi2_pvalue(_empirical(E.counts, st), probs * 16384) > 1e-4
+    E = ssa.OracleEnsemble(net, 16384, seed=32, net_id=7, q=q)
+    E.init(("fixed", start))
+    E.advance(0.6)
+    st, probs = master.time_probs(net, q, {start: 1.0}, 0.6)
+    assert chi2_pvalue(_empirical(E.counts, st), probs * 16384) > 1e-4
+
+
+def test_wide_thresholds_c_oracle_matches_python_direct_method(oracle_lib):
+    net, q = frank_fine(12)
+    n = 16
+    counts = np.tile(np.array((2, 3, 7), np.int32), (n, 1))
+    E0 = np.arange(n, dtype=np.uint64) * 11
+    K = np.full(n, 120, dtype=np.uint64)
+    out, real, _ = ssa.run_events(net, q, 9, 5, 70, counts, E0, K)
+    nu = state_change(net)
+    for k in range(n):
+        N, picked = ssa.py_events(net, q, 9, 5, 70 + k, [2, 3, 7], int(E0[k]), 120)
+        assert list(out[k]) == N
+        assert int(real[k]) == sum(1 for r in picked if r >= 0 and any(nu[r]))
+
+
+def test_plain_draw_refuses_wide_thresholds(oracle_lib):
+    net, q = frank_fine()
+    with pytest.raises(ValueError):
+        ssa.run_events(net, q, 1, 1, 0, np.zeros((4, 3), np.int32) + [0, 0, 10],
+                       np.zeros(4, np.uint64), np.ones(4, np.uint64), draw=ssa.DRAW_PLAIN)
+    with pytest.raises(ValueError):
+        ssa.py_events(net, q, 1, 1, 0, [0, 0, 10], 0, 1, draw=ssa.DRAW_PLAIN)
