@@ -240,13 +240,20 @@ typedef struct {
 
 /* Validate and quantise a network (integer weights c_j, scale, bound 2^B).
  * The bound: for 3 species conserving the count, the largest total weight
- * over the simplex (enumerated); else sum_j c_j max h_j, each reaction's
+ * over the simplex (exactly: for each first count the total is an integer
+ * quadratic in the second, whose extremes lie at the ends and next to the
+ * vertex); else sum_j c_j max h_j, each reaction's
  * largest factor over the simplex of n_tot molecules (N_X: n_tot, pairs
  * floor(n/2) ceil(n/2), N_X (N_X - 1)/2: n(n-1)/2) or, open, over the box of
  * counts at most n_tot (n, n^2, n(n-1)/2).
  * EINVAL: order not in {1,2}, not count-conserving (and not open), negative
- * or non-finite rate, n_tot < 1, sizes out of range; ERANGE: weights or
- * bound beyond 32 threshold planes or n_tot beyond the count planes;
+ * or non-finite rate, n_tot < 1, sizes out of range; ERANGE: weights beyond
+ * 32 bits, a bound beyond 48 threshold planes, or n_tot beyond the count
+ * planes.  Beyond 32 threshold planes (rates quantised at more bits of
+ * precision, precision_bits) only the bit-sliced engine runs the network,
+ * on the kernels compiled for it at run time (state_bytes refuses the other
+ * engines, BWG_OPT_NO_JIT, explicit block sizes, other word widths and shared
+ * thresholds; batches refuse such ensembles);
  * EUNSUPPORTED: a lattice that is open or not of 3 species.  The returned
  * handle is owned by the caller (bwg_net_destroy). */
 int bwg_net_create(const bwg_net_desc *desc, bwg_net **out);

@@ -383,17 +383,17 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     if (n->wide) {
         if (!total_weight_bound(*n, &q.max_total)) {
             delete n;
-            return fail(BWG_ERANGE, "total weight beyond 32 threshold planes");
+            return fail(BWG_ERANGE, "total weight beyond %d threshold planes", kMaxThresholdPlanes);
         }
     } else {
         total_weight_range(*n, &min_total, &q.max_total);
     }
     int B = 1;
     while (B < 63 && (1ll << B) < q.max_total) ++B;
-    if (B > 32) {
+    if (B + (q.max_total == (1ll << B) ? 1 : 0) > kMaxThresholdPlanes) {
         delete n;
-        return fail(BWG_ERANGE, "total weight %lld needs %d threshold planes (max 32)",
-                    (long long)q.max_total, B);
+        return fail(BWG_ERANGE, "total weight %lld needs %d threshold planes (max %d)",
+                    (long long)q.max_total, B, kMaxThresholdPlanes);
     }
     q.B = B;
     int b = 1;
@@ -545,11 +545,22 @@ static const GenVariant *pick_gen_variant(const bwg_net *n)
 
 // Kernel of an engine for a network: the Frank-family kernel where it
 // applies (unless generic is asked for), else the general bit-sliced one.
+// Threshold planes the selection needs: B, or B + 1 when the largest total
+// weight is exactly 2^B.
+static int need_planes(const bwg_net *n)
+{
+    return n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
+}
+
+// The kernels an engine runs a network on.  Weights beyond 32 threshold
+// planes run only the bit-sliced kernels compiled for the network (jit:
+// run-time compiles allowed).
 static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
-                        const GenVariant **gv = nullptr, bool generic = false)
+                        const GenVariant **gv = nullptr, bool generic = false, bool jit = true)
 {
     *v = nullptr;
     if (gv) *gv = nullptr;
+    const bool wide_planes = need_planes(n) > 32;
     if (engine == BWG_ENGINE_BITWISE && n->wide) {
         // only the kernel compiled for the network (checked at creation)
         if (!n->wide_ok)
@@ -558,9 +569,12 @@ static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
         return BWG_OK;
     }
     if (engine == BWG_ENGINE_BITWISE && (generic || !n->shape_ok)) {
-        const GenVariant *g = pick_gen_variant(n);
-        if (!g)
-            return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for this network (b=%d B=%d)",
+        const GenVariant *g = wide_planes ? nullptr : pick_gen_variant(n);
+        if (!g && !(wide_planes && n->gen_ok && jit))
+            return fail(BWG_EUNSUPPORTED,
+                        wide_planes ? "weights beyond 32 threshold planes run the kernel compiled "
+                                      "for the network (not with BWG_OPT_NO_JIT)"
+                                    : "no bit-sliced kernel for this network (b=%d B=%d)",
                         n->q.b, n->q.B);
         if (gv) *gv = g;
         return BWG_OK;
@@ -570,9 +584,13 @@ static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
             return fail(BWG_EUNSUPPORTED,
                         "network is not of the Frank family the lanes engine implements");
         *v = pick_variant(n);
+        if (!*v && engine == BWG_ENGINE_BITWISE && wide_planes && jit && jit_frank_fits(n))
+            return BWG_OK;  // the Frank kernels compiled for the network only
         if (!*v)
-            return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for b=%d B=%d fa=%d fi=%d",
-                        n->q.b, n->q.B, n->shape.fa, n->shape.fi);
+            return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for b=%d B=%d fa=%d fi=%d%s",
+                        n->q.b, n->q.B, n->shape.fa, n->shape.fi,
+                        wide_planes ? " (beyond 32 threshold planes: the bit-sliced engine's "
+                                      "compiled kernels)" : "");
         // the lanes engine compares in 32-bit arithmetic: every cumulative
         // weight must stay below 2^32 (it does whenever a bucket holds the
         // planes; checked here for the record)
@@ -582,6 +600,9 @@ static int check_engine(const bwg_net *n, int engine, const WmVariant **v,
     }
     if (engine == BWG_ENGINE_PLAIN) {
         if (!n->plain_ok) return fail(BWG_EUNSUPPORTED, "network not supported by the plain engine");
+        if (n->q.B > 32)
+            return fail(BWG_EUNSUPPORTED, "the plain engine draws 32-bit thresholds (B = %d)",
+                        n->q.B);
         return BWG_OK;
     }
     return fail(BWG_EINVAL, "unknown engine %d", engine);
@@ -626,8 +647,12 @@ extern "C" int bwg_ensemble_state_bytes(const bwg_net *n, uint64_t M, const bwg_
         return lat_state_bytes(n, M, cap, bytes);
     }
     const WmVariant *v;
-    int rc = check_engine(n, engine, &v, nullptr, generic);
+    const bool jit = !(o && (o->flags & BWG_OPT_NO_JIT));
+    int rc = check_engine(n, engine, &v, nullptr, generic, jit);
     if (rc) return rc;
+    if (engine == BWG_ENGINE_BITWISE && !v && n->shape_ok && !generic && o && o->block > 0)
+        return fail(BWG_EUNSUPPORTED, "beyond 32 threshold planes the compiled kernels choose "
+                                      "their block size (block = 0)");
     *bytes = layout(n, M, engine, cap, v).total;
     return BWG_OK;
 }
@@ -674,11 +699,16 @@ int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint3
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
     if (n->lat) return lat_bind(e);
-    check_engine(n, e->engine, &e->var, &e->gvar, o && (o->flags & BWG_OPT_GENERIC_KERNEL));
+    const bool generic = o && (o->flags & BWG_OPT_GENERIC_KERNEL);
     const bool jit_ok = !(o && (o->flags & BWG_OPT_NO_JIT));
-    if (n->wide && e->engine == BWG_ENGINE_BITWISE && !jit_ok)
+    check_engine(n, e->engine, &e->var, &e->gvar, generic, jit_ok);
+    // networks on the general kernels: the precompiled one, else (other
+    // species counts, open networks, weights beyond 32 threshold planes)
+    // only the one compiled for the network
+    const bool gen_path = e->engine == BWG_ENGINE_BITWISE && (n->wide || generic || !n->shape_ok);
+    if (gen_path && !e->gvar && !jit_ok)
         return fail(BWG_EUNSUPPORTED, "this network runs only its compiled kernel (no BWG_OPT_NO_JIT)");
-    if ((e->gvar || (n->wide && e->engine == BWG_ENGINE_BITWISE)) && jit_ok) {
+    if (gen_path && jit_ok) {
         const int rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
         if (rc) return rc;
     }
@@ -686,9 +716,12 @@ int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint3
     // compiled kernel, built at its first launch of the bit-sliced engine
     // (batch members never launch alone and never build it); the
     // precompiled variant stays for the lanes engine and explicit block
-    // sizes
-    e->want_jit_frank = e->var && jit_ok && (e->var->fa < 0 || e->var->cu < 0) &&
-                        jit_frank_fits(n);
+    // sizes.  Beyond 32 threshold planes there is no precompiled variant:
+    // the compiled kernel is the only one.
+    e->want_jit_frank = e->var ? (jit_ok && (e->var->fa < 0 || e->var->cu < 0) &&
+                                  jit_frank_fits(n))
+                               : (e->engine == BWG_ENGINE_BITWISE && !gen_path && jit_ok &&
+                                  n->shape_ok && jit_frank_fits(n));
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
@@ -738,7 +771,7 @@ extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)
         const int rc = check_engine(e->net, BWG_ENGINE_LANES, &v);
         if (rc) return rc;
     }
-    if (engine == BWG_ENGINE_BITWISE && !e->var && !e->gvar) {
+    if (engine == BWG_ENGINE_BITWISE && !e->var && !e->gvar && !e->jit && !e->want_jit_frank) {
         e->var = pick_variant(e->net);
         if (!e->var) return fail(BWG_EUNSUPPORTED, "no bit-sliced kernel for this network");
     }
@@ -902,8 +935,10 @@ static int launch_events(bwg_ens *e, uint64_t max_events, hipStream_t s)
             HIP_TRY(jit_launch(e->jit, a, s));
         else if (e->gvar)
             HIP_TRY(e->gvar->fn(a, n->gen, s));
-        else
+        else if (e->var)
             HIP_TRY(e->var->fn(a, s, e->block, e->word_bits));
+        else
+            return fail(BWG_EUNSUPPORTED, "no kernel for this ensemble's engine and options");
         rc = mark_end(e, s, ev);
         if (rc) return rc;
     } else {

@@ -31,6 +31,10 @@ hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s);
 
 }  // namespace bwg
 
+// Threshold planes the compiled bit-sliced kernels take (the precompiled
+// ones and the lanes engine: 32).
+constexpr int kMaxThresholdPlanes = 48;
+
 struct Table {  // Poisson table of one mean
     int64_t k_lo;
     uint64_t len;

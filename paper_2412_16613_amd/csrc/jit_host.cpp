@@ -54,7 +54,10 @@ void jit_release(JitKernel *k)
 // 2^22 replicas; 128-thread blocks are placed unevenly there), as for the
 // precompiled Frank kernels
 constexpr int kJitBlockSmall = 128, kJitBlockLarge = 256;
-constexpr int kJitPcHalf = 4;   // events per ring half of the producer/consumer kernel
+// Events per ring half of the producer/consumer kernels: the ring holds
+// 2 x 2 x PH events of BC planes for 128 words (BC KiB per event pair), so
+// beyond 32 threshold planes it takes 2 to stay within the CU's LDS.
+static int jit_pc_half(int BC) { return BC > 32 ? 2 : 4; }
 
 // Source of network n's kernels with NB count planes and BC threshold planes:
 // an event functor (weight kinds kept from event to event, selection, state
@@ -168,7 +171,7 @@ static std::string jit_source(const bwg_net &n, int NB, int BC)
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
       << "{\n"
-      << "    constexpr int PH = " << kJitPcHalf << ";\n"
+      << "    constexpr int PH = " << jit_pc_half(BC) << ";\n"
       << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
       << "    __shared__ uint64_t wave_span[4];\n"
       << "    gen_word_pc<NB, BC, PH>(a, ring, wave_span, NetEvent{});\n"
@@ -313,7 +316,7 @@ static std::string jit_source_wide(const bwg_net &n, int NB, int BC)
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
       << "{\n"
-      << "    constexpr int PH = " << kJitPcHalf << ";\n"
+      << "    constexpr int PH = " << jit_pc_half(BC) << ";\n"
       << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
       << "    __shared__ uint64_t wave_span[4];\n"
       << "    gen_word_pc<NB, BC, PH, S>(a, ring, wave_span, NetEvent{});\n"
@@ -376,7 +379,9 @@ int jit_get(bwg_net *n, const JitKernel **out)
         return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
     const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
     const int NB = n->q.b, BC = (need_bc + 3) / 4 * 4;
-    if (BC > 32 || NB > 14) return fail(BWG_EUNSUPPORTED, "network beyond 14 count / 32 threshold planes");
+    if (BC > kMaxThresholdPlanes || NB > 14)
+        return fail(BWG_EUNSUPPORTED, "network beyond 14 count / %d threshold planes",
+                    kMaxThresholdPlanes);
     JitKernel *k = nullptr;
     const int rc =
         jit_compile(n->wide ? jit_source_wide(*n, NB, BC) : jit_source(*n, NB, BC), false, &k);
@@ -409,7 +414,7 @@ static std::string jit_frank_source(int NB, int BC, int FA, int FI, int CU, int 
       << "}\n"
       << "extern \"C\" __global__ __launch_bounds__(256) void bwg_jit_pc(WmArgs a)\n"
       << "{\n"
-      << "    constexpr int PH = BC == 20 ? 6 : 4;\n"
+      << "    constexpr int PH = BC > 32 ? 2 : (BC == 20 ? 6 : 4);\n"
       << "    __shared__ uint4 ring[2 * 2 * PH][BC / 4][64];\n"
       << "    __shared__ uint64_t wave_span[4];\n"
       << "    wm_word_pc<NB, BC, FA, CU, PH, FI, NT, BS>(a, ring, wave_span);\n"
@@ -434,7 +439,8 @@ static bool frank_params(const bwg_net &n, FrankParams *p)
     const int fa = n.shape.fa, fi = n.shape.fi;
     const int FA = fa >= 0 ? fa : (fi >= 0 ? fi : 0);
     const int FI = fi >= 0 ? fi : FA;
-    if (BC > 32 || NB > 14 || NB < 1 || FA >= BC || FI >= BC || n.shape.cu > 0x7FFFFFFFu)
+    if (BC > kMaxThresholdPlanes || NB > 14 || NB < 1 || FA >= BC || FI >= BC ||
+        n.shape.cu > 0x7FFFFFFFu)
         return false;
     if (n.n_tot < 1 || n.n_tot >= (1 << 14)) return false;
     // exact register widths need the molecule count and both bimolecular

@@ -244,7 +244,7 @@ __device__ __forceinline__ void init_weights(const uint32_t (&L)[NB], const uint
 #pragma unroll
     for (int q = 0; q < BC; ++q) U[q] = 0;
 #pragma unroll
-    for (int k = 0; k < BC; ++k) {
+    for (int k = 0; k < BC && k < 32; ++k) {  // cu has 32 bits; U may have more planes
         if ((cu >> k) & 1u) {
             uint32_t c = 0;
 #pragma unroll

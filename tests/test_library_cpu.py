@@ -210,6 +210,51 @@ def test_options_are_checked_before_any_device_work():
     assert rc(lat, flags=shared) == _abi.BWG_EUNSUPPORTED
 
 
+def test_weights_beyond_32_planes():
+    """Rates quantised at more bits of precision: up to 48 threshold planes,
+    the same quantisation as the oracle's; the bit-sliced engine takes them on
+    the kernels compiled for the network only, the other engines, the
+    precompiled kernels, explicit block sizes, other word widths and shared
+    thresholds refuse them (before any device work); beyond 48 planes the
+    network is refused."""
+    import ctypes
+    L = _abi.load()
+
+    def rc(net, **kw):
+        o = _abi.Opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        b = ctypes.c_uint64()
+        return L.bwg_ensemble_state_bytes(net.handle, 1000, ctypes.byref(o), ctypes.byref(b))
+
+    for n_tot, bits, B in ((10, 26, 35), (1024, 20, 36), (1024, 26, 42)):
+        net = frank_network(n_tot, k0=0.0137 if n_tot == 10 else 0.013)
+        q_orc = quantize(net, precision_bits=bits)
+        n = bwg.Network(net, precision_bits=bits)
+        q_lib = n.quantized()
+        assert q_orc["B"] == q_lib["B"] == B
+        for k in ("c", "f", "b", "s", "Lambda", "max_total"):
+            assert q_lib[k] == q_orc[k], k
+        assert q_lib["z_shared"] is None and q_lib["gpu_ok"]
+        assert rc(n) == _abi.BWG_OK
+        assert rc(n, engine=_abi.BWG_ENGINE_LANES) == _abi.BWG_EUNSUPPORTED
+        assert rc(n, engine=_abi.BWG_ENGINE_PLAIN) == _abi.BWG_EUNSUPPORTED
+        assert rc(n, flags=_abi.BWG_OPT_NO_JIT) == _abi.BWG_EUNSUPPORTED
+        assert rc(n, block=64) == _abi.BWG_EUNSUPPORTED
+        assert rc(n, word_bits=16) == _abi.BWG_EUNSUPPORTED
+        assert rc(n, flags=_abi.BWG_OPT_SHARED_THRESHOLD) == _abi.BWG_ERANGE
+    gen = random_network(0, 12, 5)
+    n = bwg.Network(gen, precision_bits=20)
+    assert n.quantized()["B"] == quantize(gen, precision_bits=20)["B"] == 33
+    assert rc(n) == _abi.BWG_OK
+    assert rc(n, flags=_abi.BWG_OPT_NO_JIT) == _abi.BWG_EUNSUPPORTED
+    big = frank_network(4096, k0=0.013)
+    assert bwg.Network(big, precision_bits=30).quantized()["B"] == 48   # the largest
+    with pytest.raises(bwg.BwgError) as e:
+        bwg.Network(big, precision_bits=31)
+    assert e.value.code == _abi.BWG_ERANGE and quantize(big, precision_bits=31)["B"] == 49
+
+
 # ---- lattices ----------------------------------------------------------------
 
 def _lat_cmp(net):
