@@ -5,19 +5,22 @@ t_end).  The server admits arrived requests in arrival order while their
 device state fits the HBM budget and a member slot is free; an admitted
 request gets its own device-resident ensemble and its event budgets for the
 whole horizon are drawn at once.  Well-mixed requests join the persistent
-batch: every pass runs at most `chunk` events per word of every resident
-request, so long chains yield to newly admitted requests between passes and
-their work overlaps in one launch.  Lattice requests run their own launches
-(at most `lattice_chunk` events of their component sequence per pass) on a
-second stream, beside the persistent launch.  A request completes when its
-pending-event bound reaches zero (a host-side bound: no device query); its
-histogram (and, if asked, its counts) and its event total are copied to
-pinned host memory behind its last pass, and HIP events mark the end of
-every pass on both streams.  The host does not wait for a pass it has just
-enqueued: it keeps up to `depth` passes in flight, admits arrivals and
-enqueues the next pass while the previous ones run, and retires a pass (its
-requests' latency, completion - arrival, recorded and their memory
-returned to the budget) once its events have completed.
+batch: every well-mixed pass runs at most `chunk` events per word of every
+resident request, so long chains yield to newly admitted requests between
+passes and their work overlaps in one launch.  Lattice requests run their
+own launches (at most `lattice_chunk` events of their component sequence per
+lattice pass), spread round-robin over `lattice_streams` streams beside the
+persistent launch: a small lattice ensemble's advance is bound by its own
+layer-after-layer latency, so several run at once.  The two kinds of pass
+are queued independently (up to `depth` of each in flight), so neither
+waits for the other.  A request completes when its pending-event bound
+reaches zero (a host-side bound: no device query); its histogram (and, if
+asked, its counts) and its event total are copied to pinned host memory
+behind its last pass, and a HIP event marks the end of every pass on each of
+its streams.  The host does not wait for a pass it has just enqueued: it
+admits arrivals and enqueues the next passes while earlier ones run, and
+retires a pass (its requests' latency, completion - arrival, recorded and
+their memory returned to the budget) once its events have completed.
 
 Results do not depend on the mix: every draw is keyed by (seed, net id,
 replica, event), so a request served among others gives bit for bit the
@@ -35,7 +38,8 @@ import paper_2412_16613_amd as bwg
 class Server:
     def __init__(self, hbm_budget=64 << 30, chunk=4096, max_members=1024,
                  max_items=1 << 19, waves=2048, n_bins=256, keep_counts=False,
-                 lattice_chunk=1 << 17, depth=2, lanes_events=0, device="cuda"):
+                 lattice_chunk=1 << 17, depth=2, lanes_events=0, lattice_streams=3,
+                 device="cuda"):
         import torch
         self.torch = torch
         # well-mixed requests expecting at least this many events per replica
@@ -47,7 +51,8 @@ class Server:
         self.lanes_events = float(lanes_events)
         self.device = torch.device(device)
         self.lattice_chunk = int(lattice_chunk)
-        self.side = None
+        self.lattice_streams = max(1, int(lattice_streams))
+        self.sides = None
         self.hbm_budget = int(hbm_budget)
         self.chunk = int(chunk)
         self.max_members = int(max_members)
@@ -82,34 +87,36 @@ class Server:
         """Serve requests (dicts with arrival, net, replicas, seed, net_id,
         init, t_end); returns one result dict per completed request.  With
         real_time=False the clock is simulated: it advances by pass_time per
-        pass (deterministic interleaving, for tests).  progress, if given, is
-        called with a status string about every progress_every seconds of
-        wall time."""
+        loop that enqueues passes (deterministic interleaving, for tests).
+        progress, if given, is called with a status string about every
+        progress_every seconds of wall time."""
         torch = self.torch
         reqs = sorted(requests, key=lambda r: r["arrival"])
         incoming = collections.deque(reqs)
         waiting = collections.deque()
-        active = []           # dicts: req, ens, bytes, items, lattice, admitted
+        active = []           # dicts: req, ens, bytes, items, lattice, stream, admitted
         used_bytes = 0
         used_items = 0
         results = []
-        stats = dict(passes=0, max_active=0, replica_events=0)
+        stats = dict(passes=0, lattice_passes=0, max_active=0, replica_events=0)
         if self.batch is None:
             self.batch = bwg.Batch([], waves=self.waves, max_ensembles=self.max_members,
                                    max_items=self.max_items, device=self.device)
-        if self.side is None:
-            self.side = torch.cuda.Stream(self.device)
+        if self.sides is None:
+            self.sides = [torch.cuda.Stream(self.device) for _ in range(self.lattice_streams)]
         main = torch.cuda.current_stream(self.device)
-
-        def well_mixed(act):
-            return [a["ens"] for a in act if not a["lattice"]]
+        next_side = 0
 
         def to_host(t):
             h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
             h.copy_(t, non_blocking=True)
             return h
 
-        inflight = collections.deque()   # passes: events on both streams, requests finished
+        # passes in flight: well-mixed ones on the main stream, lattice ones
+        # on the side streams; each entry: events, requests finished, order
+        wm_inflight = collections.deque()
+        lat_inflight = collections.deque()
+        order = 0
         t0 = time.perf_counter()
         clock = (lambda: time.perf_counter() - t0) if real_time else None
         sim_now = 0.0
@@ -130,19 +137,30 @@ class Server:
                 used_bytes -= a["bytes"]
                 used_items -= a["items"]
 
+        def readouts(done):
+            for a in done:
+                with torch.cuda.stream(a["stream"]):
+                    a["hist_host"] = to_host(a["ens"].histogram(self.n_bins))
+                    a["events_host"] = to_host(a["ens"].read_events()[0].sum().view(1))
+                    if self.keep_counts:
+                        a["counts_host"] = to_host(a["ens"].read_counts())
+
+        def ready(p):
+            return all(ev.query() for ev in p["ev"])
+
+        wm_changed = True     # the batch may still list an earlier call's members
         next_report = progress_every
-        while incoming or waiting or active or inflight:
+        while incoming or waiting or active or wm_inflight or lat_inflight:
             if progress is not None and time.perf_counter() - t0 >= next_report:
                 next_report += progress_every
                 progress("t=%.0fs: %d done, %d active, %d waiting, %d not yet arrived, %d passes"
                          % (time.perf_counter() - t0, len(results), len(active), len(waiting),
-                            len(incoming), stats["passes"]))
+                            len(incoming), stats["passes"] + stats["lattice_passes"]))
             now = clock() if real_time else sim_now
             if max_seconds is not None and now > max_seconds:
                 break
             while incoming and incoming[0]["arrival"] <= now:
                 waiting.append(incoming.popleft())
-            changed = False
             while waiting and len(active) < self.max_members:
                 r = waiting[0]
                 net = self._network(r["net"])
@@ -153,67 +171,91 @@ class Server:
                                    device=self.device, engine="lanes" if lanes else "bitwise")
                 nbytes = ens.state_bytes
                 items = 0 if lattice else self._items(r["replicas"], lanes)
-                if (active or inflight) and (used_bytes + nbytes > self.hbm_budget
-                                             or used_items + items > self.max_items):
+                busy = active or wm_inflight or lat_inflight
+                if busy and (used_bytes + nbytes > self.hbm_budget
+                             or used_items + items > self.max_items):
                     del ens
                     break
                 waiting.popleft()
-                # lattice ensembles live on the side stream from their first call
-                with torch.cuda.stream(self.side if lattice else main):
+                # a lattice ensemble lives on its side stream from its first call
+                stream = main
+                if lattice:
+                    stream = self.sides[next_side % len(self.sides)]
+                    next_side += 1
+                with torch.cuda.stream(stream):
                     ens.init(r["init"])
                     ens.schedule(r["t_end"])
                 active.append(dict(req=r, ens=ens, bytes=nbytes, items=items, lattice=lattice,
-                                   admitted=clock() if real_time else now))
+                                   stream=stream, admitted=clock() if real_time else now))
                 used_bytes += nbytes
                 used_items += items
-                changed = True
-            if active:
-                stats["max_active"] = max(stats["max_active"], len(active))
-                if changed:
-                    self.batch.set_members(well_mixed(active))
-                if any(not a["lattice"] for a in active):
-                    self.batch.run(self.chunk)
-                with torch.cuda.stream(self.side):
-                    for a in active:
-                        if a["lattice"]:
-                            a["ens"].run(self.lattice_chunk)
+                wm_changed = wm_changed or not lattice
+            stats["max_active"] = max(stats["max_active"], len(active))
+            enqueued = False
+            wm = [a for a in active if not a["lattice"]]
+            lat = [a for a in active if a["lattice"]]
+            if wm and len(wm_inflight) < self.depth:
+                if wm_changed:
+                    self.batch.set_members([a["ens"] for a in wm])
+                self.batch.run(self.chunk)
+                done = [a for a in wm if a["ens"].pending() == 0]
+                readouts(done)
+                ev = torch.cuda.Event()
+                ev.record(main)
+                wm_inflight.append(dict(ev=[ev], done=done, order=order))
+                order += 1
                 stats["passes"] += 1
-                if not real_time:
-                    sim_now += pass_time
-                # requests whose last events this pass ran: readouts behind it
-                done = [a for a in active if a["ens"].pending() == 0]
-                for a in done:
-                    with torch.cuda.stream(self.side if a["lattice"] else main):
-                        a["hist_host"] = to_host(a["ens"].histogram(self.n_bins))
-                        a["events_host"] = to_host(a["ens"].read_events()[0].sum().view(1))
-                        if self.keep_counts:
-                            a["counts_host"] = to_host(a["ens"].read_counts())
-                ev = (torch.cuda.Event(), torch.cuda.Event())
-                ev[0].record(main)
-                ev[1].record(self.side)
-                inflight.append(dict(ev=ev, done=done, sim_done=sim_now))
+                enqueued = True
+                wm_changed = False
                 if done:
-                    active = [a for a in active if a["ens"].pending() != 0]
-                    self.batch.set_members(well_mixed(active))
-            elif not inflight and incoming:
-                if real_time:
-                    time.sleep(max(0.0, incoming[0]["arrival"] - clock()))
-                else:
-                    sim_now = incoming[0]["arrival"]
-                continue
-            # retire finished passes; wait for the oldest once depth passes are
-            # in flight, or when nothing new can be enqueued
-            while inflight:
-                p = inflight[0]
-                ready = p["ev"][0].query() and p["ev"][1].query()
-                if not ready and (len(inflight) >= self.depth or not active):
-                    p["ev"][0].synchronize()
-                    p["ev"][1].synchronize()
-                    ready = True
-                if not ready:
-                    break
-                inflight.popleft()
-                retire(p)
+                    # out of the batch before their ensembles can be freed
+                    active = [a for a in active if a["lattice"] or a["ens"].pending() != 0]
+                    self.batch.set_members([a["ens"] for a in active if not a["lattice"]])
+            if lat and len(lat_inflight) < self.depth:
+                streams = []
+                for a in lat:
+                    with torch.cuda.stream(a["stream"]):
+                        a["ens"].run(self.lattice_chunk)
+                    if a["stream"] not in streams:
+                        streams.append(a["stream"])
+                done = [a for a in lat if a["ens"].pending() == 0]
+                readouts(done)
+                evs = []
+                for st in streams:
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                    evs.append(ev)
+                lat_inflight.append(dict(ev=evs, done=done, order=order))
+                order += 1
+                stats["lattice_passes"] += 1
+                enqueued = True
+                if done:
+                    active = [a for a in active if not a["lattice"] or a["ens"].pending() != 0]
+            if enqueued and not real_time:
+                sim_now += pass_time
+            for q in (wm_inflight, lat_inflight):
+                for p in q:
+                    p.setdefault("sim_done", sim_now)
+            if not enqueued and not wm_inflight and not lat_inflight:
+                if incoming and not waiting and not active:
+                    if real_time:
+                        time.sleep(max(0.0, incoming[0]["arrival"] - clock()))
+                    else:
+                        sim_now = incoming[0]["arrival"]
+                    continue
+            # retire finished passes; when nothing could be enqueued, wait for
+            # the oldest pass in flight
+            retired = False
+            for q in (wm_inflight, lat_inflight):
+                while q and ready(q[0]):
+                    retire(q.popleft())
+                    retired = True
+            if not enqueued and not retired and (wm_inflight or lat_inflight):
+                heads = [q for q in (wm_inflight, lat_inflight) if q]
+                q = min(heads, key=lambda d: d[0]["order"])
+                for ev in q[0]["ev"]:
+                    ev.synchronize()
+                retire(q.popleft())
         stats["wall_s"] = (time.perf_counter() - t0)
         self.stats = stats
         return results
@@ -226,5 +268,6 @@ def summarize(results, stats):
                 p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else None,
                 mean_latency_s=float(lat.mean()) if len(lat) else None,
                 replica_events_per_s=stats["replica_events"] / stats["wall_s"],
-                passes=stats["passes"], max_active=stats["max_active"],
+                passes=stats["passes"], lattice_passes=stats.get("lattice_passes", 0),
+                max_active=stats["max_active"],
                 wall_s=stats["wall_s"])
