@@ -76,7 +76,7 @@ HBM_PEAK = 8.0e12               # bytes/s, MI355X HBM3E
 # kernel -> (sha1 prefix of its sources, sources, bytes per launch, summary file).
 CSRC = os.path.join(ROOT, "paper_2412_16613_amd", "csrc")
 MEASURED_TRAFFIC = {
-    "wm_pc_kernel": ("a84d8d59a6bb", ("bitops.h", "wm_device.h", "wm_event_body.inc",
+    "wm_pc_kernel": ("56dc664d5d4c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
                      (2 * 10822 + 12672) * 1024, "profiles/wm_pc_kernel_frank1024_2p20.md"),
     "lat_event_kernel": ("96ce50d96af1", ("bitops.h", "lattice.hip"),
@@ -88,7 +88,7 @@ MEASURED_TRAFFIC = {
 # VALU wave instructions per launch (rocprofv3 SQ_INSTS_VALU), valid for the same sources:
 # kernel -> (sha1 prefix, sources, instructions per launch, summary file).
 MEASURED_VALU = {
-    "wm_pc_kernel": ("a84d8d59a6bb", ("bitops.h", "wm_device.h", "wm_event_body.inc",
+    "wm_pc_kernel": ("56dc664d5d4c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
                      20831937027, "profiles/wm_pc_kernel_frank1024_2p20.md"),
 }

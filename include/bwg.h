@@ -267,6 +267,21 @@ int bwg_net_quantized(const bwg_net *net, bwg_qnet *out);
 int bwg_net_lattice(const bwg_net *net, bwg_lattice_info *out);
 void bwg_net_destroy(bwg_net *net);
 
+/* Compile now, on the host and without touching a device, the kernels that
+ * a bit-sliced ensemble of this network under default options would compile
+ * at run time (hipRTC, gfx950): the general kernel for networks outside the
+ * Frank family, open networks and other species counts; the Frank-family
+ * kernel with the network's weights as constants where no precompiled
+ * variant has them.  Ensembles created later only load the code (done once
+ * per network).  *built (may be NULL) gets BWG_JIT_GENERAL | BWG_JIT_FRANK
+ * for the kernels this network uses, 0 when it runs precompiled kernels
+ * only or is a lattice.  EUNSUPPORTED if no bit-sliced kernel runs the
+ * network; EDEVICE with the compiler's log if a compile fails.  Thread-safe
+ * per network. */
+#define BWG_JIT_GENERAL 1u
+#define BWG_JIT_FRANK 2u
+int bwg_net_compile(bwg_net *net, uint32_t *built);
+
 /* Poisson inverse-CDF table of the event budget for mean mu (host):
  * table[j] = floor(2^64 P(K <= k_lo + j)), j < len, ending at the first
  * entry equal to 2^64-1.  ERANGE if cap entries do not suffice (len then

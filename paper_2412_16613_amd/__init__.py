@@ -77,6 +77,15 @@ class Network:
                     Lambda=q.lambda_, max_total=q.max_total, gpu_ok=bool(q.gpu_ok),
                     z_shared=q.z_shared or None)
 
+    def compile(self):
+        """Compile on the host now the run-time kernels a bit-sliced ensemble
+        of this network would compile on its first use (bwg_net_compile);
+        returns the set of kernels it uses, of "general" and "frank"."""
+        built = ctypes.c_uint32()
+        _abi.check(_lib().bwg_net_compile(self.handle, ctypes.byref(built)))
+        return ({"general"} if built.value & _abi.BWG_JIT_GENERAL else set()) | \
+            ({"frank"} if built.value & _abi.BWG_JIT_FRANK else set())
+
     def lattice(self):
         """Integer form of a lattice network (bwg_net_lattice)."""
         i = _abi.LatticeInfo()
@@ -264,7 +273,13 @@ class Ensemble:
         t = self.torch
         grid = [float(x) for x in t_grid]
         arr = (ctypes.c_double * max(len(grid), 1))(*grid)
-        sel = t.tensor(list(replicas), dtype=t.int32, device=self.device)
+        # uint32 indices, carried in an int32 tensor (indices of 2^31 and up
+        # wrap to negative values and keep their bits)
+        idx = [int(r) for r in replicas]
+        if any(r < 0 or r >= 1 << 32 for r in idx):
+            raise ValueError("replica indices are uint32")
+        sel = t.tensor([r - (1 << 32) if r >= 1 << 31 else r for r in idx], dtype=t.int32,
+                       device=self.device)
         out = t.empty((len(grid), len(sel), 3), dtype=t.int32, device=self.device)
         fp = None
         if threshold is not None:

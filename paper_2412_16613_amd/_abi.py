@@ -32,6 +32,8 @@ BWG_OPT_GENERIC_KERNEL = 4
 BWG_OPT_NO_JIT = 8
 BWG_OPT_NO_LDS_STAGE = 16
 BWG_LAT_STAGE_SITES = 840
+BWG_JIT_GENERAL = 1
+BWG_JIT_FRANK = 2
 
 # Every symbol include/bwg.h declares.
 SYMBOLS = (
@@ -46,6 +48,7 @@ SYMBOLS = (
     "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
     "bwg_ensemble_kernel_time", "bwg_ensemble_set_engine", "bwg_ensemble_set_lanes_words",
     "bwg_ensemble_record", "bwg_ensemble_prepare", "bwg_ensemble_step_static",
+    "bwg_net_compile",
 )
 BWG_STATIC_STATE_BYTES = 64 << 20
 
@@ -119,6 +122,7 @@ def load():
         "bwg_net_create": (i32, [P(NetDesc), P(vp)]),
         "bwg_net_quantized": (i32, [vp, P(QNet)]),
         "bwg_net_destroy": (None, [vp]),
+        "bwg_net_compile": (i32, [vp, P(u32)]),
         "bwg_poisson_table": (i32, [ctypes.c_double, P(i64), P(u64), u64, P(u64)]),
         "bwg_ensemble_state_bytes": (i32, [vp, u64, P(Opts), P(u64)]),
         "bwg_ensemble_create": (i32, [vp, u64, u64, u32, vp, u64, P(Opts), P(vp)]),

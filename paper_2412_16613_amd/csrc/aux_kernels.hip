@@ -52,10 +52,10 @@ __device__ __forceinline__ void multinomial_counts(uint64_t i, int64_t n_tot, ui
 
 __global__ void init_multinomial_kernel(uint32_t *planes, int nb, uint64_t wp, uint64_t M,
                                         int64_t n_tot, uint64_t seed, uint32_t net_id,
-                                        uint64_t *E, uint64_t *Et, uint64_t *real)
+                                        uint64_t *E, uint64_t *Et, uint64_t *real, uint64_t i0)
 {
-    // blockDim is a multiple of 64 and the grid covers 32*wp replicas exactly
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // blockDim is a multiple of 64 and the pieces cover 32*wp replicas exactly
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = i < M;
     int32_t c[3] = {0, 0, 0};
     if (ok) multinomial_counts(i, n_tot, seed, net_id, c[0], c[1], c[2]);
@@ -101,9 +101,9 @@ __device__ __forceinline__ uint64_t draw_budget(const uint64_t *T, uint64_t len,
 __global__ void budget_kernel(const uint64_t *T, uint64_t len, int64_t k_lo, uint64_t fixed_k,
                               int use_table, uint64_t seed, uint32_t net_id,
                               const uint64_t *adv_dev, uint64_t M, const uint64_t *E,
-                              uint64_t *Et)
+                              uint64_t *Et, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     uint64_t K = fixed_k;
     if (use_table) K = draw_budget(T, len, k_lo, seed, net_id, *adv_dev, i);
@@ -127,25 +127,26 @@ __device__ __forceinline__ int32_t plane_count(const uint32_t *planes, int x, in
 }
 
 __global__ void read_counts_planes_kernel(const uint32_t *planes, int S, int nb, uint64_t wp,
-                                          uint64_t M, int32_t *dst)
+                                          uint64_t M, int32_t *dst, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     const uint64_t w = i >> 5;
     const int lane = (int)(i & 31);
     for (int x = 0; x < S; ++x) dst[S * i + x] = plane_count(planes, x, nb, wp, w, lane);
 }
 
-__global__ void read_counts_plain_kernel(const int32_t *counts, uint64_t M, int32_t *dst)
+__global__ void read_counts_plain_kernel(const int32_t *counts, uint64_t M, int32_t *dst,
+                                         uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 3 * M) return;
     dst[i] = counts[i];
 }
 
-__global__ void fill_u64_kernel(uint64_t *dst, uint64_t n, uint64_t v)
+__global__ void fill_u64_kernel(uint64_t *dst, uint64_t n, uint64_t v, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = v;
 }
 
@@ -153,12 +154,12 @@ __global__ void fill_u64_kernel(uint64_t *dst, uint64_t n, uint64_t v)
 // histogram in LDS, then one global atomic per non-empty bin.
 __global__ void histogram_kernel(const uint32_t *planes, const int32_t *counts, int nb,
                                  uint64_t wp, uint64_t M, int64_t n_tot, int n_bins,
-                                 uint64_t *dst)
+                                 uint64_t *dst, uint64_t i0)
 {
     extern __shared__ uint32_t hist[];
     for (int b = threadIdx.x; b < n_bins; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < M) {
         int32_t nl, nd;
         if (planes) {
@@ -184,9 +185,9 @@ __global__ void histogram_kernel(const uint32_t *planes, const int32_t *counts, 
 // M gives -1 for every species.
 __global__ void gather_counts_kernel(const uint32_t *planes, const int32_t *counts, int nb,
                                      uint64_t wp, uint64_t M, const uint32_t *sel, uint32_t n_sel,
-                                     int32_t *dst)
+                                     int32_t *dst, uint64_t i0)
 {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t j = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_sel) return;
     const uint64_t i = sel[j];
     for (int x = 0; x < 3; ++x) {
@@ -201,9 +202,9 @@ __global__ void gather_counts_kernel(const uint32_t *planes, const int32_t *coun
 // |N_L - N_D| has reached the threshold.
 __global__ void first_passage_kernel(const uint32_t *planes, const int32_t *counts, int nb,
                                      uint64_t wp, uint64_t M, int32_t threshold, uint32_t k,
-                                     uint32_t *first)
+                                     uint32_t *first, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M || first[i] != 0xFFFFFFFFu) return;
     int32_t nl, nd;
     if (planes) {
@@ -217,9 +218,9 @@ __global__ void first_passage_kernel(const uint32_t *planes, const int32_t *coun
     if ((d < 0 ? -d : d) >= threshold) first[i] = k;
 }
 
-__global__ void copy_u64_kernel(const uint64_t *src, uint64_t *dst, uint64_t n)
+__global__ void copy_u64_kernel(const uint64_t *src, uint64_t *dst, uint64_t n, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
 
@@ -262,18 +263,20 @@ hipError_t launch_init_multinomial(uint32_t *planes, int nb, uint64_t wp, uint64
                                    uint64_t *Et, uint64_t *real, hipStream_t s)
 {
     // 32*wp is a multiple of 128 (wp is padded to 64 words)
-    hipLaunchKernelGGL(init_multinomial_kernel, grid_for(32 * wp, 128), dim3(128), 0, s,
-                       planes, nb, wp, M, n_tot, seed, net_id, E, Et, real);
-    return hipGetLastError();
+    return launch_pieces(32 * wp, 128, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(init_multinomial_kernel, g, dim3(128), 0, s, planes, nb, wp, M, n_tot,
+                           seed, net_id, E, Et, real, i0);
+    });
 }
 
 hipError_t launch_budget(const uint64_t *T, uint64_t len, int64_t k_lo, uint64_t fixed_k,
                          int use_table, uint64_t seed, uint32_t net_id, const uint64_t *adv_dev,
                          uint64_t M, const uint64_t *E, uint64_t *Et, hipStream_t s)
 {
-    hipLaunchKernelGGL(budget_kernel, grid_for(M, 256), dim3(256), 0, s, T, len, k_lo,
-                       fixed_k, use_table, seed, net_id, adv_dev, M, E, Et);
-    return hipGetLastError();
+    return launch_pieces(M, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(budget_kernel, g, dim3(256), 0, s, T, len, k_lo, fixed_k, use_table,
+                           seed, net_id, adv_dev, M, E, Et, i0);
+    });
 }
 
 hipError_t launch_add_u64(uint64_t *p, uint64_t v, hipStream_t s)
@@ -284,65 +287,65 @@ hipError_t launch_add_u64(uint64_t *p, uint64_t v, hipStream_t s)
 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_u64_kernel, grid_for(n, 256), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
+    return launch_pieces(n, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(fill_u64_kernel, g, dim3(256), 0, s, p, n, v, i0);
+    });
 }
 
 hipError_t launch_read_counts_planes(const uint32_t *planes, int S, int nb, uint64_t wp,
                                      uint64_t M, int32_t *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(read_counts_planes_kernel, grid_for(M, 256), dim3(256), 0, s, planes, S,
-                       nb, wp, M, dst);
-    return hipGetLastError();
+    return launch_pieces(M, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(read_counts_planes_kernel, g, dim3(256), 0, s, planes, S, nb, wp, M,
+                           dst, i0);
+    });
 }
 
 hipError_t launch_read_counts_plain(const int32_t *counts, uint64_t M, int32_t *dst,
                                     hipStream_t s)
 {
-    hipLaunchKernelGGL(read_counts_plain_kernel, grid_for(3 * M, 256), dim3(256), 0, s,
-                       counts, M, dst);
-    return hipGetLastError();
+    return launch_pieces(3 * M, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(read_counts_plain_kernel, g, dim3(256), 0, s, counts, M, dst, i0);
+    });
 }
 
 hipError_t launch_histogram(const uint32_t *planes, const int32_t *counts, int nb, uint64_t wp,
                             uint64_t M, int64_t n_tot, int n_bins, uint64_t *dst,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(fill_u64_kernel, grid_for((uint64_t)n_bins, 256), dim3(256), 0, s, dst,
-                       (uint64_t)n_bins, 0ull);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = launch_fill_u64(dst, (uint64_t)n_bins, 0ull, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(histogram_kernel, grid_for(M, 256), dim3(256),
-                       (size_t)n_bins * sizeof(uint32_t), s, planes, counts, nb, wp, M, n_tot,
-                       n_bins, dst);
-    return hipGetLastError();
+    return launch_pieces(M, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(histogram_kernel, g, dim3(256), (size_t)n_bins * sizeof(uint32_t), s,
+                           planes, counts, nb, wp, M, n_tot, n_bins, dst, i0);
+    });
 }
 
 hipError_t launch_gather_counts(const uint32_t *planes, const int32_t *counts, int nb,
                                 uint64_t wp, uint64_t M, const uint32_t *sel, uint32_t n_sel,
                                 int32_t *dst, hipStream_t s)
 {
-    if (n_sel == 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_counts_kernel, grid_for(n_sel, 256), dim3(256), 0, s, planes,
-                       counts, nb, wp, M, sel, n_sel, dst);
-    return hipGetLastError();
+    return launch_pieces(n_sel, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(gather_counts_kernel, g, dim3(256), 0, s, planes, counts, nb, wp, M,
+                           sel, n_sel, dst, i0);
+    });
 }
 
 hipError_t launch_first_passage(const uint32_t *planes, const int32_t *counts, int nb,
                                 uint64_t wp, uint64_t M, int32_t threshold, uint32_t k,
                                 uint32_t *first, hipStream_t s)
 {
-    hipLaunchKernelGGL(first_passage_kernel, grid_for(M, 256), dim3(256), 0, s, planes, counts,
-                       nb, wp, M, threshold, k, first);
-    return hipGetLastError();
+    return launch_pieces(M, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(first_passage_kernel, g, dim3(256), 0, s, planes, counts, nb, wp, M,
+                           threshold, k, first, i0);
+    });
 }
 
 hipError_t launch_copy_u64(const uint64_t *src, uint64_t *dst, uint64_t n, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(copy_u64_kernel, grid_for(n, 256), dim3(256), 0, s, src, dst, n);
-    return hipGetLastError();
+    return launch_pieces(n, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(copy_u64_kernel, g, dim3(256), 0, s, src, dst, n, i0);
+    });
 }
 
 hipError_t launch_sum_u64(const uint64_t *src, uint64_t n, uint64_t *dst, int slot,

@@ -124,9 +124,9 @@ __global__ __launch_bounds__(64, 2) void wm_persistent_kernel(const BatchEns *en
 
 // Budgets of every ensemble of a batch in one launch: thread g belongs to
 // the ensemble whose replica range [offset, offset + M) holds it.
-__global__ void batch_budget_kernel(const BatchBudget *bb, int n_ens, uint64_t total)
+__global__ void batch_budget_kernel(const BatchBudget *bb, int n_ens, uint64_t total, uint64_t g0)
 {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t g = g0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     int lo = 0, hi = n_ens - 1;
     while (lo < hi) {
@@ -184,10 +184,9 @@ hipError_t launch_persistent(const BatchEns *ens, const BatchItem *items, uint32
 
 hipError_t launch_batch_budget(const BatchBudget *bb, int n_ens, uint64_t total, hipStream_t s)
 {
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_budget_kernel, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0,
-                       s, bb, n_ens, total);
-    return hipGetLastError();
+    return launch_pieces(total, 256, [&](uint64_t g0, dim3 g) {
+        hipLaunchKernelGGL(batch_budget_kernel, g, dim3(256), 0, s, bb, n_ens, total, g0);
+    });
 }
 
 hipError_t launch_batch_prologue(uint32_t *counter, hipStream_t s)

@@ -16,6 +16,30 @@ enum : uint32_t {
     DOM_SHARED = 6,
 };
 
+// A dispatch covers fewer than 2^32 work-items (the dispatch packet counts
+// them in 32 bits), so a launch with one work-item per replica (up to
+// 2^32 - 1 of them, three per replica for plain-count copies) goes out in
+// pieces of kLaunchSpan items, each kernel taking the first index of its
+// piece.  Launches over words (at most 2^27) and lattice launches (whose
+// schedule memory bounds the replicas far below 2^32) fit in one dispatch.
+constexpr uint64_t kLaunchSpan = 1ull << 31;
+
+#ifndef __HIPCC_RTC__   // host launch code: not part of the run-time compiled kernels
+// f(i0, grid) once per piece [i0, i0 + kLaunchSpan) of [0, n); nothing for
+// n = 0.
+template <class F>
+inline hipError_t launch_pieces(uint64_t n, uint32_t block, F &&f)
+{
+    for (uint64_t i0 = 0; i0 < n; i0 += kLaunchSpan) {
+        const uint64_t len = n - i0 < kLaunchSpan ? n - i0 : kLaunchSpan;
+        f(i0, dim3((uint32_t)((len + block - 1) / block)));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+#endif
+
 // Frank-family structure recognised for the bit-sliced kernel: the reaction
 // table, after dropping trailing ghost reactions, is a subsequence of
 //   A -> L, A -> D, A + L -> 2L, A + D -> 2D, L + D -> 2A

@@ -552,6 +552,31 @@ static int need_planes(const bwg_net *n)
     return n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
 }
 
+// Networks on the general kernels: the precompiled one, else (other species
+// counts, open networks, weights beyond 32 threshold planes) only the one
+// compiled for the network.
+static bool gen_path(const bwg_net *n, int engine, bool generic)
+{
+    return engine == BWG_ENGINE_BITWISE && (n->wide || generic || !n->shape_ok);
+}
+
+// The kernels compiled at run time that an ensemble of n on engine runs,
+// given the precompiled variant var: the general one (gen) on the general
+// path, and the Frank-family one (frank) for a Frank-family network on a
+// run-time weight variant, or on none beyond 32 threshold planes.  The
+// Frank one is built at the first launch of the bit-sliced engine (batch
+// members never launch alone and never build it); the precompiled variant
+// stays for the lanes engine and explicit block sizes.
+static void jit_plan(const bwg_net *n, int engine, const WmVariant *var, bool generic,
+                     bool jit_ok, bool *gen, bool *frank)
+{
+    const bool gp = gen_path(n, engine, generic);
+    *gen = gp && jit_ok;
+    *frank = var ? (jit_ok && (var->fa < 0 || var->cu < 0) && jit_frank_fits(n))
+                 : (engine == BWG_ENGINE_BITWISE && !gp && jit_ok && n->shape_ok &&
+                    jit_frank_fits(n));
+}
+
 // The kernels an engine runs a network on.  Weights beyond 32 threshold
 // planes run only the bit-sliced kernels compiled for the network (jit:
 // run-time compiles allowed).
@@ -702,26 +727,14 @@ int bwg::ens_bind(bwg_ens *e, const bwg_net *n, uint64_t M, uint64_t seed, uint3
     const bool generic = o && (o->flags & BWG_OPT_GENERIC_KERNEL);
     const bool jit_ok = !(o && (o->flags & BWG_OPT_NO_JIT));
     check_engine(n, e->engine, &e->var, &e->gvar, generic, jit_ok);
-    // networks on the general kernels: the precompiled one, else (other
-    // species counts, open networks, weights beyond 32 threshold planes)
-    // only the one compiled for the network
-    const bool gen_path = e->engine == BWG_ENGINE_BITWISE && (n->wide || generic || !n->shape_ok);
-    if (gen_path && !e->gvar && !jit_ok)
+    if (gen_path(n, e->engine, generic) && !e->gvar && !jit_ok)
         return fail(BWG_EUNSUPPORTED, "this network runs only its compiled kernel (no BWG_OPT_NO_JIT)");
-    if (gen_path && jit_ok) {
+    bool want_gen = false;
+    jit_plan(n, e->engine, e->var, generic, jit_ok, &want_gen, &e->want_jit_frank);
+    if (want_gen) {
         const int rc = jit_get(const_cast<bwg_net *>(n), &e->jit);
         if (rc) return rc;
     }
-    // a Frank-family network on a run-time weight variant gets its own
-    // compiled kernel, built at its first launch of the bit-sliced engine
-    // (batch members never launch alone and never build it); the
-    // precompiled variant stays for the lanes engine and explicit block
-    // sizes.  Beyond 32 threshold planes there is no precompiled variant:
-    // the compiled kernel is the only one.
-    e->want_jit_frank = e->var ? (jit_ok && (e->var->fa < 0 || e->var->cu < 0) &&
-                                  jit_frank_fits(n))
-                               : (e->engine == BWG_ENGINE_BITWISE && !gen_path && jit_ok &&
-                                  n->shape_ok && jit_frank_fits(n));
     const Layout L = layout(n, M, e->engine, e->table_cap, e->var);
     e->buf = (uint8_t *)dev_buf;
     e->bytes = buf_bytes;
@@ -756,6 +769,23 @@ extern "C" int bwg_ensemble_prepare(bwg_ens *e)
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (e->lat || !e->want_jit_frank || e->jit_frank) return BWG_OK;
     return jit_frank_get(e->net, &e->jit_frank);
+}
+
+extern "C" int bwg_net_compile(bwg_net *n, uint32_t *built)
+{
+    if (!n) return fail(BWG_EINVAL, "null network");
+    if (built) *built = 0;
+    if (n->lat) return BWG_OK;
+    const WmVariant *var = nullptr;
+    const GenVariant *gv = nullptr;
+    int rc = check_engine(n, BWG_ENGINE_BITWISE, &var, &gv);
+    if (rc) return rc;
+    bool gen = false, frank = false;
+    jit_plan(n, BWG_ENGINE_BITWISE, var, false, true, &gen, &frank);
+    rc = jit_build_codes(n, gen, frank);
+    if (rc) return rc;
+    if (built) *built = (gen ? BWG_JIT_GENERAL : 0u) | (frank ? BWG_JIT_FRANK : 0u);
+    return BWG_OK;
 }
 
 extern "C" int bwg_ensemble_set_engine(bwg_ens *e, int32_t engine)

@@ -72,6 +72,7 @@ struct bwg_net {
     std::map<uint64_t, Table> tables;  // keyed by the bits of mu
     bwg::JitKernel *jit = nullptr;     // compiled on the first ensemble that needs it
     bwg::JitKernel *jit_frank = nullptr;  // compiled Frank-family kernel (run-time weights)
+    std::vector<char> jit_code, jit_frank_code;  // their code objects (gfx950)
     ~bwg_net()
     {
         for (auto &kv : tables)
@@ -151,6 +152,9 @@ int jit_get(bwg_net *n, const JitKernel **out);
 // and whether the network fits that kernel's template parameters.
 int jit_frank_get(bwg_net *n, const JitKernel **out);
 bool jit_frank_fits(const bwg_net *n);
+// Build, on the host only, the code objects of the general and/or the Frank
+// kernel that are not built yet (later loads reuse them).
+int jit_build_codes(bwg_net *n, bool general, bool frank);
 // Budgets of one advance to t_end (no event launches); *kmin/*kmax bound K.
 int schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *kmin, uint64_t *kmax);
 // Bookkeeping after budgets with K in [kmin, kmax] were drawn.

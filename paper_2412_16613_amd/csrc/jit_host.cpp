@@ -325,10 +325,9 @@ static std::string jit_source_wide(const bwg_net &n, int NB, int BC)
     return o.str();
 }
 
-// Compiles src with hipRTC for gfx950 and loads its kernels (one wave per
-// word and producer/consumer; for the Frank kernels also the
-// shared-threshold instantiation).
-static int jit_compile(const std::string &src, bool frank, JitKernel **out)
+// Compiles src with hipRTC for gfx950 into a code object: host work only,
+// no device needed.
+static int jit_build(const std::string &src, std::vector<char> *code)
 {
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "bwg_jit_word.hip", kJitHeaderCount, kJitHeaders,
@@ -349,9 +348,17 @@ static int jit_compile(const std::string &src, bool frank, JitKernel **out)
     }
     size_t cs = 0;
     hiprtcGetCodeSize(prog, &cs);
-    std::vector<char> code(cs);
-    hiprtcGetCode(prog, code.data());
+    code->assign(cs, 0);
+    hiprtcGetCode(prog, code->data());
     hiprtcDestroyProgram(&prog);
+    return BWG_OK;
+}
+
+// Loads a code object's kernels (one wave per word and producer/consumer;
+// for the Frank kernels also the shared-threshold instantiation) onto the
+// current device.
+static int jit_load(const std::vector<char> &code, bool frank, JitKernel **out)
+{
     auto k = new JitKernel();
     k->frank = frank;
     hipError_t e = hipModuleLoadData(&k->mod, code.data());
@@ -366,15 +373,11 @@ static int jit_compile(const std::string &src, bool frank, JitKernel **out)
     return BWG_OK;
 }
 
-// The compiled kernel of network n, built on the first call (under the
+// Code object of network n's general kernel, built once (caller holds the
 // network's lock).
-int jit_get(bwg_net *n, const JitKernel **out)
+static int jit_general_code(bwg_net *n)
 {
-    std::lock_guard<std::mutex> lock(n->mu);
-    if (n->jit) {
-        *out = n->jit;
-        return BWG_OK;
-    }
+    if (!n->jit_code.empty()) return BWG_OK;
     if (!n->gen_ok && !n->wide_ok)
         return fail(BWG_EUNSUPPORTED, "no general reaction table for this network");
     const int need_bc = n->q.B + (n->q.max_total == (1ll << n->q.B) ? 1 : 0);
@@ -382,9 +385,23 @@ int jit_get(bwg_net *n, const JitKernel **out)
     if (BC > kMaxThresholdPlanes || NB > 14)
         return fail(BWG_EUNSUPPORTED, "network beyond 14 count / %d threshold planes",
                     kMaxThresholdPlanes);
+    return jit_build(n->wide ? jit_source_wide(*n, NB, BC) : jit_source(*n, NB, BC),
+                     &n->jit_code);
+}
+
+// The compiled kernel of network n, built and loaded on the first call
+// (under the network's lock).
+int jit_get(bwg_net *n, const JitKernel **out)
+{
+    std::lock_guard<std::mutex> lock(n->mu);
+    if (n->jit) {
+        *out = n->jit;
+        return BWG_OK;
+    }
+    int rc = jit_general_code(n);
+    if (rc) return rc;
     JitKernel *k = nullptr;
-    const int rc =
-        jit_compile(n->wide ? jit_source_wide(*n, NB, BC) : jit_source(*n, NB, BC), false, &k);
+    rc = jit_load(n->jit_code, false, &k);
     if (rc) return rc;
     n->jit = k;
     *out = k;
@@ -456,9 +473,21 @@ bool jit_frank_fits(const bwg_net *n)
     return frank_params(*n, &p);
 }
 
-// The compiled Frank-family kernel of network n (first call compiles it,
-// under the network's lock); BWG_EUNSUPPORTED where the network's planes
-// or weights do not fit the kernel's template parameters.
+// Code object of network n's Frank-family kernel, built once (caller holds
+// the network's lock); BWG_EUNSUPPORTED where the network's planes or
+// weights do not fit the kernel's template parameters.
+static int jit_frank_code(bwg_net *n)
+{
+    if (!n->jit_frank_code.empty()) return BWG_OK;
+    FrankParams p;
+    if (!frank_params(*n, &p))
+        return fail(BWG_EUNSUPPORTED, "network beyond the compiled Frank kernel's range");
+    return jit_build(jit_frank_source(p.NB, p.BC, p.FA, p.FI, p.CU, p.NT, p.BS),
+                     &n->jit_frank_code);
+}
+
+// The compiled Frank-family kernel of network n (first call builds and
+// loads it, under the network's lock).
 int jit_frank_get(bwg_net *n, const JitKernel **out)
 {
     std::lock_guard<std::mutex> lock(n->mu);
@@ -466,15 +495,22 @@ int jit_frank_get(bwg_net *n, const JitKernel **out)
         *out = n->jit_frank;
         return BWG_OK;
     }
-    FrankParams p;
-    if (!frank_params(*n, &p))
-        return fail(BWG_EUNSUPPORTED, "network beyond the compiled Frank kernel's range");
+    int rc = jit_frank_code(n);
+    if (rc) return rc;
     JitKernel *k = nullptr;
-    const int rc = jit_compile(jit_frank_source(p.NB, p.BC, p.FA, p.FI, p.CU, p.NT, p.BS), true, &k);
+    rc = jit_load(n->jit_frank_code, true, &k);
     if (rc) return rc;
     n->jit_frank = k;
     *out = k;
     return BWG_OK;
+}
+
+int jit_build_codes(bwg_net *n, bool general, bool frank)
+{
+    std::lock_guard<std::mutex> lock(n->mu);
+    int rc = general ? jit_general_code(n) : BWG_OK;
+    if (!rc && frank) rc = jit_frank_code(n);
+    return rc;
 }
 
 hipError_t jit_launch(const JitKernel *k, const WmArgs &a, hipStream_t s)

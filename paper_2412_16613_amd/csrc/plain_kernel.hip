@@ -10,9 +10,9 @@
 
 namespace bwg {
 
-__global__ __launch_bounds__(256) void plain_event_kernel(PlainArgs a)
+__global__ __launch_bounds__(256) void plain_event_kernel(PlainArgs a, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.M) return;
     int32_t N[3] = {a.counts[3 * i], a.counts[3 * i + 1], a.counts[3 * i + 2]};
     const uint64_t e0 = a.E[i];
@@ -65,18 +65,18 @@ __global__ __launch_bounds__(256) void plain_event_kernel(PlainArgs a)
 hipError_t launch_plain(const PlainArgs &a, hipStream_t s, int block)
 {
     if (block <= 0) block = 256;
-    const uint64_t grid = (a.M + block - 1) / block;
-    hipLaunchKernelGGL(plain_event_kernel, dim3((uint32_t)grid), dim3(block), 0, s, a);
-    return hipGetLastError();
+    return launch_pieces(a.M, (uint32_t)block, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(plain_event_kernel, g, dim3(block), 0, s, a, i0);
+    });
 }
 
 // Initial state of the plain engine: fixed counts or the multinomial draw
 // (same INIT contract as the bit-sliced engine).
 __global__ void plain_init_kernel(int32_t *counts, uint64_t M, int mode, int32_t c0, int32_t c1,
                                   int32_t c2, int64_t n_tot, uint64_t seed, uint32_t net_id,
-                                  uint64_t *E, uint64_t *Et, uint64_t *real)
+                                  uint64_t *E, uint64_t *Et, uint64_t *real, uint64_t i0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= M) return;
     if (mode == 0) {
         counts[3 * i] = c0;
@@ -108,9 +108,10 @@ hipError_t launch_plain_init(int32_t *counts, uint64_t M, int mode, const int32_
                              int64_t n_tot, uint64_t seed, uint32_t net_id, uint64_t *E,
                              uint64_t *Et, uint64_t *real, hipStream_t s)
 {
-    hipLaunchKernelGGL(plain_init_kernel, dim3((uint32_t)((M + 255) / 256)), dim3(256), 0, s,
-                       counts, M, mode, c[0], c[1], c[2], n_tot, seed, net_id, E, Et, real);
-    return hipGetLastError();
+    return launch_pieces(M, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(plain_init_kernel, g, dim3(256), 0, s, counts, M, mode, c[0], c[1],
+                           c[2], n_tot, seed, net_id, E, Et, real, i0);
+    });
 }
 
 }  // namespace bwg

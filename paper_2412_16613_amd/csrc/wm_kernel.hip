@@ -138,36 +138,39 @@ hipError_t launch_wm(const WmArgs &a, hipStream_t s, int block, int word_bits)
     X(12, 28, -1, -1, 0, 28)                                                  \
     X(14, 32, -1, -1, 0, 32)
 
-// Lanes engine: 8 words per 256-thread block, one replica per thread.
-__global__ __launch_bounds__(256) void wm_lanes_kernel(WmArgs a)
+// Lanes engine: 8 words per 256-thread block, one replica per thread; the
+// launch's piece starts at word w0.
+__global__ __launch_bounds__(256) void wm_lanes_kernel(WmArgs a, uint64_t w0)
 {
     __shared__ __align__(16) uint32_t sq[8][kLanesHalfWords];
     const int half = threadIdx.x >> 5;
-    wm_lanes(a, 8 * (uint64_t)blockIdx.x + half, sq[half]);
+    wm_lanes(a, w0 + 8 * (uint64_t)blockIdx.x + half, sq[half]);
 }
 
 // Shared thresholds of events e0 .. e0 + len - 1, one thread per event.
 __global__ __launch_bounds__(256) void shared_fill_kernel(uint32_t *tab, uint64_t e0, uint64_t len,
-                                                          uint64_t seed, uint32_t net_id, uint32_t Z)
+                                                          uint64_t seed, uint32_t net_id, uint32_t Z,
+                                                          uint64_t k0)
 {
-    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t k = k0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < len) tab[k] = shared_threshold(seed, net_id, e0 + k, Z, (0u - Z) % Z);
 }
 
 hipError_t launch_shared_fill(uint32_t *tab, uint64_t e0, uint64_t len, uint64_t seed,
                               uint32_t net_id, uint32_t Z, hipStream_t s)
 {
-    if (len == 0) return hipSuccess;
-    hipLaunchKernelGGL(shared_fill_kernel, dim3((uint32_t)((len + 255) / 256)), dim3(256), 0, s,
-                       tab, e0, len, seed, net_id, Z);
-    return hipGetLastError();
+    return launch_pieces(len, 256, [&](uint64_t k0, dim3 g) {
+        hipLaunchKernelGGL(shared_fill_kernel, g, dim3(256), 0, s, tab, e0, len, seed, net_id, Z,
+                           k0);
+    });
 }
 
 hipError_t launch_wm_lanes(const WmArgs &a, hipStream_t s)
 {
-    const uint64_t grid = (a.n_words + 7) / 8;
-    hipLaunchKernelGGL(wm_lanes_kernel, dim3((uint32_t)grid), dim3(256), 0, s, a);
-    return hipGetLastError();
+    // one work-item per replica slot: pieces of kLaunchSpan / 32 words
+    return launch_pieces(32 * a.n_words, 256, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(wm_lanes_kernel, g, dim3(256), 0, s, a, i0 / 32);
+    });
 }
 
 #define BWG_WM_INST(nb, bc, fa, cu, nt, bs)                                     \

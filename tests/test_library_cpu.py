@@ -352,3 +352,28 @@ def test_wide_network_limits():
     with pytest.raises(bwg.BwgError) as e:
         bwg.Network(lat)
     assert e.value.code == _abi.BWG_EUNSUPPORTED
+
+
+def test_run_time_kernels_compile_on_the_host():
+    """bwg_net_compile builds every kernel a bit-sliced ensemble of the network
+    would compile at run time, with no device (there is none here): the
+    Frank-family kernel for run-time weights and beyond 32 threshold planes,
+    the general kernel for other networks, closed or open, of 3 or more
+    species; nothing for networks on precompiled kernels and for lattices.
+    A second call reuses the code."""
+    from workloads import open_network, random_wide_network
+    cases = [
+        (frank_network(1024), 0, set()),                 # exact-width precompiled kernel
+        (paper_network(32), 0, set()),
+        (frank_network(200, k0=0.03), 0, {"frank"}),
+        (frank_network(10, k0=0.0137), 26, {"frank"}),   # B = 35
+        (random_network(3, 100, 6), 0, {"general"}),
+        (random_network(0, 12, 5), 20, {"general"}),     # B = 33
+        (random_wide_network(1, 5, 60, 7), 0, {"general"}),
+        (open_network("lotka_volterra", 200), 0, {"general"}),
+        (frank_network(12, lx=4, ly=4, hop=0.1, site_planes=4), 0, set()),
+    ]
+    for net, bits, want in cases:
+        n = bwg.Network(net, precision_bits=bits)
+        assert n.compile() == want
+        assert n.compile() == want
