@@ -424,6 +424,45 @@ int bwg_ensemble_set_engine(bwg_ens *ens, int32_t engine);
  * for a null ensemble.  Host only. */
 int bwg_ensemble_prepare(bwg_ens *ens);
 
+/* Checkpoint and resume between advances.  Every draw is keyed by replica,
+ * absolute event index and advance index (counter-based, Sec. 3 and Sec. 4
+ * draws of the chain), so the counts, the event counters, t_now and the
+ * advance index fix the rest of a run: an ensemble restored from a
+ * checkpoint and advanced further gives, bit for bit, what the saved one
+ * would have given, if both have the same seed and net_id (with others it
+ * continues from the saved state on other draws).
+ *
+ * bwg_ensemble_checkpoint_bytes: host bytes a checkpoint of ens takes.
+ * bwg_ensemble_save: copy the state into host_dst (caller-owned, dst_bytes
+ *   at least that size; ERANGE otherwise); EINVAL before init or while
+ *   events of the last advance or step are pending.  Synchronous: returns
+ *   after the copies on stream have finished.
+ * bwg_ensemble_restore: load a checkpoint into ens, which must be created
+ *   for the same network (the same integer form), replica count and state
+ *   kind (bit planes -- the BITWISE and LANES engines share them --, PLAIN
+ *   counts, or lattice) and shared-threshold option; other options may
+ *   differ.  EINVAL for anything else, for replicas with pending events or a
+ *   shared-threshold checkpoint whose replicas are not at one event; ERANGE
+ *   for an event index of 2^47 or more.  Synchronous.
+ *
+ * Layout (host byte order; the first 256 bytes are 32 uint64 header words):
+ *   [0] magic 0x31544b5043475742, [1] header bytes (256), [2] total bytes,
+ *   [3] network fingerprint (FNV-1a of the integer form), [4] n_replicas,
+ *   [5] seed, [6] net_id, [7] state kind (0 bit planes, 1 plain, 2 lattice),
+ *   [8] shared-threshold range Z (0: none), [9] t_now (binary64 bits),
+ *   [10] advance index, [11] region count r (<= 6), then for k < r the words
+ *   [12+3k] region id, [13+3k] byte offset (a multiple of 256), [14+3k] bytes.
+ * Region ids: 1 bit planes (the device layout: [species][plane][word]
+ * uint32, lattices [group][site][species][plane] words), 2 plain counts
+ * (int32 [replica][3]), 3 events run per replica (uint64; entries past
+ * n_replicas up to the padded word count are ignored), 4 event targets
+ * (uint64, equal to region 3 between advances), 5 real events (uint64, per
+ * 32-replica word, per replica for PLAIN), 6 blocked hops (uint64 per word,
+ * lattices). */
+int bwg_ensemble_checkpoint_bytes(const bwg_ens *ens, uint64_t *bytes);
+int bwg_ensemble_save(bwg_ens *ens, void *host_dst, uint64_t dst_bytes, void *stream);
+int bwg_ensemble_restore(bwg_ens *ens, const void *host_src, uint64_t src_bytes, void *stream);
+
 /* In batches, run the last n_words words of a bit-sliced ensemble (rounded so
  * that the bit-sliced part is whole 64-word items) as lanes items of the same
  * persistent launch: the two kinds of item fill the SIMDs that one wave per

@@ -294,6 +294,22 @@ class Ensemble:
             self._stream()))
         return out, (fp.to(t.int64) if fp is not None else None)
 
+    def save(self):
+        """Checkpoint between advances (bwg_ensemble_save): a bytearray in the
+        layout include/bwg.h documents."""
+        n = ctypes.c_uint64()
+        _abi.check(_lib().bwg_ensemble_checkpoint_bytes(self.handle, ctypes.byref(n)))
+        buf = bytearray(n.value)
+        ptr = (ctypes.c_char * n.value).from_buffer(buf)
+        _abi.check(_lib().bwg_ensemble_save(self.handle, ptr, n.value, self._stream()))
+        return buf
+
+    def restore(self, blob):
+        """Load a checkpoint (bwg_ensemble_restore); returns self."""
+        src = (ctypes.c_char * len(blob)).from_buffer_copy(blob)
+        _abi.check(_lib().bwg_ensemble_restore(self.handle, src, len(blob), self._stream()))
+        return self
+
     def read_events(self):
         """(events per replica, real events per 32-lane group (bitwise) or
         per replica (plain)) as int64 tensors."""

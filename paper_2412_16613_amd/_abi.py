@@ -48,7 +48,8 @@ SYMBOLS = (
     "bwg_net_lattice", "bwg_ensemble_read_sites", "bwg_ensemble_read_blocked",
     "bwg_ensemble_kernel_time", "bwg_ensemble_set_engine", "bwg_ensemble_set_lanes_words",
     "bwg_ensemble_record", "bwg_ensemble_prepare", "bwg_ensemble_step_static",
-    "bwg_net_compile",
+    "bwg_net_compile", "bwg_ensemble_checkpoint_bytes", "bwg_ensemble_save",
+    "bwg_ensemble_restore",
 )
 BWG_STATIC_STATE_BYTES = 64 << 20
 
@@ -123,6 +124,9 @@ def load():
         "bwg_net_quantized": (i32, [vp, P(QNet)]),
         "bwg_net_destroy": (None, [vp]),
         "bwg_net_compile": (i32, [vp, P(u32)]),
+        "bwg_ensemble_checkpoint_bytes": (i32, [vp, P(u64)]),
+        "bwg_ensemble_save": (i32, [vp, vp, u64, vp]),
+        "bwg_ensemble_restore": (i32, [vp, vp, u64, vp]),
         "bwg_poisson_table": (i32, [ctypes.c_double, P(i64), P(u64), u64, P(u64)]),
         "bwg_ensemble_state_bytes": (i32, [vp, u64, P(Opts), P(u64)]),
         "bwg_ensemble_create": (i32, [vp, u64, u64, u32, vp, u64, P(Opts), P(vp)]),
