@@ -124,6 +124,29 @@ def step_static(network, n_replicas, counts, n_events, seed=0, net_id=0, out=Non
     return out
 
 
+def _opts(engine, events_per_launch, table_capacity, block, time_kernels, shared_threshold,
+          generic, jit, word_bits, lds_stage):
+    o = _abi.Opts()
+    o.engine = ENGINES[engine]
+    o.block = block
+    o.table_capacity = table_capacity
+    o.events_per_launch = events_per_launch
+    o.word_bits = word_bits
+    o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
+               (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0) |
+               (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0) |
+               (0 if jit else _abi.BWG_OPT_NO_JIT) |
+               (0 if lds_stage else _abi.BWG_OPT_NO_LDS_STAGE))
+    return o
+
+
+def _state_bytes(network, n_replicas, opts):
+    nbytes = ctypes.c_uint64()
+    _abi.check(_lib().bwg_ensemble_state_bytes(network.handle, n_replicas, ctypes.byref(opts),
+                                               ctypes.byref(nbytes)))
+    return nbytes.value
+
+
 class Ensemble:
     """Replicas of one network in a caller-owned device buffer."""
 
@@ -137,22 +160,10 @@ class Ensemble:
         self.network = network
         self.M = int(n_replicas)
         self.device = torch.device(device)
-        o = _abi.Opts()
-        o.engine = ENGINES[engine]
-        o.block = block
-        o.table_capacity = table_capacity
-        o.events_per_launch = events_per_launch
-        o.word_bits = word_bits
-        o.flags = ((_abi.BWG_OPT_TIME_KERNELS if time_kernels else 0) |
-                   (_abi.BWG_OPT_SHARED_THRESHOLD if shared_threshold else 0) |
-                   (_abi.BWG_OPT_GENERIC_KERNEL if generic else 0) |
-                   (0 if jit else _abi.BWG_OPT_NO_JIT) |
-                   (0 if lds_stage else _abi.BWG_OPT_NO_LDS_STAGE))
+        o = _opts(engine, events_per_launch, table_capacity, block, time_kernels,
+                  shared_threshold, generic, jit, word_bits, lds_stage)
         self._opts = o
-        nbytes = ctypes.c_uint64()
-        _abi.check(L.bwg_ensemble_state_bytes(network.handle, self.M, ctypes.byref(o),
-                                              ctypes.byref(nbytes)))
-        self.state_bytes = nbytes.value
+        self.state_bytes = _state_bytes(network, self.M, o)
         self._buf = torch.empty(self.state_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self._buf.data_ptr()
         off = (-base) % 256
@@ -164,6 +175,15 @@ class Ensemble:
         self.groups = (self.M + 31) // 32
         self.engine = engine
         self.n_species = len(network.net["species"])
+
+    @staticmethod
+    def bytes_needed(network, n_replicas, engine="bitwise", events_per_launch=0,
+                     table_capacity=0, block=0, shared_threshold=False, generic=False,
+                     jit=True, word_bits=0, lds_stage=True):
+        """Device bytes an ensemble with these arguments takes (no allocation)."""
+        return _state_bytes(network, int(n_replicas),
+                            _opts(engine, events_per_launch, table_capacity, block, False,
+                                  shared_threshold, generic, jit, word_bits, lds_stage))
 
     def _stream(self):
         return _stream_ptr(self.torch.cuda.current_stream(self.device))

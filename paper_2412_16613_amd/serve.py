@@ -25,6 +25,15 @@ their memory returned to the budget) once its events have completed.
 Results do not depend on the mix: every draw is keyed by (seed, net id,
 replica, event), so a request served among others gives bit for bit the
 result it gives alone.
+
+Failures stay with their request.  Every result has a status: "ok"; "error"
+for a request the library refuses (an invalid network or initial state) or
+whose launch fails (the message in "error"; a failed persistent pass fails
+the well-mixed requests it ran); "rejected" for a request whose state alone
+exceeds the HBM budget or the batch's work items; "cancelled" for a request
+not complete `deadline` seconds after its arrival (a request key, optional).
+A request leaves the batch before its memory is returned, and only once the
+work enqueued for it has completed.
 """
 
 import collections
@@ -107,6 +116,31 @@ class Server:
         main = torch.cuda.current_stream(self.device)
         next_side = 0
 
+        cancelling = []       # (event, entry, status, message): memory back once done
+
+        def closed(r, status, message, t_admitted=None):
+            t = clock() if real_time else sim_now
+            results.append(dict(id=r["net_id"], arrival=r["arrival"], admitted=t_admitted,
+                                completed=t, latency=t - r["arrival"], status=status,
+                                error=message, replicas=r["replicas"]))
+
+        def expired(r, now):
+            d = r.get("deadline")
+            return d is not None and now > r["arrival"] + d
+
+        def drop(entries, status, message):
+            """Take entries out of service; their memory returns to the budget
+            once the work already enqueued on their stream has completed."""
+            nonlocal active
+            ids = {id(a) for a in entries}
+            active = [a for a in active if id(a) not in ids]
+            if any(not a["lattice"] for a in entries):
+                self.batch.set_members([a["ens"] for a in active if not a["lattice"]])
+            for a in entries:
+                ev = torch.cuda.Event()
+                ev.record(a["stream"])
+                cancelling.append((ev, a, status, message))
+
         def to_host(t):
             h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
             h.copy_(t, non_blocking=True)
@@ -128,7 +162,7 @@ class Server:
             for a in p["done"]:
                 r = a["req"]
                 res = dict(id=r["net_id"], arrival=r["arrival"], admitted=a["admitted"],
-                           completed=t_done, latency=t_done - r["arrival"],
+                           completed=t_done, latency=t_done - r["arrival"], status="ok",
                            hist=a["hist_host"].numpy().copy(), replicas=r["replicas"])
                 if self.keep_counts:
                     res["counts"] = a["counts_host"].numpy().copy()
@@ -150,7 +184,7 @@ class Server:
 
         wm_changed = True     # the batch may still list an earlier call's members
         next_report = progress_every
-        while incoming or waiting or active or wm_inflight or lat_inflight:
+        while incoming or waiting or active or wm_inflight or lat_inflight or cancelling:
             if progress is not None and time.perf_counter() - t0 >= next_report:
                 next_report += progress_every
                 progress("t=%.0fs: %d done, %d active, %d waiting, %d not yet arrived, %d passes"
@@ -161,20 +195,36 @@ class Server:
                 break
             while incoming and incoming[0]["arrival"] <= now:
                 waiting.append(incoming.popleft())
+            # deadlines: waiting requests leave the queue, active ones the service
+            for r in [r for r in waiting if expired(r, now)]:
+                waiting.remove(r)
+                closed(r, "cancelled", "deadline passed before admission")
+            late = [a for a in active if expired(a["req"], now)]
+            if late:
+                drop(late, "cancelled", "deadline passed")
+                wm_changed = True
             while waiting and len(active) < self.max_members:
                 r = waiting[0]
-                net = self._network(r["net"])
-                lattice = net.is_lattice
-                lanes = (not lattice and self.lanes_events > 0 and
-                         net.quantized()["Lambda"] * r["t_end"] >= self.lanes_events)
-                ens = bwg.Ensemble(net, r["replicas"], seed=r["seed"], net_id=r["net_id"],
-                                   device=self.device, engine="lanes" if lanes else "bitwise")
-                nbytes = ens.state_bytes
+                try:
+                    net = self._network(r["net"])
+                    lattice = net.is_lattice
+                    lanes = (not lattice and self.lanes_events > 0 and
+                             net.quantized()["Lambda"] * r["t_end"] >= self.lanes_events)
+                    nbytes = bwg.Ensemble.bytes_needed(
+                        net, r["replicas"], engine="lanes" if lanes else "bitwise")
+                except (bwg.BwgError, ValueError, KeyError, TypeError) as exc:
+                    waiting.popleft()
+                    closed(r, "error", str(exc))
+                    continue
                 items = 0 if lattice else self._items(r["replicas"], lanes)
-                busy = active or wm_inflight or lat_inflight
+                if nbytes > self.hbm_budget or items > self.max_items:
+                    waiting.popleft()
+                    closed(r, "rejected", "state of %d bytes and %d work items exceeds the "
+                           "server's budget" % (nbytes, items))
+                    continue
+                busy = active or wm_inflight or lat_inflight or cancelling
                 if busy and (used_bytes + nbytes > self.hbm_budget
                              or used_items + items > self.max_items):
-                    del ens
                     break
                 waiting.popleft()
                 # a lattice ensemble lives on its side stream from its first call
@@ -182,9 +232,18 @@ class Server:
                 if lattice:
                     stream = self.sides[next_side % len(self.sides)]
                     next_side += 1
-                with torch.cuda.stream(stream):
-                    ens.init(r["init"])
-                    ens.schedule(r["t_end"])
+                try:
+                    ens = bwg.Ensemble(net, r["replicas"], seed=r["seed"], net_id=r["net_id"],
+                                       device=self.device, engine="lanes" if lanes else "bitwise")
+                    with torch.cuda.stream(stream):
+                        ens.init(r["init"])
+                        ens.schedule(r["t_end"])
+                except (bwg.BwgError, ValueError, KeyError, TypeError) as exc:
+                    # whatever init enqueued finishes before the buffer can
+                    # be handed out again
+                    stream.synchronize()
+                    closed(r, "error", str(exc))
+                    continue
                 active.append(dict(req=r, ens=ens, bytes=nbytes, items=items, lattice=lattice,
                                    stream=stream, admitted=clock() if real_time else now))
                 used_bytes += nbytes
@@ -197,7 +256,13 @@ class Server:
             if wm and len(wm_inflight) < self.depth:
                 if wm_changed:
                     self.batch.set_members([a["ens"] for a in wm])
-                self.batch.run(self.chunk)
+                try:
+                    self.batch.run(self.chunk)
+                except bwg.BwgError as exc:
+                    # the pass's members are in an unknown state: all fail
+                    drop(wm, "error", "persistent pass failed: %s" % exc)
+                    wm_changed = True
+                    continue
                 done = [a for a in wm if a["ens"].pending() == 0]
                 readouts(done)
                 ev = torch.cuda.Event()
@@ -213,11 +278,19 @@ class Server:
                     self.batch.set_members([a["ens"] for a in active if not a["lattice"]])
             if lat and len(lat_inflight) < self.depth:
                 streams = []
+                failed = []
                 for a in lat:
-                    with torch.cuda.stream(a["stream"]):
-                        a["ens"].run(self.lattice_chunk)
+                    try:
+                        with torch.cuda.stream(a["stream"]):
+                            a["ens"].run(self.lattice_chunk)
+                    except bwg.BwgError as exc:
+                        failed.append((a, str(exc)))
+                        continue
                     if a["stream"] not in streams:
                         streams.append(a["stream"])
+                for a, msg in failed:
+                    drop([a], "error", "lattice pass failed: %s" % msg)
+                lat = [a for a in lat if all(a is not f for f, _ in failed)]
                 done = [a for a in lat if a["ens"].pending() == 0]
                 readouts(done)
                 evs = []
@@ -250,6 +323,20 @@ class Server:
                 while q and ready(q[0]):
                     retire(q.popleft())
                     retired = True
+            still = []
+            for ev, a, status, msg in cancelling:
+                if ev.query():
+                    closed(a["req"], status, msg, a["admitted"])
+                    used_bytes -= a["bytes"]
+                    used_items -= a["items"]
+                    retired = True
+                else:
+                    still.append((ev, a, status, msg))
+            cancelling = still
+            if not enqueued and not retired and cancelling and not (wm_inflight or
+                                                                    lat_inflight):
+                cancelling[0][0].synchronize()
+                continue
             if not enqueued and not retired and (wm_inflight or lat_inflight):
                 heads = [q for q in (wm_inflight, lat_inflight) if q]
                 q = min(heads, key=lambda d: d[0]["order"])
@@ -262,8 +349,11 @@ class Server:
 
 
 def summarize(results, stats):
-    lat = np.array([r["latency"] for r in results])
-    return dict(requests=len(results),
+    ok = [r for r in results if r.get("status", "ok") == "ok"]
+    lat = np.array([r["latency"] for r in ok])
+    return dict(requests=len(ok),
+                failed={s: sum(r.get("status") == s for r in results)
+                        for s in ("error", "rejected", "cancelled")},
                 p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else None,
                 p99_latency_s=float(np.percentile(lat, 99)) if len(lat) else None,
                 mean_latency_s=float(lat.mean()) if len(lat) else None,

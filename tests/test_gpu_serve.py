@@ -118,3 +118,89 @@ def test_real_time_stream_reports_latency(torch):
     assert len(res) == len(reqs)
     assert all(r["latency"] >= 0 for r in res)
     assert s["p99_latency_s"] >= s["p50_latency_s"]
+
+
+def _alone(r, keep_counts=True):
+    e = bwg.Ensemble(bwg.Network(r["net"]), r["replicas"], seed=r["seed"], net_id=r["net_id"])
+    e.init(r["init"]).advance(r["t_end"])
+    return e.histogram(256).cpu().numpy(), e.read_counts().cpu().numpy()
+
+
+def test_failures_stay_with_their_request(torch, monkeypatch):
+    """An invalid network, an invalid start, a request larger than the whole
+    budget, one past its deadline and a lattice whose launch fails (injected)
+    each end with their own status; every other request completes with
+    the result it gives alone."""
+    reqs = _lattice_requests()
+    base = len(reqs)
+    bad_rates = dict(frank_network(16), rates=[-1.0] + frank_network(16)["rates"][1:])
+    bad = [dict(arrival=0.2, net=bad_rates, replicas=100, seed=1, net_id=900,
+                init=("fixed", (0, 0, 16)), t_end=1.0),
+           dict(arrival=0.4, net=frank_network(16), replicas=100, seed=1, net_id=901,
+                init=("fixed", (0, 0, 15)), t_end=1.0),
+           dict(arrival=0.6, net=frank_network(64), replicas=1 << 31, seed=1, net_id=902,
+                init=("fixed", (0, 0, 64)), t_end=1.0),
+           dict(arrival=0.8, net=frank_network(64), replicas=4096, seed=1, net_id=903,
+                init=("fixed", (0, 0, 64)), t_end=1e4, deadline=2.5)]
+    orig = bwg.Ensemble.run
+
+    def flaky(self, max_events=0):
+        if self.network.net.get("lx") == 16:
+            raise bwg.BwgError(_abi_edevice(), "injected launch failure")
+        return orig(self, max_events)
+
+    monkeypatch.setattr(bwg.Ensemble, "run", flaky)
+    srv = Server(hbm_budget=8 << 30, chunk=200, max_members=6, keep_counts=True,
+                 lattice_chunk=8192)
+    res = srv.serve(reqs + bad, real_time=False, pass_time=1.0)
+    by_id = {r["id"]: r for r in res}
+    assert len(res) == base + len(bad)
+    assert by_id[900]["status"] == "error" and "rate" in by_id[900]["error"]
+    assert by_id[901]["status"] == "error"
+    assert by_id[902]["status"] == "rejected"
+    assert by_id[903]["status"] == "cancelled"
+    assert by_id[701]["status"] == "error" and "injected" in by_id[701]["error"]
+    for r in reqs:
+        if r["net_id"] == 701:
+            continue
+        got = by_id[r["net_id"]]
+        assert got["status"] == "ok", got
+        h, c = _alone(r)
+        np.testing.assert_array_equal(got["hist"], h)
+        np.testing.assert_array_equal(got["counts"], c)
+    s = summarize(res, srv.stats)
+    assert s["requests"] == base - 1
+    assert s["failed"] == dict(error=3, rejected=1, cancelled=1)
+
+
+def test_failed_persistent_pass_fails_only_its_members(torch, monkeypatch):
+    reqs = _requests()
+    orig = bwg.Batch.run
+    calls = {"n": 0}
+
+    def flaky(self, max_events=0):
+        calls["n"] += 1
+        if calls["n"] == 3:
+            raise bwg.BwgError(_abi_edevice(), "injected launch failure")
+        return orig(self, max_events)
+
+    monkeypatch.setattr(bwg.Batch, "run", flaky)
+    srv = Server(chunk=200, max_members=3, keep_counts=True)
+    res = srv.serve(reqs, real_time=False, pass_time=1.0)
+    assert len(res) == len(reqs)
+    failed = [r for r in res if r["status"] != "ok"]
+    assert failed and all(r["status"] == "error" and "injected" in r["error"] for r in failed)
+    assert len(failed) <= 3
+    by_id = {r["id"]: r for r in res}
+    for r in reqs:
+        got = by_id[r["net_id"]]
+        if got["status"] == "ok":
+            h, c = _alone(r)
+            np.testing.assert_array_equal(got["hist"], h)
+            np.testing.assert_array_equal(got["counts"], c)
+    assert sum(r["status"] == "ok" for r in res) >= len(reqs) - 3
+
+
+def _abi_edevice():
+    from paper_2412_16613_amd import _abi
+    return _abi.BWG_EDEVICE

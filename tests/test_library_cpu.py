@@ -377,3 +377,19 @@ def test_run_time_kernels_compile_on_the_host():
         n = bwg.Network(net, precision_bits=bits)
         assert n.compile() == want
         assert n.compile() == want
+
+
+def test_bytes_needed_matches_the_library():
+    """Ensemble.bytes_needed (the server's admission check) allocates nothing
+    and reports bwg_ensemble_state_bytes for the same options."""
+    import ctypes
+    L = _abi.load()
+    n = bwg.Network(frank_network(1024))
+    for engine, M in (("bitwise", 1 << 20), ("lanes", 1000), ("plain", 77)):
+        o = _abi.Opts()
+        o.engine = bwg.ENGINES[engine]
+        b = ctypes.c_uint64()
+        assert L.bwg_ensemble_state_bytes(n.handle, M, ctypes.byref(o), ctypes.byref(b)) == 0
+        assert bwg.Ensemble.bytes_needed(n, M, engine=engine) == b.value
+    with pytest.raises(bwg.BwgError):
+        bwg.Ensemble.bytes_needed(n, 0)
