@@ -208,6 +208,7 @@ static int set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, hipStream_t
 extern "C" int bwg_batch_create(bwg_ens *const *ens, int32_t n, void *dev_buf, uint64_t buf_bytes,
                                 const bwg_batch_opts *opts, void *stream, bwg_batch **out)
 {
+    TraceRange trace_("bwg_batch_create");
     if (!out || !dev_buf) return fail(BWG_EINVAL, "null argument");
     *out = nullptr;
     if ((uintptr_t)dev_buf & 255) return fail(BWG_EINVAL, "device buffer not 256-byte aligned");
@@ -253,6 +254,7 @@ extern "C" int bwg_batch_create(bwg_ens *const *ens, int32_t n, void *dev_buf, u
 
 extern "C" int bwg_batch_set_members(bwg_batch *b, bwg_ens *const *ens, int32_t n, void *stream)
 {
+    TraceRange trace_("bwg_batch_set_members");
     if (!b) return fail(BWG_EINVAL, "null batch");
     return set_members(b, ens, n, (hipStream_t)stream);
 }
@@ -413,6 +415,7 @@ static void note_budgets(bwg_batch *b, const double *t_end, const std::vector<ui
 
 extern "C" int bwg_batch_advance(bwg_batch *b, const double *t_end, void *stream)
 {
+    TraceRange trace_("bwg_batch_advance");
     if (!b || (!t_end && !b->ens.empty())) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(sync_staging(b));
@@ -434,6 +437,7 @@ extern "C" int bwg_batch_advance(bwg_batch *b, const double *t_end, void *stream
 
 extern "C" int bwg_batch_run(bwg_batch *b, uint64_t max_events, void *stream)
 {
+    TraceRange trace_("bwg_batch_run");
     if (!b) return fail(BWG_EINVAL, "null batch");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(sync_staging(b));
@@ -449,6 +453,7 @@ extern "C" int bwg_batch_run(bwg_batch *b, uint64_t max_events, void *stream)
 
 extern "C" int bwg_batch_graph_advance(bwg_batch *b, double dt, int32_t n_steps, void *stream)
 {
+    TraceRange trace_("bwg_batch_graph_advance");
     if (!b) return fail(BWG_EINVAL, "null batch");
     if (n_steps < 1 || !(dt >= 0)) return fail(BWG_EINVAL, "need n_steps >= 1 and dt >= 0");
     hipStream_t s = (hipStream_t)stream;

@@ -132,6 +132,7 @@ extern "C" int bwg_ensemble_checkpoint_bytes(const bwg_ens *e, uint64_t *bytes)
 
 extern "C" int bwg_ensemble_save(bwg_ens *e, void *host_dst, uint64_t dst_bytes, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_save");
     if (!e || !host_dst) return fail(BWG_EINVAL, "null argument");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     if (e->pending)
@@ -175,6 +176,7 @@ extern "C" int bwg_ensemble_save(bwg_ens *e, void *host_dst, uint64_t dst_bytes,
 extern "C" int bwg_ensemble_restore(bwg_ens *e, const void *host_src, uint64_t src_bytes,
                                     void *stream)
 {
+    TraceRange trace_("bwg_ensemble_restore");
     if (!e || !host_src) return fail(BWG_EINVAL, "null argument");
     if (e->pending)
         return fail(BWG_EINVAL, "events of the last advance are still pending");

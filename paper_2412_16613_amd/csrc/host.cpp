@@ -264,6 +264,7 @@ static void classify_generic(bwg_net &n)
 
 extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
 {
+    TraceRange trace_("bwg_net_create");
     if (!d || !out) return fail(BWG_EINVAL, "null argument");
     *out = nullptr;
     const int S = d->n_species, R = d->n_reactions;
@@ -686,6 +687,7 @@ extern "C" int bwg_ensemble_create(const bwg_net *n, uint64_t M, uint64_t seed, 
                                    void *dev_buf, uint64_t buf_bytes, const bwg_opts *o,
                                    bwg_ens **out)
 {
+    TraceRange trace_("bwg_ensemble_create");
     if (!n || !out || !dev_buf) return fail(BWG_EINVAL, "null argument");
     *out = nullptr;
     if ((uintptr_t)dev_buf & 255) return fail(BWG_EINVAL, "device buffer not 256-byte aligned");
@@ -766,6 +768,7 @@ extern "C" int bwg_ensemble_set_lanes_words(bwg_ens *e, uint64_t n_words)
 
 extern "C" int bwg_ensemble_prepare(bwg_ens *e)
 {
+    TraceRange trace_("bwg_ensemble_prepare");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (e->lat || !e->want_jit_frank || e->jit_frank) return BWG_OK;
     return jit_frank_get(e->net, &e->jit_frank);
@@ -773,6 +776,7 @@ extern "C" int bwg_ensemble_prepare(bwg_ens *e)
 
 extern "C" int bwg_net_compile(bwg_net *n, uint32_t *built)
 {
+    TraceRange trace_("bwg_net_compile");
     if (!n) return fail(BWG_EINVAL, "null network");
     if (built) *built = 0;
     if (n->lat) return BWG_OK;
@@ -862,6 +866,7 @@ extern "C" int bwg_ensemble_kernel_time(bwg_ens *e, double *ms, uint64_t *launch
 
 extern "C" int bwg_ensemble_init(bwg_ens *e, int32_t mode, const int32_t *counts, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_init");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     hipStream_t s = (hipStream_t)stream;
     const bwg_net *n = e->net;
@@ -1132,6 +1137,7 @@ int bwg::schedule_ensemble(bwg_ens *e, double t_end, hipStream_t s, uint64_t *km
 
 extern "C" int bwg_ensemble_schedule(bwg_ens *e, double t_end, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_schedule");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (e->lat) return lat_schedule(e, t_end, (hipStream_t)stream);
     uint64_t kmin, kmax;
@@ -1143,6 +1149,7 @@ extern "C" int bwg_ensemble_schedule(bwg_ens *e, double t_end, void *stream)
 
 extern "C" int bwg_ensemble_run(bwg_ens *e, uint64_t max_events, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_run");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     if (e->lat) return lat_run(e, max_events, (hipStream_t)stream);
@@ -1159,6 +1166,7 @@ extern "C" int bwg_ensemble_pending(const bwg_ens *e, uint64_t *bound)
 
 extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_advance");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     hipStream_t s = (hipStream_t)stream;
     if (e->lat) {
@@ -1174,6 +1182,7 @@ extern "C" int bwg_ensemble_advance(bwg_ens *e, double t_end, void *stream)
 
 extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_step");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     hipStream_t s = (hipStream_t)stream;
@@ -1191,6 +1200,7 @@ extern "C" int bwg_ensemble_step(bwg_ens *e, uint64_t n_events, void *stream)
 
 extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_read_counts");
     if (!e || !dst) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
     if (e->lat) return lat_read_counts(e, dst, s);
@@ -1203,6 +1213,7 @@ extern "C" int bwg_ensemble_read_counts(bwg_ens *e, int32_t *dst, void *stream)
 
 extern "C" int bwg_ensemble_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_histogram");
     if (!e || !dst) return fail(BWG_EINVAL, "null argument");
     if (n_bins < 1 || n_bins > 16384) return fail(BWG_EINVAL, "n_bins %d out of range", n_bins);
     if (e->net->wide) return fail(BWG_EUNSUPPORTED, "the histogram is of the Frank species");
@@ -1217,6 +1228,7 @@ extern "C" int bwg_ensemble_record(bwg_ens *e, const double *t_grid, uint32_t n_
                                    const uint32_t *dev_sel, uint32_t n_sel, int32_t *dev_out,
                                    int32_t threshold, uint32_t *dev_first, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_record");
     if (!e) return fail(BWG_EINVAL, "null ensemble");
     if (!e->inited) return fail(BWG_EINVAL, "ensemble not initialised");
     if (e->lat) return fail(BWG_EUNSUPPORTED, "record runs on well-mixed ensembles");
@@ -1263,6 +1275,7 @@ extern "C" int bwg_ensemble_read_events(bwg_ens *e, uint64_t *dev_events, uint64
 
 extern "C" int bwg_ensemble_stats(bwg_ens *e, void *stream, bwg_stats *out)
 {
+    TraceRange trace_("bwg_ensemble_stats");
     if (!e || !out) return fail(BWG_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_sum_u64(e->E, e->M, e->scratch, 0, s));

@@ -10,12 +10,23 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "bwg.h"
 #include "bwg_internal.h"
 
 namespace bwg {
 
 int fail(int code, const char *fmt, ...);
+
+// A roctx range over a library call: a named range in rocprofv3's marker
+// trace (--marker-trace), a function call otherwise.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 #define HIP_TRY(expr)                                                                 \
     do {                                                                              \

@@ -429,6 +429,7 @@ extern "C" int bwg_net_lattice(const bwg_net *n, bwg_lattice_info *out)
 extern "C" int bwg_ensemble_read_sites(bwg_ens *e, uint64_t first, uint64_t count,
                                        int32_t *dev_dst, void *stream)
 {
+    TraceRange trace_("bwg_ensemble_read_sites");
     if (!e || !dev_dst) return fail(BWG_EINVAL, "null argument");
     if (!e->lat) return fail(BWG_EINVAL, "not a lattice ensemble");
     if (first > e->M || count > e->M - first) return fail(BWG_EINVAL, "replica range out of bounds");
