@@ -147,3 +147,50 @@ def test_plain_engine_beyond_2p31_replicas(torch):
     del ev, real, ens
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+
+
+def test_batch_beyond_2p31_replicas(torch):
+    """A persistent batch whose members hold 2.7e9 replicas together: the
+    batch's budget launch (one work-item per replica of every member) takes
+    two dispatches, the second starting inside the second member.  Sampled
+    replicas of each member, including both sides of the boundary, against
+    the oracle."""
+    mix = [(frank_network(16, k0=0.05), (1 << 30) + 3),
+           (frank_network(24, k0=0.02), (1 << 30) + (1 << 29) + 7)]
+    t_end = 2.0
+    M1 = mix[0][1]
+    samples = [((0, 64), (M1 - 40, 40)),
+               ((0, 32), (PIECE - M1 - 32, 64), (mix[1][1] - 50, 50))]
+    oracles = []
+    for k, ((net, M), ranges) in enumerate(zip(mix, samples)):
+        row = []
+        for first, count in ranges:
+            o = ssa.OracleEnsemble(net, M, seed=3, net_id=100 + k, first=first, count=count)
+            o.init(("fixed", (0, 0, net["n_tot"])))
+            o.advance(t_end)
+            row.append(o)
+        oracles.append(row)
+    _need(torch, 100 * 10 ** 9)
+    _say("case batch of", [M for _, M in mix], "replicas")
+    ens = []
+    for k, (net, M) in enumerate(mix):
+        e = bwg.Ensemble(bwg.Network(net), M, seed=3, net_id=100 + k)
+        e.init_fixed((0, 0, net["n_tot"]))
+        ens.append(e)
+    b = bwg.Batch(ens)
+    b.advance([t_end, t_end])
+    torch.cuda.synchronize()
+    for e, ranges, row, (net, M) in zip(ens, samples, oracles, mix):
+        counts = e.read_counts()
+        ev = e.read_events()[0]
+        torch.cuda.synchronize()
+        for (first, count), o in zip(ranges, row):
+            np.testing.assert_array_equal(counts[first:first + count].cpu().numpy(), o.counts)
+            np.testing.assert_array_equal(ev[first:first + count].cpu().numpy().astype(np.uint64),
+                                          o.E)
+        for k in range(0, M, CHUNK):
+            assert bool((counts[k:k + CHUNK].to(torch.int64).sum(1) == net["n_tot"]).all())
+        del counts, ev
+    del b, ens
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
