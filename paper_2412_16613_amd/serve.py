@@ -37,6 +37,7 @@ work enqueued for it has completed.
 """
 
 import collections
+import json
 import time
 
 import numpy as np
@@ -48,9 +49,13 @@ class Server:
     def __init__(self, hbm_budget=64 << 30, chunk=4096, max_members=1024,
                  max_items=1 << 19, waves=2048, n_bins=256, keep_counts=False,
                  lattice_chunk=1 << 17, depth=2, lanes_events=0, lattice_streams=3,
-                 device="cuda"):
+                 device="cuda", log=None):
         import torch
         self.torch = torch
+        # log: a path or a text stream; one JSON line per finished request
+        # (status, times, latency, replicas, events run or the error) and a
+        # last line with the summary of each serve call
+        self.log = log
         # well-mixed requests expecting at least this many events per replica
         # run on the lanes engine (one replica per thread: a word's chain of
         # events an order of magnitude shorter, at about twice the work per
@@ -118,11 +123,26 @@ class Server:
 
         cancelling = []       # (event, entry, status, message): memory back once done
 
+        log = self.log
+        log_file = open(log, "a") if isinstance(log, str) else log
+
+        def record(res, events=None):
+            results.append(res)
+            if log_file is not None:
+                line = {k: res[k] for k in ("id", "status", "arrival", "admitted", "completed",
+                                            "latency", "replicas")}
+                line["id"] = int(line["id"])
+                if events is not None:
+                    line["events"] = int(events)
+                if res.get("error") is not None:
+                    line["error"] = res["error"]
+                log_file.write(json.dumps(line) + "\n")
+
         def closed(r, status, message, t_admitted=None):
             t = clock() if real_time else sim_now
-            results.append(dict(id=r["net_id"], arrival=r["arrival"], admitted=t_admitted,
-                                completed=t, latency=t - r["arrival"], status=status,
-                                error=message, replicas=r["replicas"]))
+            record(dict(id=r["net_id"], arrival=r["arrival"], admitted=t_admitted,
+                        completed=t, latency=t - r["arrival"], status=status,
+                        error=message, replicas=r["replicas"]))
 
         def expired(r, now):
             d = r.get("deadline")
@@ -166,8 +186,9 @@ class Server:
                            hist=a["hist_host"].numpy().copy(), replicas=r["replicas"])
                 if self.keep_counts:
                     res["counts"] = a["counts_host"].numpy().copy()
-                stats["replica_events"] += int(a["events_host"].numpy()[0])
-                results.append(res)
+                events = int(a["events_host"].numpy()[0])
+                stats["replica_events"] += events
+                record(res, events)
                 used_bytes -= a["bytes"]
                 used_items -= a["items"]
 
@@ -345,6 +366,12 @@ class Server:
                 retire(q.popleft())
         stats["wall_s"] = (time.perf_counter() - t0)
         self.stats = stats
+        if log_file is not None:
+            log_file.write(json.dumps(dict(summary=summarize(results, stats))) + "\n")
+            if isinstance(log, str):
+                log_file.close()
+            else:
+                log_file.flush()
         return results
 
 

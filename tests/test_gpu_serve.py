@@ -1,5 +1,7 @@
 """Continuous batching: results alone and in the mix are bit-identical."""
 
+import json
+
 import numpy as np
 import pytest
 
@@ -126,7 +128,7 @@ def _alone(r, keep_counts=True):
     return e.histogram(256).cpu().numpy(), e.read_counts().cpu().numpy()
 
 
-def test_failures_stay_with_their_request(torch, monkeypatch):
+def test_failures_stay_with_their_request(torch, monkeypatch, tmp_path):
     """An invalid network, an invalid start, a request larger than the whole
     budget, one past its deadline and a lattice whose launch fails (injected)
     each end with their own status; every other request completes with
@@ -150,10 +152,17 @@ def test_failures_stay_with_their_request(torch, monkeypatch):
         return orig(self, max_events)
 
     monkeypatch.setattr(bwg.Ensemble, "run", flaky)
+    log = tmp_path / "serve.jsonl"
     srv = Server(hbm_budget=8 << 30, chunk=200, max_members=6, keep_counts=True,
-                 lattice_chunk=8192)
+                 lattice_chunk=8192, log=str(log))
     res = srv.serve(reqs + bad, real_time=False, pass_time=1.0)
     by_id = {r["id"]: r for r in res}
+    # the log: one JSON line per request, then the summary
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert [x["id"] for x in lines[:-1]] == [r["id"] for r in res]
+    assert all(x["status"] == r["status"] for x, r in zip(lines, res))
+    assert all(("events" in x) == (x["status"] == "ok") for x in lines[:-1])
+    assert lines[-1]["summary"]["failed"] == dict(error=3, rejected=1, cancelled=1)
     assert len(res) == base + len(bad)
     assert by_id[900]["status"] == "error" and "rate" in by_id[900]["error"]
     assert by_id[901]["status"] == "error"
