@@ -202,14 +202,16 @@ extern "C" int bwg_ensemble_restore(bwg_ens *e, const void *host_src, uint64_t s
     if (h[8] != e->zs)
         return fail(BWG_EINVAL, "checkpoint and ensemble differ in the shared threshold");
     if (h[11] != (uint64_t)k) return fail(BWG_EINVAL, "checkpoint regions do not match");
-    const uint64_t *E = nullptr, *Et = nullptr;
+    // the counters are read with memcpy: the caller's buffer need not be
+    // 8-byte aligned
+    const uint8_t *E = nullptr, *Et = nullptr;
     for (int i = 0; i < k; ++i) {
         const uint64_t id = h[12 + 3 * i], off = h[13 + 3 * i], bytes = h[14 + 3 * i];
         if (id != r[i].id || bytes != r[i].bytes || off % 256 || off > need ||
             bytes > need - off)
             return fail(BWG_EINVAL, "checkpoint regions do not match");
-        if (id == REG_E) E = (const uint64_t *)(src + off);
-        if (id == REG_ET) Et = (const uint64_t *)(src + off);
+        if (id == REG_E) E = src + off;
+        if (id == REG_ET) Et = src + off;
     }
     // between advances every replica has run its budget; derive the host
     // bounds from the live replicas' counters
@@ -219,11 +221,14 @@ extern "C" int bwg_ensemble_restore(bwg_ens *e, const void *host_src, uint64_t s
         uint64_t wlo = ~0ull, whi = 0;
         const uint64_t end = std::min<uint64_t>(32 * w + 32, e->M);
         for (uint64_t i = 32 * w; i < end; ++i) {
-            if (E[i] != Et[i])
+            uint64_t ei, ti;
+            memcpy(&ei, E + 8 * i, 8);
+            memcpy(&ti, Et + 8 * i, 8);
+            if (ei != ti)
                 return fail(BWG_EINVAL, "replica %llu has pending events in the checkpoint",
                             (unsigned long long)i);
-            wlo = std::min(wlo, E[i]);
-            whi = std::max(whi, E[i]);
+            wlo = std::min(wlo, ei);
+            whi = std::max(whi, ei);
         }
         lo = std::min(lo, wlo);
         hi = std::max(hi, whi);
