@@ -79,7 +79,7 @@ MEASURED_TRAFFIC = {
     "wm_pc_kernel": ("56dc664d5d4c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
                      (2 * 10822 + 12672) * 1024, "profiles/wm_pc_kernel_frank1024_2p20.md"),
-    "lat_event_kernel": ("96ce50d96af1", ("bitops.h", "lattice.hip"),
+    "lat_event_kernel": ("91624cd30ecf", ("bitops.h", "lattice.hip"),
                          (2 * 3004255 + 6513929) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
 }

@@ -763,18 +763,27 @@ __global__ __launch_bounds__(BLOCK, 1) void lat_event_kernel(LatArgs a)
 
 // ---- readouts --------------------------------------------------------------
 
-// Species totals over sites of every replica: dst[i*3 + x].
+// Species totals over sites of every replica: dst[i*3 + x].  A workgroup
+// takes one word (the piece of the launch starts at word w0): thread t reads
+// lane t mod 32 of the word on every LAT_TOT_SPLIT-th site from t / 32, so a
+// half-wave reads one site's planes once for its 32 lanes and the sites of a
+// word are read in parallel; the partial sums meet in LDS.
+constexpr int LAT_TOT_SPLIT = 8;
+
 template <int P>
-__global__ void lat_totals_kernel(const uint32_t *planes, uint64_t M, int S, int32_t *dst)
+__global__ __launch_bounds__(32 * LAT_TOT_SPLIT) void lat_totals_kernel(const uint32_t *planes,
+                                                                        uint64_t M, int S,
+                                                                        int32_t *dst, uint64_t w0)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const uint64_t w = i >> 5;
-    const uint32_t lane = i & 31;
+    __shared__ int32_t part[LAT_TOT_SPLIT][3][32];
+    const uint64_t w = w0 + blockIdx.x;
+    const uint32_t lane = threadIdx.x & 31, sub = threadIdx.x >> 5;
     int32_t t[3] = {0, 0, 0};
-    for (int s = 0; s < S; ++s) {
+    // several sites' loads in flight per thread
+#pragma unroll 4
+    for (int s = (int)sub; s < S; s += LAT_TOT_SPLIT) {
         uint32_t l[P], d[P], x[P];
-        load_site<P>(site_planes(planes, w, s, S, 3 * P), l, d, x);
+        load_site<P>(site_planes(planes, w, (uint32_t)s, S, 3 * P), l, d, x);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             t[0] += (int32_t)((l[q] >> lane) & 1u) << q;
@@ -782,9 +791,17 @@ __global__ void lat_totals_kernel(const uint32_t *planes, uint64_t M, int S, int
             t[2] += (int32_t)((x[q] >> lane) & 1u) << q;
         }
     }
-    dst[3 * i] = t[0];
-    dst[3 * i + 1] = t[1];
-    dst[3 * i + 2] = t[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) part[sub][k][lane] = t[k];
+    __syncthreads();
+    if (threadIdx.x < 96) {
+        const uint32_t k = threadIdx.x / 32, r = threadIdx.x % 32;
+        int32_t v = 0;
+#pragma unroll
+        for (int j = 0; j < LAT_TOT_SPLIT; ++j) v += part[j][k][r];
+        const uint64_t i = 32 * w + r;
+        if (i < M) dst[3 * i + k] = v;
+    }
 }
 
 // Site counts of replicas first .. first+count-1: dst[(k S + s) 3 + x].
@@ -884,9 +901,12 @@ hipError_t launch_lat_totals(const uint32_t *planes, uint64_t M, int S, int P, i
                              hipStream_t s)
 {
     if (P != 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(lat_totals_kernel<4>, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s,
-                       planes, M, S, dst);
-    return hipGetLastError();
+    // one workgroup per word
+    constexpr uint32_t block = 32 * LAT_TOT_SPLIT;
+    return launch_pieces((M + 31) / 32 * block, block, [&](uint64_t i0, dim3 g) {
+        hipLaunchKernelGGL(lat_totals_kernel<4>, g, dim3(block), 0, s, planes, M, S, dst,
+                           i0 / block);
+    });
 }
 
 hipError_t launch_lat_sites(const uint32_t *planes, int S, int P, uint64_t first, uint64_t count,
