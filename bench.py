@@ -79,8 +79,8 @@ MEASURED_TRAFFIC = {
     "wm_pc_kernel": ("56dc664d5d4c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
                      (2 * 10822 + 12672) * 1024, "profiles/wm_pc_kernel_frank1024_2p20.md"),
-    "lat_event_kernel": ("91624cd30ecf", ("bitops.h", "lattice.hip"),
-                         (2 * 3004255 + 6513929) * 1024,
+    "lat_event_kernel": ("ad5df348ca1e", ("bitops.h", "bwg_internal.h", "lattice.hip"),
+                         (2 * 5477457 + 11890680) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
 }
 
@@ -433,7 +433,7 @@ def bench_lattice(args):
     # site-plane bytes: a reaction reads and writes the 3 x P planes of its
     # site (one 32-bit word each), a hop those of both sites.  The event
     # kernel keeps the first BWG_LAT_STAGE_SITES sites of every word in LDS
-    # for a pass of 16 chunks: its algorithmic HBM bytes are one copy of
+    # for a pass of BWG_LAT_PASS_CHUNKS chunks: its algorithmic HBM bytes are one copy of
     # those sites in and out per word and pass, and the site-plane bytes of
     # the events on the other sites
     from paper_2412_16613_amd import _abi
@@ -442,7 +442,7 @@ def bench_lattice(args):
     words = (M + 31) // 32
     n_stage = (min(li["sites"], _abi.BWG_LAT_STAGE_SITES)
                if words >= 512 and not args.no_lds_stage else 0)
-    passes = math.ceil(events / M / (16 * 8192))
+    passes = math.ceil(events / M / (_abi.BWG_LAT_PASS_CHUNKS * _abi.BWG_LAT_CHUNK_EVENTS))
     stage_bytes = passes * words * 2 * n_stage * site_bytes / launches_per_step
     hbm_bytes = stage_bytes + (1 - n_stage / li["sites"]) * plane_bytes_we * word_events
     bytes_we = hbm_bytes / word_events

@@ -205,6 +205,13 @@ typedef struct {
  * networks. */
 #define BWG_OPT_NO_LDS_STAGE 16u
 #define BWG_LAT_STAGE_SITES 840
+/* Lattice schedule geometry: the component events of a group of 2048
+ * replicas are cut into chunks of BWG_LAT_CHUNK_EVENTS, each sorted into
+ * conflict-free layers; a pass schedules up to BWG_LAT_PASS_CHUNKS chunks of
+ * every group and runs them.  The schedule takes BWG_LAT_PASS_CHUNKS x
+ * (3 BWG_LAT_CHUNK_EVENTS + 64) x 4 bytes of the state per group. */
+#define BWG_LAT_CHUNK_EVENTS 8192
+#define BWG_LAT_PASS_CHUNKS 32
 
 typedef struct {
     int32_t engine;              /* BWG_ENGINE_*                              */

@@ -32,6 +32,8 @@ BWG_OPT_GENERIC_KERNEL = 4
 BWG_OPT_NO_JIT = 8
 BWG_OPT_NO_LDS_STAGE = 16
 BWG_LAT_STAGE_SITES = 840
+BWG_LAT_CHUNK_EVENTS = 8192
+BWG_LAT_PASS_CHUNKS = 32
 BWG_JIT_GENERAL = 1
 BWG_JIT_FRANK = 2
 

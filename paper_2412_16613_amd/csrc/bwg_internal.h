@@ -184,7 +184,7 @@ hipError_t launch_batch_epilogue(const BatchBudget *bb, int n_ens, hipStream_t s
 // up to LAT_NCB chunks.
 constexpr int LAT_GROUP_WORDS = 64;
 constexpr int LAT_CH = 8192;
-constexpr int LAT_NCB = 16;
+constexpr int LAT_NCB = 32;
 constexpr int LAT_SLOT = 3 * LAT_CH + 64;   // uint32 per (group, chunk) slot
 constexpr int LAT_MAX_SITES = 4096;
 

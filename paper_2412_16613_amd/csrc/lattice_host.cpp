@@ -407,6 +407,9 @@ int lat_histogram(bwg_ens *e, int32_t n_bins, uint64_t *dst, hipStream_t s)
 
 using namespace bwg;
 
+static_assert(LAT_CH == BWG_LAT_CHUNK_EVENTS && LAT_NCB == BWG_LAT_PASS_CHUNKS,
+              "the schedule geometry include/bwg.h states");
+
 extern "C" int bwg_net_lattice(const bwg_net *n, bwg_lattice_info *out)
 {
     if (!n || !out) return fail(BWG_EINVAL, "null argument");

@@ -322,7 +322,9 @@ def test_lattice_state_bytes():
     b = ctypes.c_uint64()
     _abi.check(_abi.load().bwg_ensemble_state_bytes(n.handle, 1 << 16, None, ctypes.byref(b)))
     planes = 2048 * 4096 * 12 * 4
-    assert planes <= b.value < planes + (64 << 20)
+    # the schedule of include/bwg.h's geometry for 32 groups of 2048 replicas
+    sched = 32 * _abi.BWG_LAT_PASS_CHUNKS * (3 * _abi.BWG_LAT_CHUNK_EVENTS + 64) * 4
+    assert planes + sched <= b.value < planes + sched + (8 << 20)
 
 
 def test_quantisation_of_wide_and_open_networks_matches_oracle():
