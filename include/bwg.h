@@ -277,7 +277,8 @@ void bwg_net_destroy(bwg_net *net);
 /* Compile now, on the host and without touching a device, the kernels that
  * a bit-sliced ensemble of this network under default options would compile
  * at run time (hipRTC, gfx950): the general kernel for networks outside the
- * Frank family, open networks and other species counts; the Frank-family
+ * Frank family, open networks and other species counts (the general networks
+ * Sec. 6 proposes, on the Sec. 4 state); the Frank-family
  * kernel with the network's weights as constants where no precompiled
  * variant has them.  Ensembles created later only load the code (done once
  * per network).  *built (may be NULL) gets BWG_JIT_GENERAL | BWG_JIT_FRANK
