@@ -79,7 +79,7 @@ MEASURED_TRAFFIC = {
     "wm_pc_kernel": ("56dc664d5d4c", ("bitops.h", "wm_device.h", "wm_event_body.inc",
                                       "wm_kernel.hip"),
                      (2 * 10822 + 12672) * 1024, "profiles/wm_pc_kernel_frank1024_2p20.md"),
-    "lat_event_kernel": ("ad5df348ca1e", ("bitops.h", "bwg_internal.h", "lattice.hip"),
+    "lat_event_kernel": ("ed3743083ea0", ("bitops.h", "bwg_internal.h", "lattice.hip"),
                          (2 * 5477457 + 11890680) * 1024,
                          "profiles/lat_event_kernel_lattice64x64_2p16.md"),
 }

@@ -25,13 +25,15 @@ enum : uint32_t {
 constexpr uint64_t kLaunchSpan = 1ull << 31;
 
 #ifndef __HIPCC_RTC__   // host launch code: not part of the run-time compiled kernels
-// f(i0, grid) once per piece [i0, i0 + kLaunchSpan) of [0, n); nothing for
-// n = 0.
+// f(i0, grid) once per piece [i0, i0 + span) of [0, n), span the largest
+// multiple of block within kLaunchSpan (so a piece's last workgroup ends
+// where the next piece starts, for any block size); nothing for n = 0.
 template <class F>
 inline hipError_t launch_pieces(uint64_t n, uint32_t block, F &&f)
 {
-    for (uint64_t i0 = 0; i0 < n; i0 += kLaunchSpan) {
-        const uint64_t len = n - i0 < kLaunchSpan ? n - i0 : kLaunchSpan;
+    const uint64_t span = kLaunchSpan / block * block;
+    for (uint64_t i0 = 0; i0 < n; i0 += span) {
+        const uint64_t len = n - i0 < span ? n - i0 : span;
         f(i0, dim3((uint32_t)((len + block - 1) / block)));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
