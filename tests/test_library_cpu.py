@@ -395,3 +395,28 @@ def test_bytes_needed_matches_the_library():
         assert bwg.Ensemble.bytes_needed(n, M, engine=engine) == b.value
     with pytest.raises(bwg.BwgError):
         bwg.Ensemble.bytes_needed(n, 0)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/bwg.h compiles as strict C99 and links against libbwg.so from a
+    C program: the boundary carries no C++ or torch types."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_bwg.c"
+    src.write_text(
+        '#include "bwg.h"\n'
+        "int main(void) {\n"
+        "    int64_t k_lo; uint64_t len, t[64];\n"
+        "    return bwg_poisson_table(2.0, &k_lo, t, 64, &len) == BWG_OK ? 0 : 1;\n"
+        "}\n")
+    exe = tmp_path / "use_bwg"
+    lib_dir = os.path.join(ROOT, "paper_2412_16613_amd")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                        "-L" + lib_dir, "-lbwg", "-Wl,-rpath," + lib_dir],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert subprocess.run([str(exe)]).returncode == 0
