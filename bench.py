@@ -159,6 +159,10 @@ def main():
                          "on the lanes engine (0: none)")
     ap.add_argument("--compare-nets", type=int, default=32,
                     help="networks for the one-network-per-launch comparison")
+    ap.add_argument("--shard", type=int, default=1,
+                    help="well-mixed: time one GPU's share of the workload split by word over this "
+                         "many GPUs (replicas 0 .. 2^20/shard - 1, the same draws as in the whole "
+                         "run)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     ap.add_argument("--valu-ref", action="store_true",
@@ -200,10 +204,16 @@ def main():
 
     c = config("c1")
     net, M, t_end = c["net"], c["replicas"], c["t_end"]
+    if args.shard < 1 or M % (32 * args.shard):
+        print("--shard must split the replicas into whole words", file=sys.stderr)
+        sys.exit(2)
+    M //= args.shard
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     network = bwg.Network(net)
     q = network.quantized()
+    # counters were taken on the whole workload's launch
+    whole = args.shard == 1
 
     def make(engine):
         ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], engine=engine,
@@ -276,20 +286,24 @@ def main():
         "dtype": "u32 bit-planes",
         "data": "synthetic",
         "config": {"workload": "well-mixed Frank model, N_tot=1024, 2^20 replicas, "
-                               "t_end=100, all-A start, seed 0",
+                               "t_end=100, all-A start, seed 0" +
+                               ("" if whole else ", one GPU's shard of %d (replicas 0..%d)"
+                                % (args.shard, M - 1)),
                    "n_tot": 1024, "replicas": M, "t_end": t_end, "threshold_planes": q["B"],
-                   "count_planes": q["b"]},
+                   "count_planes": q["b"], "shard": args.shard},
         "real_events_per_s": r["real"] * args.steps / (r["ms"] / 1e3),
         "replica_time_per_s": M * t_end * args.steps / (r["ms"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK,
-                     "traffic": measured_traffic("wm_pc_kernel"), "traffic_unit": "B/launch",
+                     "traffic": measured_traffic("wm_pc_kernel") if whole else None,
+                     "traffic_unit": "B/launch",
                      "kernel": "wm_pc_kernel", "kernel_ms": launch_ms,
                      "launches_per_step": launches_per_step, "advance_ms": adv_avg_ms,
                      "slots_per_word_event": slots,
-                     "valu_insts_per_launch": measured_valu("wm_pc_kernel"),
+                     "valu_insts_per_launch": measured_valu("wm_pc_kernel") if whole else None,
                      "issued_frac": (measured_valu("wm_pc_kernel") * 64 / (launch_ms / 1e3) /
-                                     VALU_PEAK if measured_valu("wm_pc_kernel") else None)},
+                                     VALU_PEAK if whole and measured_valu("wm_pc_kernel")
+                                     else None)},
     }
     if not args.no_plain:
         p = run("plain", max(1, args.steps // 2), 1)
@@ -303,7 +317,7 @@ def main():
                                   ssa.ee_histogram(r["counts"], net["n_tot"], 256)))
     out["parity"] = hist_ok
     if not args.no_cpu:
-        cb, orc = cpu_baseline(net, c, args.cpu_replicas)
+        cb, orc = cpu_baseline(net, c, min(args.cpu_replicas, M))
         n = orc.n
         same = (np.array_equal(r["counts"][:n], orc.counts) and
                 np.array_equal(r["ev"][:n].astype(np.uint64), orc.E))
