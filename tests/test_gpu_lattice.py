@@ -56,12 +56,20 @@ def test_init_uniform_site_matches_oracle():
 
 @pytest.mark.parametrize("lx,ly,M,K", [(4, 4, 100, 3000), (8, 8, 2048 + 70, 2500),
                                        (5, 3, 33, 4000), (2, 2, 64, 20000),
-                                       (1, 4, 40, 5000), (3, 1, 31, 5000)])
+                                       (1, 4, 40, 5000), (3, 1, 31, 5000),
+                                       (1, 1, 100, 3000), (2, 1, 65, 4000)])
 def test_fixed_event_count(lx, ly, M, K):
+    # (1, 1): a single site, every hop leads back to it; (2, 1): both
+    # x-directions lead to the same neighbour
     ens, orc = pair(lattice(lx, ly), M)
     ens.step(K)
     orc.step(K)
     check(ens, orc, "step")
+    torch.cuda.synchronize()
+    blocked = ens.read_blocked().cpu().numpy().astype(np.uint64)
+    g = np.zeros((M + 31) // 32, dtype=np.uint64)
+    np.add.at(g, np.arange(M) // 32, orc.blocked.astype(np.uint64))
+    np.testing.assert_array_equal(blocked, g)
 
 
 @pytest.mark.parametrize("lds_stage", [True, False])
