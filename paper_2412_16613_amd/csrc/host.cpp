@@ -392,9 +392,10 @@ extern "C" int bwg_net_create(const bwg_net_desc *d, bwg_net **out)
     int B = 1;
     while (B < 63 && (1ll << B) < q.max_total) ++B;
     if (B + (q.max_total == (1ll << B) ? 1 : 0) > kMaxThresholdPlanes) {
+        const long long total = (long long)q.max_total;   // q lives in n
         delete n;
-        return fail(BWG_ERANGE, "total weight %lld needs %d threshold planes (max %d)",
-                    (long long)q.max_total, B, kMaxThresholdPlanes);
+        return fail(BWG_ERANGE, "total weight %lld needs %d threshold planes (max %d)", total, B,
+                    kMaxThresholdPlanes);
     }
     q.B = B;
     int b = 1;
