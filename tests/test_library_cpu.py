@@ -462,3 +462,38 @@ def test_quantisation_matches_oracle_on_random_networks():
             assert lib[k] == orc[k], (kind, bits, k)
         checked += 1
     assert checked > 200
+
+
+def test_host_calls_from_several_threads():
+    """Network creation, quantisation, Poisson tables, state sizes and the
+    run-time compile of one shared network, from eight threads at once (the
+    calls release the interpreter lock): every call succeeds and the shared
+    network's compile happens once."""
+    import random
+    import threading
+    shared = bwg.Network(frank_network(200, k0=0.03))
+    errors = []
+
+    def work(seed):
+        rng = random.Random(seed)
+        try:
+            for _ in range(40):
+                k = rng.random()
+                if k < 0.4:
+                    bwg.Network(random_network(rng.randrange(10 ** 6), rng.choice([5, 50, 300]),
+                                               rng.choice([3, 5, 8]))).quantized()
+                elif k < 0.7:
+                    bwg.poisson_table(rng.uniform(1, 5000))
+                else:
+                    assert shared.compile() == {"frank"}
+                    bwg.Ensemble.bytes_needed(shared, rng.choice([1, 1000, 1 << 20]),
+                                              engine=rng.choice(["bitwise", "lanes", "plain"]))
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(s,)) for s in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert errors == []
