@@ -159,6 +159,8 @@ def main():
                          "on the lanes engine (0: none)")
     ap.add_argument("--compare-nets", type=int, default=32,
                     help="networks for the one-network-per-launch comparison")
+    ap.add_argument("--engine", default="bitwise", choices=["bitwise", "lanes"],
+                    help="well-mixed: the engine that runs the replicas (identical results)")
     ap.add_argument("--shard", type=int, default=1,
                     help="well-mixed: time one GPU's share of the workload split by word over this "
                          "many GPUs (replicas 0 .. 2^20/shard - 1, the same draws as in the whole "
@@ -212,8 +214,9 @@ def main():
     torch.cuda.set_device(dev)
     network = bwg.Network(net)
     q = network.quantized()
-    # counters were taken on the whole workload's launch
-    whole = args.shard == 1
+    # counters were taken on the whole workload's bit-sliced launch
+    whole = args.shard == 1 and args.engine == "bitwise"
+    kernel = "wm_pc_kernel" if args.engine == "bitwise" else "wm_lanes_kernel"
 
     def make(engine):
         ens = bwg.Ensemble(network, M, seed=c["seed"], net_id=c["net_id"], engine=engine,
@@ -260,7 +263,7 @@ def main():
                     counts=counts.cpu().numpy(), hist=hist.cpu().numpy(),
                     ev=ens.read_events()[0].cpu().numpy())
 
-    r = run("bitwise", args.steps, args.warmup)
+    r = run(args.engine, args.steps, args.warmup)
     ms_step = r["ms"] / args.steps
     events_per_step = r["events"]          # same seed every step: same budgets
     value = events_per_step * args.steps / (r["ms"] / 1e3)
@@ -287,17 +290,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "well-mixed Frank model, N_tot=1024, 2^20 replicas, "
                                "t_end=100, all-A start, seed 0" +
-                               ("" if whole else ", one GPU's shard of %d (replicas 0..%d)"
-                                % (args.shard, M - 1)),
+                               ("" if args.shard == 1 else ", one GPU's shard of %d (replicas "
+                                "0..%d)" % (args.shard, M - 1)) +
+                               ("" if args.engine == "bitwise" else ", lanes engine"),
                    "n_tot": 1024, "replicas": M, "t_end": t_end, "threshold_planes": q["B"],
-                   "count_planes": q["b"], "shard": args.shard},
+                   "count_planes": q["b"], "shard": args.shard, "engine": args.engine},
         "real_events_per_s": r["real"] * args.steps / (r["ms"] / 1e3),
         "replica_time_per_s": M * t_end * args.steps / (r["ms"] / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU lane-slots/s", "frac": achieved / VALU_PEAK,
                      "traffic": measured_traffic("wm_pc_kernel") if whole else None,
                      "traffic_unit": "B/launch",
-                     "kernel": "wm_pc_kernel", "kernel_ms": launch_ms,
+                     "kernel": kernel, "kernel_ms": launch_ms,
                      "launches_per_step": launches_per_step, "advance_ms": adv_avg_ms,
                      "slots_per_word_event": slots,
                      "valu_insts_per_launch": measured_valu("wm_pc_kernel") if whole else None,
@@ -305,6 +309,11 @@ def main():
                                      VALU_PEAK if whole and measured_valu("wm_pc_kernel")
                                      else None)},
     }
+    if args.engine == "lanes":
+        # the lane-slot count above is the bit-sliced word's algorithmic work;
+        # the one-replica-per-lane form has no such count of its own
+        out["roofline"].update(achieved=None, frac=None, slots_per_word_event=None,
+                               note="no algorithmic lane-slot count for the lanes engine")
     if not args.no_plain:
         p = run("plain", max(1, args.steps // 2), 1)
         pv = p["events"] * max(1, args.steps // 2) / (p["ms"] / 1e3)
