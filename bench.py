@@ -342,7 +342,8 @@ def main():
 def valu_ref():
     """Sustained 32-bit VALU lane-operations per second of the two instructions
     the bit-sliced kernels are made of (calib/valu_ref.hip): v_bitop3_b32 and
-    Philox's v_mad_u64_u32, eight independent chains per thread, with 1, 2,
+    Philox's v_mad_u64_u32, eight independent chains per thread, and of the
+    two-operand v_add_u32 the lanes engine is mostly made of, with 1, 2,
     4 and 8 waves per SIMD (256, 512, 1024, 2048 blocks of four waves).  Each
     wave64 instruction counts 64 lane-operations; the fraction is of the
     derived peak (256 CUs x 128 lanes per clock x 2.4 GHz)."""
@@ -361,7 +362,8 @@ def valu_ref():
     for kind, name, chains, iters in ((0, "v_bitop3_b32", 8, 20000),
                                       (1, "v_mad_u64_u32", 8, 20000),
                                       (3, "v_bitop3_b32", 2, 10000),
-                                      (2, "v_bitop3_b32", 1, 5000)):
+                                      (2, "v_bitop3_b32", 1, 5000),
+                                      (4, "v_add_u32", 8, 20000)):
         for w in (1, 2, 4, 8):
             blocks = 256 * w
             out = torch.empty(blocks * 256, dtype=torch.int32, device=dev)

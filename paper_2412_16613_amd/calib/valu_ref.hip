@@ -66,10 +66,38 @@ __global__ __launch_bounds__(256) void mad64_issue_kernel(uint32_t *out, uint32_
     out[t] = r;
 }
 
+// Two-operand 32-bit adds (v_add_u32 of two registers), the kind of
+// instruction the lanes engine is mostly made of: in each step every one of
+// kChains accumulators adds its neighbour's value, so the adds stay
+// separate instructions with kChains of them independent at a time.  Each
+// step counts kChains instructions.
+__global__ __launch_bounds__(256) void add_issue_kernel(uint32_t *out, uint32_t seed,
+                                                       uint32_t iters)
+{
+    uint32_t v[kChains];
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) v[c] = t * 0x9E3779B9u + c * 0x85EBCA6Bu + seed;
+    for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+#pragma unroll
+            for (int c = 0; c < kChains; ++c)
+                // written out so the compiler cannot merge two adds into v_add3_u32
+                asm volatile("v_add_u32_e32 %0, %0, %1" : "+v"(v[c]) : "v"(v[(c + 1 + k) % kChains]));
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) r ^= v[c];
+    out[t] = r;
+}
+
 }  // namespace
 
 // Run one reference kernel: kind 0 = bitop3 (8 chains), 1 = mad_u64 (8
-// chains), 2 = bitop3 (1 chain), 3 = bitop3 (2 chains); `blocks` blocks of
+// chains), 2 = bitop3 (1 chain), 3 = bitop3 (2 chains), 4 = v_add_u32 (8
+// accumulators); `blocks` blocks of
 // 256 threads (4 waves), each thread 16 * kChains * iters instructions of
 // that kind; out holds blocks * 256 uint32.  Returns the kernel's duration
 // in ms (HIP events on `stream`), or a negative value on a HIP error.
@@ -86,8 +114,10 @@ extern "C" double bwg_valu_ref(int kind, uint32_t blocks, uint32_t iters, uint32
         hipLaunchKernelGGL(mad64_issue_kernel, dim3(blocks), dim3(256), 0, s, out, 1u, iters);
     else if (kind == 2)
         hipLaunchKernelGGL(bitop3_issue_kernel<1>, dim3(blocks), dim3(256), 0, s, out, 1u, iters);
-    else
+    else if (kind == 3)
         hipLaunchKernelGGL(bitop3_issue_kernel<2>, dim3(blocks), dim3(256), 0, s, out, 1u, iters);
+    else
+        hipLaunchKernelGGL(add_issue_kernel, dim3(blocks), dim3(256), 0, s, out, 1u, iters);
     const hipError_t le = hipGetLastError();
     hipEventRecord(b, s);
     float ms = -1.0f;
