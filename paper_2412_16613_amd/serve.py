@@ -123,12 +123,16 @@ class Server:
 
         cancelling = []       # (event, entry, status, message): memory back once done
 
-        log = self.log
-        log_file = open(log, "a") if isinstance(log, str) else log
+        def log_line(obj):
+            if isinstance(self.log, str):
+                with open(self.log, "a") as f:
+                    f.write(json.dumps(obj) + "\n")
+            elif self.log is not None:
+                self.log.write(json.dumps(obj) + "\n")
 
         def record(res, events=None):
             results.append(res)
-            if log_file is not None:
+            if self.log is not None:
                 line = {k: res[k] for k in ("id", "status", "arrival", "admitted", "completed",
                                             "latency", "replicas")}
                 line["id"] = int(line["id"])
@@ -136,7 +140,7 @@ class Server:
                     line["events"] = int(events)
                 if res.get("error") is not None:
                     line["error"] = res["error"]
-                log_file.write(json.dumps(line) + "\n")
+                log_line(line)
 
         def closed(r, status, message, t_admitted=None):
             t = clock() if real_time else sim_now
@@ -366,12 +370,10 @@ class Server:
                 retire(q.popleft())
         stats["wall_s"] = (time.perf_counter() - t0)
         self.stats = stats
-        if log_file is not None:
-            log_file.write(json.dumps(dict(summary=summarize(results, stats))) + "\n")
-            if isinstance(log, str):
-                log_file.close()
-            else:
-                log_file.flush()
+        if self.log is not None:
+            log_line(dict(summary=summarize(results, stats)))
+            if not isinstance(self.log, str):
+                self.log.flush()
         return results
 
 
